@@ -1,0 +1,363 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only *describes* inputs: gate streams (lists of :class:`Gate`),
+Pauli observables (lists of ``(coeff, x_mask, z_mask)``), graphs and seeded
+random states.  It contains none of the simulation arithmetic: it never
+applies a gate, never forms a matrix product and never evaluates an
+expectation.  Both the CPU oracle (``oracle/``) and the HIP path
+(``paper_2609_19147_amd``) consume exactly what is produced here.
+
+Conventions (Section "State Management" and the gate-operation description
+of the paper): qubit ``q`` is bit ``n-1-q`` of the basis index (MSB-first).
+Pauli masks use *qubit* numbering: bit ``q`` of ``x_mask``/``z_mask`` refers
+to qubit ``q``; a qubit with both bits set carries a Y.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# Gate names understood by both sides.  Matrices are defined by the oracle
+# (the plain definition) and independently by the library.
+ONE_QUBIT = ("I", "H", "X", "Y", "Z", "S", "SDG", "T", "TDG", "SX",
+             "RX", "RY", "RZ", "P", "U")
+TWO_QUBIT = ("CNOT", "CZ", "CPHASE", "SWAP", "RZZ", "RXX", "RYY", "CU")
+MULTI = ("MCZ", "MCP", "UNITARY")
+PARAMETRIC = ("RX", "RY", "RZ", "P", "CPHASE", "RZZ", "RXX", "RYY", "MCP")
+
+
+@dataclass(frozen=True)
+class Gate:
+    """One gate of a stream.
+
+    ``wires`` lists qubits (for controlled gates: control(s) first, target
+    last).  ``theta`` is the fixed angle.  When ``param >= 0`` the angle is
+    ``theta + scale * params[param]`` (parameters are bound at run time).
+    ``mat`` is a row-major complex matrix for ``U`` (2x2), ``CU`` (the
+    2x2 target block) and ``UNITARY`` (2^k x 2^k, first wire = most
+    significant row bit).
+    """
+    name: str
+    wires: Tuple[int, ...]
+    theta: float = 0.0
+    param: int = -1
+    scale: float = 1.0
+    mat: Optional[Tuple[complex, ...]] = field(default=None, compare=False)
+
+    def angle(self, params: Optional[Sequence[float]] = None) -> float:
+        if self.param < 0:
+            return float(self.theta)
+        if params is None:
+            raise ValueError(f"gate {self.name} needs parameter {self.param}")
+        return float(self.theta) + float(self.scale) * float(params[self.param])
+
+
+def G(name: str, *wires: int, theta: float = 0.0, param: int = -1,
+      scale: float = 1.0, mat=None) -> Gate:
+    m = None if mat is None else tuple(complex(v) for v in np.asarray(mat).ravel())
+    return Gate(name, tuple(int(w) for w in wires), float(theta), int(param),
+                float(scale), m)
+
+
+# --------------------------------------------------------------------------
+# Seeded states
+# --------------------------------------------------------------------------
+
+def gaussian_state(n: int, seed: int) -> np.ndarray:
+    """i.i.d. complex Gaussian amplitudes, normalised in FP64 (complex128).
+
+    ``numpy.random.default_rng(seed)`` (PCG64); real parts are drawn first,
+    then imaginary parts.  Callers that run in complex64 cast this array and
+    hand the *rounded* values (upcast) to the oracle.
+    """
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal(1 << n)
+    im = rng.standard_normal(1 << n)
+    psi = re + 1j * im
+    psi /= math.sqrt(float(np.vdot(psi, psi).real))
+    return psi
+
+
+def sparse_state(n: int, seed: int, k: int = 8) -> Tuple[np.ndarray, np.ndarray]:
+    """``k`` distinct random basis indices with random complex weights.
+
+    Returns ``(indices, coeffs)`` (uint64, complex128), coefficients
+    normalised.  Used at sizes where a dense host state is too large: every
+    output amplitude of a linear map is then a ``k``-term sum.
+    """
+    rng = np.random.default_rng(seed)
+    idx = np.unique(rng.integers(0, 1 << n, size=4 * k, dtype=np.uint64))[:k]
+    rng.shuffle(idx)
+    c = rng.standard_normal(len(idx)) + 1j * rng.standard_normal(len(idx))
+    c /= math.sqrt(float(np.vdot(c, c).real))
+    return idx.astype(np.uint64), c
+
+
+def index_tag_state(n: int) -> np.ndarray:
+    """State whose amplitude at index i encodes i exactly in complex64.
+
+    Re = i mod 2^24, Im = floor(i / 2^24); both are integers below 2^24 and
+    therefore exact in float32.  Not normalised: it is a probe for
+    permutations, which move amplitudes without arithmetic.
+    """
+    i = np.arange(1 << n, dtype=np.int64)
+    return ((i & ((1 << 24) - 1)).astype(np.float64)
+            + 1j * (i >> 24).astype(np.float64))
+
+
+# --------------------------------------------------------------------------
+# Gate streams
+# --------------------------------------------------------------------------
+
+def qft_stream(n: int) -> List[Gate]:
+    """Textbook QFT: for j: H(j), then CPHASE(pi/2^(k-j)) on (k, j), k>j.
+
+    No final swaps, so the output is bit-reversed; n + n(n-1)/2 gates
+    (Section "Quantum Fourier Transform" and the benchmark depth formulas).
+    """
+    out: List[Gate] = []
+    for j in range(n):
+        out.append(G("H", j))
+        for k in range(j + 1, n):
+            out.append(G("CPHASE", k, j, theta=math.pi / (1 << (k - j))))
+    return out
+
+
+def wht_stream(n: int) -> List[Gate]:
+    return [G("H", q) for q in range(n)]
+
+
+def random_perm_block(n: int, n_gates: int, seed: int) -> List[Gate]:
+    """Random X / CNOT / SWAP block: kind uniform, wires uniform distinct."""
+    rng = np.random.default_rng(seed)
+    out: List[Gate] = []
+    for _ in range(n_gates):
+        kind = int(rng.integers(0, 3))
+        w = rng.choice(n, size=2, replace=False)
+        if kind == 0:
+            out.append(G("X", int(w[0])))
+        elif kind == 1:
+            out.append(G("CNOT", int(w[0]), int(w[1])))
+        else:
+            out.append(G("SWAP", int(w[0]), int(w[1])))
+    return out
+
+
+def ghz_stream(n: int) -> List[Gate]:
+    return [G("H", 0)] + [G("CNOT", q, q + 1) for q in range(n - 1)]
+
+
+def tfim_first_order_stream(n: int, J: float, h: float, t: float, r: int) -> List[Gate]:
+    """First-order Lie-Trotter TFIM (open chain), ZZ layer before X layer.
+
+    H = -J sum Z_i Z_{i+1} + h sum X_i; exp(i J Z Z dt) = RZZ(-2 J dt) and
+    exp(-i h X dt) = RX(2 h dt), dt = t / r; start |0...0>.
+    """
+    dt = t / r
+    out: List[Gate] = []
+    for _ in range(r):
+        out += [G("RZZ", q, q + 1, theta=-2.0 * J * dt) for q in range(n - 1)]
+        out += [G("RX", q, theta=2.0 * h * dt) for q in range(n)]
+    return out
+
+
+def tfim_strang_stream(n: int, J: float, h: float, dt: float, steps: int,
+                       h_layer: bool = True) -> List[Gate]:
+    """Second-order (Strang) TFIM steps: RX(h dt), RZZ(-2 J dt), RX(h dt).
+
+    Optionally preceded by an H layer on every qubit.
+    """
+    out: List[Gate] = wht_stream(n) if h_layer else []
+    for _ in range(steps):
+        out += [G("RX", q, theta=h * dt) for q in range(n)]
+        out += [G("RZZ", q, q + 1, theta=-2.0 * J * dt) for q in range(n - 1)]
+        out += [G("RX", q, theta=h * dt) for q in range(n)]
+    return out
+
+
+def hea_stream(n: int, layers: int) -> List[Gate]:
+    """Hardware-efficient ansatz: per layer RY then RZ on every qubit, then
+    CNOT(q, q+1) for q = 0..n-2.  Parameter index = (layer*n + q)*2 + {0: RY, 1: RZ}.
+    """
+    out: List[Gate] = []
+    for l in range(layers):
+        for q in range(n):
+            out.append(G("RY", q, param=(l * n + q) * 2))
+            out.append(G("RZ", q, param=(l * n + q) * 2 + 1))
+        out += [G("CNOT", q, q + 1) for q in range(n - 1)]
+    return out
+
+
+def hea_params(n: int, layers: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-math.pi, math.pi, size=2 * n * layers)
+
+
+def random_regular3_graph(n: int, rng: np.random.Generator) -> List[Tuple[int, int]]:
+    """Random 3-regular simple graph: configuration model with rejection."""
+    if (3 * n) % 2:
+        raise ValueError("a 3-regular graph needs an even vertex count")
+    while True:
+        stubs = np.repeat(np.arange(n), 3)
+        rng.shuffle(stubs)
+        pairs = stubs.reshape(-1, 2)
+        ok = True
+        seen = set()
+        for a, b in pairs:
+            a, b = int(a), int(b)
+            if a == b:
+                ok = False
+                break
+            e = (min(a, b), max(a, b))
+            if e in seen:
+                ok = False
+                break
+            seen.add(e)
+        if ok:
+            return sorted(seen)
+
+
+@dataclass
+class QaoaInstance:
+    n: int
+    edges: List[Tuple[int, int]]
+    gammas: np.ndarray
+    betas: np.ndarray
+
+
+def qaoa_instances(count: int, seed: int, depth: int = 4,
+                   n_choices: Sequence[int] = (16, 18, 20, 22, 24)) -> List[QaoaInstance]:
+    """MaxCut QAOA instances: n uniform over ``n_choices`` (even, so that a
+    3-regular graph exists), random 3-regular graph, gamma, beta ~ U[0, pi)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(np.asarray(n_choices)))
+        edges = random_regular3_graph(n, rng)
+        gam = rng.uniform(0.0, math.pi, size=depth)
+        bet = rng.uniform(0.0, math.pi, size=depth)
+        out.append(QaoaInstance(n, edges, gam, bet))
+    return out
+
+
+def qaoa_stream(inst: QaoaInstance, param_offset: int = -1) -> List[Gate]:
+    """|+>^n, then per layer exp(-i gamma C) (as RZZ(-gamma) per edge, equal to
+    the cost unitary up to a global phase) and exp(-i beta sum X) = RX(2 beta).
+
+    With ``param_offset >= 0`` the angles are parameters: gamma_l at index
+    offset + 2l (RZZ scale -1), beta_l at offset + 2l + 1 (RX scale 2).
+    """
+    out = wht_stream(inst.n)
+    for l in range(len(inst.gammas)):
+        if param_offset >= 0:
+            out += [G("RZZ", u, v, param=param_offset + 2 * l, scale=-1.0) for u, v in inst.edges]
+            out += [G("RX", q, param=param_offset + 2 * l + 1, scale=2.0) for q in range(inst.n)]
+        else:
+            out += [G("RZZ", u, v, theta=-float(inst.gammas[l])) for u, v in inst.edges]
+            out += [G("RX", q, theta=2.0 * float(inst.betas[l])) for q in range(inst.n)]
+    return out
+
+
+def grover_stream(n: int, marked: int, iterations: int) -> List[Gate]:
+    """Grover search: H layer, then per iteration an oracle (X-conjugated
+    multi-controlled Z marking ``marked``, given MSB-first) and the diffusion
+    H X MCZ X H."""
+    allq = tuple(range(n))
+    zeros = [q for q in range(n) if not (marked >> (n - 1 - q)) & 1]
+    out = wht_stream(n)
+    for _ in range(iterations):
+        out += [G("X", q) for q in zeros]
+        out.append(G("MCZ", *allq))
+        out += [G("X", q) for q in zeros]
+        out += wht_stream(n)
+        out += [G("X", q) for q in range(n)]
+        out.append(G("MCZ", *allq))
+        out += [G("X", q) for q in range(n)]
+        out += wht_stream(n)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Observables: lists of (coeff, x_mask, z_mask), bit q = qubit q
+# --------------------------------------------------------------------------
+
+PauliTerm = Tuple[float, int, int]
+
+
+def pauli(coeff: float, ops: dict) -> PauliTerm:
+    """``ops`` maps qubit -> 'X' | 'Y' | 'Z'."""
+    xm = zm = 0
+    for q, p in ops.items():
+        if p in ("X", "Y"):
+            xm |= 1 << q
+        if p in ("Z", "Y"):
+            zm |= 1 << q
+    return (float(coeff), xm, zm)
+
+
+def xxz_terms(n: int, jz: float = 0.5, J: float = 1.0) -> List[PauliTerm]:
+    """Open-chain XXZ: J sum_i (X_i X_{i+1} + Y_i Y_{i+1} + jz Z_i Z_{i+1})."""
+    out: List[PauliTerm] = []
+    for i in range(n - 1):
+        out.append(pauli(J, {i: "X", i + 1: "X"}))
+        out.append(pauli(J, {i: "Y", i + 1: "Y"}))
+        out.append(pauli(J * jz, {i: "Z", i + 1: "Z"}))
+    return out
+
+
+def z_terms(n: int) -> List[PauliTerm]:
+    return [pauli(1.0, {q: "Z"}) for q in range(n)]
+
+
+def x_terms(n: int) -> List[PauliTerm]:
+    return [pauli(1.0, {q: "X"}) for q in range(n)]
+
+
+def zz_chain_terms(n: int) -> List[PauliTerm]:
+    return [pauli(1.0, {q: "Z", q + 1: "Z"}) for q in range(n - 1)]
+
+
+def maxcut_terms(edges: Sequence[Tuple[int, int]]) -> List[PauliTerm]:
+    """C = sum_E (1 - Z_u Z_v) / 2 as Pauli terms (identity term has masks 0)."""
+    out: List[PauliTerm] = [(0.5 * len(edges), 0, 0)]
+    out += [pauli(-0.5, {u: "Z", v: "Z"}) for u, v in edges]
+    return out
+
+
+def random_stream(n: int, n_gates: int, seed: int, kinds: Sequence[str] = None) -> List[Gate]:
+    """Random mixed stream over the whole vocabulary (for parity tests)."""
+    rng = np.random.default_rng(seed)
+    kinds = list(kinds or ("H", "X", "Y", "Z", "S", "SDG", "T", "TDG", "SX", "RX", "RY",
+                           "RZ", "P", "U", "CNOT", "CZ", "CPHASE", "SWAP", "RZZ", "RXX",
+                           "RYY", "CU"))
+    out: List[Gate] = []
+    for _ in range(n_gates):
+        k = kinds[int(rng.integers(0, len(kinds)))]
+        th = float(rng.uniform(-math.pi, math.pi))
+        if k in ONE_QUBIT:
+            q = int(rng.integers(0, n))
+            if k == "U":
+                out.append(G("U", q, mat=random_unitary(2, rng)))
+            else:
+                out.append(G(k, q, theta=th))
+        else:
+            w = rng.choice(n, size=2, replace=False)
+            if k == "CU":
+                out.append(G("CU", int(w[0]), int(w[1]), mat=random_unitary(2, rng)))
+            else:
+                out.append(G(k, int(w[0]), int(w[1]), theta=th))
+    return out
+
+
+def random_unitary(dim: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-ish unitary: QR of a complex Gaussian matrix, phases fixed.
+
+    (Input generation only: the result is a list of numbers handed to both
+    sides as a gate matrix.)"""
+    z = rng.standard_normal((dim, dim)) + 1j * rng.standard_normal((dim, dim))
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r)
+    return q * (d / np.abs(d))
