@@ -1,0 +1,464 @@
+// C ABI of libqs: states, plans, layer application, reductions, profiling.
+// Validation happens before any device work; errors are reported through
+// qs_status and a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "planner.h"
+#include "qs.h"
+#include "runtime.h"
+
+using namespace qs;
+
+namespace qs {
+
+thread_local std::string g_last_error = "";
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(QS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void check_launch(const char* name) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(QS_EDEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- profiling
+namespace {
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::map<std::string, std::pair<long, double>> g_prof_stats;
+thread_local hipEvent_t g_prof_cur = nullptr;
+thread_local const char* g_prof_name = nullptr;
+}  // namespace
+
+void prof_begin(const char* name, hipStream_t s) {
+  if (!g_prof_on) return;
+  hipEvent_t e;
+  check_hip(hipEventCreate(&e), "hipEventCreate");
+  check_hip(hipEventRecord(e, s), "hipEventRecord");
+  g_prof_cur = e;
+  g_prof_name = name;
+}
+void prof_end(hipStream_t s) {
+  if (!g_prof_on || !g_prof_cur) return;
+  hipEvent_t e;
+  check_hip(hipEventCreate(&e), "hipEventCreate");
+  check_hip(hipEventRecord(e, s), "hipEventRecord");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_pending.push_back({g_prof_name, g_prof_cur, e});
+  g_prof_cur = nullptr;
+}
+static void prof_drain() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof_pending) {
+    check_hip(hipEventSynchronize(r.b), "hipEventSynchronize");
+    float ms = 0;
+    check_hip(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+    auto& st = g_prof_stats[r.name];
+    st.first += 1;
+    st.second += ms;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+}
+
+}  // namespace qs
+
+// ---------------------------------------------------------------- error wrapper
+template <class F>
+static qs_status guarded(F&& f) {
+  try {
+    f();
+    return QS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return QS_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return QS_EINVAL;
+  }
+}
+
+extern "C" const char* qs_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* qs_version(void) { return "qs 0.1 (gfx950, wave64)"; }
+
+// ---------------------------------------------------------------- states
+size_t qs_state::amp_bytes() const { return dtype == QS_C64 ? 8 : 16; }
+size_t qs_state::state_bytes() const { return amp_bytes() << n; }
+
+void qs_state::ensure_other() {
+  if (buf[1 - cur]) return;
+  size_t bytes = state_bytes();
+  size_t fr = 0, tot = 0;
+  check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+  if (bytes > fr) fail(QS_ENOMEM, "not enough device memory for the permutation scratch buffer");
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of the scratch buffer failed");
+  buf[1 - cur] = p;
+  owned[1 - cur] = true;
+}
+
+void qs_state::ensure_red() {
+  if (red_partials) return;
+  check_hip(hipMalloc(&red_partials, sizeof(double) * 2 * kMaxTermsPerLaunch * kRedBlocks), "hipMalloc");
+  check_hip(hipMalloc(&red_out, sizeof(double) * 16), "hipMalloc");
+}
+
+void qs_state::sync() { check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+static qs_state* check_state(qs_state* s) {
+  if (!s) fail(QS_EINVAL, "state is NULL");
+  return s;
+}
+
+extern "C" qs_status qs_alloc(int n, qs_dtype dtype, void* buf, void* scratch, size_t bytes, void* stream,
+                              qs_state** out) {
+  return guarded([&] {
+    if (!out) fail(QS_EINVAL, "out is NULL");
+    if (n < 1 || n > QS_MAX_QUBITS) fail(QS_EINVAL, "qubit count out of range");
+    if (dtype != QS_C64 && dtype != QS_C128) fail(QS_EINVAL, "unknown dtype");
+    auto s = std::make_unique<qs_state>();
+    s->n = n;
+    s->dtype = dtype;
+    s->stream = (hipStream_t)stream;
+    const size_t need = s->state_bytes();
+    if ((buf && bytes < need) || (scratch && bytes < need)) fail(QS_EINVAL, "given buffer smaller than 2^n amplitudes");
+    size_t alloc = (buf ? 0 : need);
+    if (alloc) {
+      size_t fr = 0, tot = 0;
+      check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+      if (alloc > fr) fail(QS_ENOMEM, "state does not fit in free device memory");
+    }
+    check_hip(hipGetDevice(&s->device), "hipGetDevice");
+    if (buf) {
+      s->buf[0] = buf;
+    } else {
+      if (hipMalloc(&s->buf[0], need) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of the state failed");
+      s->owned[0] = true;
+    }
+    if (scratch) s->buf[1] = scratch;
+    *out = s.release();
+  });
+}
+
+qs_state::~qs_state() {
+  for (int k = 0; k < 2; ++k)
+    if (owned[k] && buf[k]) hipFree(buf[k]);
+  if (red_partials) hipFree(red_partials);
+  if (red_out) hipFree(red_out);
+  if (matbuf) hipFree(matbuf);
+}
+
+extern "C" qs_status qs_free(qs_state* s) {
+  return guarded([&] {
+    if (!s) return;
+    if (!s->view) {
+      hipStreamSynchronize(s->stream);
+      delete s;
+    }
+  });
+}
+
+extern "C" qs_status qs_state_buffers(const qs_state* s, void** current, void** other) {
+  return guarded([&] {
+    if (!s) fail(QS_EINVAL, "state is NULL");
+    if (current) *current = s->buf[s->cur];
+    if (other) *other = s->buf[1 - s->cur];
+  });
+}
+
+extern "C" qs_status qs_state_info(const qs_state* s, int* n, int* dtype) {
+  return guarded([&] {
+    if (!s) fail(QS_EINVAL, "state is NULL");
+    if (n) *n = s->n;
+    if (dtype) *dtype = s->dtype;
+  });
+}
+
+extern "C" qs_status qs_set_basis(qs_state* s, uint64_t index) {
+  return guarded([&] {
+    check_state(s);
+    if (index >> s->n) fail(QS_EINVAL, "basis index out of range");
+    uint64_t N = 1ull << s->n;
+    if (s->dtype == QS_C64) launch_fill_basis<float>((cplx<float>*)s->cur_ptr(), N, index, s->stream);
+    else launch_fill_basis<double>((cplx<double>*)s->cur_ptr(), N, index, s->stream);
+  });
+}
+
+extern "C" qs_status qs_set_uniform(qs_state* s) {
+  return guarded([&] {
+    check_state(s);
+    uint64_t N = 1ull << s->n;
+    double v = std::ldexp(1.0, -s->n / 2) * ((s->n & 1) ? std::sqrt(0.5) : 1.0);
+    if (s->dtype == QS_C64) launch_fill_uniform<float>((cplx<float>*)s->cur_ptr(), N, v, s->stream);
+    else launch_fill_uniform<double>((cplx<double>*)s->cur_ptr(), N, v, s->stream);
+  });
+}
+
+extern "C" qs_status qs_upload(qs_state* s, const void* host, size_t bytes) {
+  return guarded([&] {
+    check_state(s);
+    if (!host || bytes != s->state_bytes()) fail(QS_EINVAL, "host buffer size must be 2^n amplitudes");
+    check_hip(hipMemcpyAsync(s->cur_ptr(), host, bytes, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+    s->sync();
+  });
+}
+
+extern "C" qs_status qs_download(const qs_state* cs, void* host, size_t bytes) {
+  return guarded([&] {
+    qs_state* s = const_cast<qs_state*>(cs);
+    check_state(s);
+    if (!host || bytes != s->state_bytes()) fail(QS_EINVAL, "host buffer size must be 2^n amplitudes");
+    check_hip(hipMemcpyAsync(host, s->cur_ptr(), bytes, hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+    s->sync();
+  });
+}
+
+extern "C" qs_status qs_copy(qs_state* dst, const qs_state* csrc) {
+  return guarded([&] {
+    qs_state* src = const_cast<qs_state*>(csrc);
+    check_state(dst);
+    check_state(src);
+    if (dst->n != src->n) fail(QS_EINVAL, "qubit counts differ");
+    if (src->stream != dst->stream) src->sync();
+    uint64_t N = 1ull << dst->n;
+    if (dst->dtype == QS_C64 && src->dtype == QS_C64)
+      launch_convert<float, float>((cplx<float>*)dst->cur_ptr(), (const cplx<float>*)src->cur_ptr(), N, dst->stream);
+    else if (dst->dtype == QS_C64)
+      launch_convert<float, double>((cplx<float>*)dst->cur_ptr(), (const cplx<double>*)src->cur_ptr(), N, dst->stream);
+    else if (src->dtype == QS_C64)
+      launch_convert<double, float>((cplx<double>*)dst->cur_ptr(), (const cplx<float>*)src->cur_ptr(), N, dst->stream);
+    else
+      launch_convert<double, double>((cplx<double>*)dst->cur_ptr(), (const cplx<double>*)src->cur_ptr(), N,
+                                     dst->stream);
+  });
+}
+
+extern "C" qs_status qs_sync(qs_state* s) {
+  return guarded([&] {
+    check_state(s);
+    s->sync();
+  });
+}
+
+// ---------------------------------------------------------------- plans
+extern "C" qs_status qs_plan_create(int n, const qs_gate* gates, size_t n_gates, size_t n_params,
+                                    const qs_plan_opts* opts, qs_plan** out) {
+  return guarded([&] {
+    if (!out) fail(QS_EINVAL, "out is NULL");
+    PlanOptions o;
+    if (opts) {
+      if (opts->mode != QS_PLAIN && opts->mode != QS_FUSED) fail(QS_EINVAL, "unknown plan mode");
+      o.mode = opts->mode;
+      o.max_tile_bits = opts->max_tile_bits;
+    }
+    int tb = o.max_tile_bits ? o.max_tile_bits : 13;
+    if (tb < kRoundBits + 1 || tb > kMaxTileBits) fail(QS_EINVAL, "max_tile_bits out of range");
+    auto g = normalise_gates(n, gates, n_gates, n_params);
+    auto p = std::make_unique<qs_plan>();
+    p->ir = build_plan(n, std::move(g), n_params, o, tb, 4);
+    p->bound = n_params == 0;
+    *out = p.release();
+  });
+}
+
+extern "C" qs_status qs_plan_set_params(qs_plan* p, const double* params, size_t n_params) {
+  return guarded([&] {
+    if (!p) fail(QS_EINVAL, "plan is NULL");
+    if (n_params != p->ir.n_params) fail(QS_EINVAL, "parameter count does not match the plan");
+    if (n_params && !params) fail(QS_EINVAL, "params is NULL");
+    for (size_t i = 0; i < n_params; ++i)
+      if (!std::isfinite(params[i])) fail(QS_EINVAL, "non-finite parameter");
+    p->params.assign(params, params + n_params);
+    p->bound = true;
+    p->refresh_device();
+  });
+}
+
+extern "C" qs_status qs_plan_num_layers(const qs_plan* p, size_t* out) {
+  return guarded([&] {
+    if (!p || !out) fail(QS_EINVAL, "NULL argument");
+    *out = p->ir.layers.size();
+  });
+}
+
+extern "C" qs_status qs_plan_describe(const qs_plan* p, char* buf, size_t cap, size_t* needed) {
+  return guarded([&] {
+    if (!p) fail(QS_EINVAL, "plan is NULL");
+    std::string js = describe_json(p->ir, p->params, p->bound);
+    if (needed) *needed = js.size() + 1;
+    if (buf && cap) {
+      size_t k = std::min(cap - 1, js.size());
+      std::memcpy(buf, js.data(), k);
+      buf[k] = 0;
+    }
+  });
+}
+
+qs_plan::~qs_plan() {
+  for (auto& d : dev)
+    if (d.blob) hipFree(d.blob);
+}
+
+extern "C" qs_status qs_plan_free(qs_plan* p) {
+  return guarded([&] { delete p; });
+}
+
+extern "C" qs_status qs_apply_layer(qs_state* s, const qs_plan* p, size_t first, size_t count) {
+  return guarded([&] {
+    check_state(s);
+    if (!p) fail(QS_EINVAL, "plan is NULL");
+    if (p->ir.n != s->n) fail(QS_EINVAL, "plan and state qubit counts differ");
+    if (!p->bound) fail(QS_EINVAL, "plan parameters are not bound");
+    size_t L = p->ir.layers.size();
+    if (first > L) fail(QS_EINVAL, "first layer out of range");
+    size_t last = (count == (size_t)-1 || count > L - first) ? L : first + count;
+    apply_layers(*s, const_cast<qs_plan&>(*p), first, last);
+  });
+}
+
+extern "C" qs_status qs_apply_gates(qs_state* s, const qs_gate* gates, size_t n_gates, const double* params,
+                                    size_t n_params) {
+  return guarded([&] {
+    check_state(s);
+    auto g = normalise_gates(s->n, gates, n_gates, n_params);
+    if (n_params && !params) fail(QS_EINVAL, "params is NULL");
+    std::vector<double> pv(params, params + n_params);
+    for (auto& ng : g) apply_plain_gate(*s, ng, pv);
+  });
+}
+
+// ---------------------------------------------------------------- reductions
+extern "C" qs_status qs_norm2(qs_state* s, double* out) {
+  return guarded([&] {
+    check_state(s);
+    if (!out) fail(QS_EINVAL, "out is NULL");
+    *out = state_norm2(*s);
+  });
+}
+
+extern "C" qs_status qs_overlap(qs_state* a, qs_state* b, double out[2]) {
+  return guarded([&] {
+    check_state(a);
+    check_state(b);
+    if (!out) fail(QS_EINVAL, "out is NULL");
+    if (a->n != b->n) fail(QS_EINVAL, "qubit counts differ");
+    auto v = state_overlap(*a, *b);
+    out[0] = v.real();
+    out[1] = v.imag();
+  });
+}
+
+extern "C" qs_status qs_infidelity(qs_state* a, qs_state* b, double* out) {
+  return guarded([&] {
+    check_state(a);
+    check_state(b);
+    if (!out) fail(QS_EINVAL, "out is NULL");
+    if (a->n != b->n) fail(QS_EINVAL, "qubit counts differ");
+    *out = state_infidelity(*a, *b);
+  });
+}
+
+extern "C" qs_status qs_expect(qs_state* s, const qs_pauli* terms, size_t n_terms, double* per_term, double* total) {
+  return guarded([&] {
+    check_state(s);
+    if (n_terms && !terms) fail(QS_EINVAL, "terms is NULL");
+    std::vector<double> v = state_expect(*s, terms, n_terms);
+    double tot = 0.0, c = 0.0;
+    for (size_t i = 0; i < n_terms; ++i) {
+      if (per_term) per_term[i] = v[i];
+      double y = v[i] - c, t = tot + y;
+      c = (t - tot) - y;
+      tot = t;
+    }
+    if (total) *total = tot;
+  });
+}
+
+extern "C" qs_status qs_amplitudes(qs_state* s, const uint64_t* idx, size_t count, void* host_amps) {
+  return guarded([&] {
+    check_state(s);
+    if (count == 0) return;
+    if (!idx || !host_amps) fail(QS_EINVAL, "NULL argument");
+    for (size_t i = 0; i < count; ++i)
+      if (idx[i] >> s->n) fail(QS_EINVAL, "index out of range");
+    uint64_t* didx = nullptr;
+    void* dout = nullptr;
+    check_hip(hipMalloc(&didx, count * 8), "hipMalloc");
+    if (hipMalloc(&dout, count * s->amp_bytes()) != hipSuccess) {
+      hipFree(didx);
+      fail(QS_ENOMEM, "hipMalloc");
+    }
+    struct Guard {
+      void* a;
+      void* b;
+      ~Guard() { hipFree(a); hipFree(b); }
+    } guard{didx, dout};
+    check_hip(hipMemcpyAsync(didx, idx, count * 8, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+    if (s->dtype == QS_C64)
+      launch_gather<float>((const cplx<float>*)s->cur_ptr(), didx, (cplx<float>*)dout, count, s->stream);
+    else
+      launch_gather<double>((const cplx<double>*)s->cur_ptr(), didx, (cplx<double>*)dout, count, s->stream);
+    check_hip(hipMemcpyAsync(host_amps, dout, count * s->amp_bytes(), hipMemcpyDeviceToHost, s->stream),
+              "hipMemcpyAsync");
+    s->sync();
+  });
+}
+
+// ---------------------------------------------------------------- profiling
+extern "C" qs_status qs_profile_enable(int on) {
+  return guarded([&] {
+    if (!on) prof_drain();
+    g_prof_on = on != 0;
+  });
+}
+
+extern "C" qs_status qs_profile_report(char* buf, size_t cap, size_t* needed) {
+  return guarded([&] {
+    prof_drain();
+    std::string js = "[";
+    bool first = true;
+    for (auto& kv : g_prof_stats) {
+      char line[256];
+      std::snprintf(line, sizeof line, "%s{\"kernel\":\"%s\",\"launches\":%ld,\"total_ms\":%.6f}", first ? "" : ",",
+                    kv.first.c_str(), kv.second.first, kv.second.second);
+      js += line;
+      first = false;
+    }
+    js += "]";
+    if (needed) *needed = js.size() + 1;
+    if (buf && cap) {
+      size_t k = std::min(cap - 1, js.size());
+      std::memcpy(buf, js.data(), k);
+      buf[k] = 0;
+    }
+  });
+}
+
+extern "C" qs_status qs_profile_reset(void) {
+  return guarded([&] {
+    prof_drain();
+    g_prof_stats.clear();
+  });
+}

@@ -1,0 +1,143 @@
+// Streaming kernels: state initialisation, dtype conversion, amplitude
+// gathers, the stand-alone diagonal phase-LUT layer and the GF(2) affine
+// permutation gather.
+#include "kernels.h"
+
+namespace qs {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(uint64_t work, int per_block) {
+  uint64_t b = (work + per_block - 1) / per_block;
+  const uint64_t cap = 256ull * 8 * 16;  // enough resident waves on 256 CUs
+  return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+template <class R>
+__global__ void fill_basis_kernel(cplx<R>* psi, uint64_t N, uint64_t index) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    psi[i] = {i == index ? R(1) : R(0), R(0)};
+}
+
+template <class R>
+__global__ void fill_uniform_kernel(cplx<R>* psi, uint64_t N, R v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    psi[i] = {v, R(0)};
+}
+
+template <class Rd, class Rs>
+__global__ void convert_kernel(cplx<Rd>* dst, const cplx<Rs>* src, uint64_t N) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = {(Rd)src[i].re, (Rd)src[i].im};
+}
+
+template <class R>
+__global__ void gather_kernel(const cplx<R>* psi, const uint64_t* idx, cplx<R>* out, uint64_t count) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = psi[idx[i]];
+}
+
+// One diagonal layer in place: psi_i *= prod_g LUT_g[count_g(i)].  Two
+// amplitudes per 16-byte access; the phase tables are small and stay cached.
+template <class R>
+__global__ void __launch_bounds__(kThreads) diag_kernel(cplx<R>* psi, uint64_t npairs, DiagDev D) {
+  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < npairs; t += (uint64_t)gridDim.x * kThreads) {
+    cplx2<R> v = reinterpret_cast<cplx2<R>*>(psi)[t];
+    const uint32_t i = (uint32_t)(2 * t);
+    v.a = cmul(v.a, diag_phase<R>(i, D));
+    v.b = cmul(v.b, diag_phase<R>(i + 1, D));
+    reinterpret_cast<cplx2<R>*>(psi)[t] = v;
+  }
+}
+
+// GF(2) affine gather out[y] = in[A y ^ c'] over coset tiles of dimension d.
+// Reads: x = x0 ^ s_lo ^ AU[s_hi] (aligned runs of 2^c); the element lands at
+// tile coordinate t = TL[s_lo] ^ TH[s_hi].  Writes: y = y0 ^ t_lo ^ VH[t_hi]
+// (aligned runs of 2^c).
+template <class R>
+__global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                       Gf2Args A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
+  __shared__ uint32_t tl[1 << kGf2MaxC], th[1 << kGf2MaxC], au[1 << kGf2MaxC], vh[1 << kGf2MaxC];
+  const uint32_t nlo = 1u << A.c;
+  const uint32_t nhi = 1u << (A.d - A.c);
+  for (uint32_t k = threadIdx.x; k < nlo; k += kThreads) tl[k] = A.t_lo[k];
+  for (uint32_t k = threadIdx.x; k < nhi; k += kThreads) {
+    th[k] = A.t_hi[k];
+    au[k] = A.au_hi[k];
+    vh[k] = A.v_hi[k];
+  }
+  // coset representative and its source
+  const uint32_t coset = blockIdx.x;
+  uint32_t y0 = 0;
+  for (uint32_t j = 0; j < A.n_free; ++j) y0 |= ((coset >> j) & 1u) << A.free_bits[j];
+  uint32_t x0 = A.cprime;
+  for (uint32_t j = 0; j < A.n; ++j)
+    if ((y0 >> j) & 1u) x0 ^= A.acol[j];
+  __syncthreads();
+  const uint32_t D = 1u << A.d;
+  const uint32_t lomask = nlo - 1u;
+  for (uint32_t s = threadIdx.x; s < D; s += kThreads) {
+    const uint32_t slo = s & lomask, shi = s >> A.c;
+    const uint32_t x = x0 ^ slo ^ au[shi];
+    T[tl[slo] ^ th[shi]] = in[x];
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < D; t += kThreads) {
+    const uint32_t y = y0 ^ (t & lomask) ^ vh[t >> A.c];
+    out[y] = T[t];
+  }
+}
+
+}  // namespace
+
+template <class R>
+void launch_fill_basis(cplx<R>* psi, uint64_t N, uint64_t index, hipStream_t s) {
+  QS_LAUNCH("fill_basis", s, fill_basis_kernel<R>, dim3(grid_for(N, kThreads * 4)), dim3(kThreads), 0, s, psi, N,
+            index);
+}
+template <class R>
+void launch_fill_uniform(cplx<R>* psi, uint64_t N, double v, hipStream_t s) {
+  QS_LAUNCH("fill_uniform", s, fill_uniform_kernel<R>, dim3(grid_for(N, kThreads * 4)), dim3(kThreads), 0, s, psi,
+            N, (R)v);
+}
+template <class Rd, class Rs>
+void launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, uint64_t N, hipStream_t s) {
+  QS_LAUNCH("convert", s, (convert_kernel<Rd, Rs>), dim3(grid_for(N, kThreads * 4)), dim3(kThreads), 0, s, dst, src,
+            N);
+}
+template <class R>
+void launch_gather(const cplx<R>* psi, const uint64_t* idx, cplx<R>* out, uint64_t count, hipStream_t s) {
+  QS_LAUNCH("gather", s, gather_kernel<R>, dim3(grid_for(count, kThreads)), dim3(kThreads), 0, s, psi, idx, out,
+            count);
+}
+template <class R>
+void launch_diag(cplx<R>* psi, int n, const DiagDev& D, hipStream_t s) {
+  const uint64_t npairs = (1ull << n) / 2;
+  QS_LAUNCH("diag_lut", s, diag_kernel<R>, dim3(grid_for(npairs, kThreads * 4)), dim3(kThreads), 0, s, psi, npairs,
+            D);
+}
+template <class R>
+void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s) {
+  const unsigned n_cosets = 1u << (A.n - A.d);
+  const size_t lds = sizeof(cplx<R>) << A.d;
+  QS_LAUNCH("gf2_gather", s, gf2_kernel<R>, dim3(n_cosets), dim3(kThreads), lds, s, in, out, A);
+}
+
+#define INST(R)                                                                              \
+  template void launch_fill_basis<R>(cplx<R>*, uint64_t, uint64_t, hipStream_t);            \
+  template void launch_fill_uniform<R>(cplx<R>*, uint64_t, double, hipStream_t);            \
+  template void launch_gather<R>(const cplx<R>*, const uint64_t*, cplx<R>*, uint64_t, hipStream_t); \
+  template void launch_diag<R>(cplx<R>*, int, const DiagDev&, hipStream_t);                 \
+  template void launch_gf2<R>(const cplx<R>*, cplx<R>*, const Gf2Args&, hipStream_t);
+INST(float)
+INST(double)
+template void launch_convert<float, double>(cplx<float>*, const cplx<double>*, uint64_t, hipStream_t);
+template void launch_convert<double, float>(cplx<double>*, const cplx<float>*, uint64_t, hipStream_t);
+template void launch_convert<float, float>(cplx<float>*, const cplx<float>*, uint64_t, hipStream_t);
+template void launch_convert<double, double>(cplx<double>*, const cplx<double>*, uint64_t, hipStream_t);
+
+}  // namespace qs

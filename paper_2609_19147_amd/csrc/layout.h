@@ -1,0 +1,91 @@
+// Plain-old-data descriptors shared by the host planner and the device kernels.
+//
+// Everything here is expressed in *state bit positions* (bit p of the basis
+// index; qubit q sits at p = n-1-q).  Masks are 32-bit because the library
+// caps n at 32 qubits.
+#pragma once
+#include <stdint.h>
+
+namespace qs {
+
+// ---- tile passes -----------------------------------------------------------
+// A tile is the set of basis indices that differ only in the tile bits
+// [0, L) U [a, a+h) (a == L gives the contiguous tile [0, L+h)).  Tile
+// position j (0 <= j < 2^(L+h)) maps to state offset
+//   (j & (2^L-1)) | ((j >> L) << a).
+// One workgroup owns one coset of the tile (all other bits fixed), stages its
+// 2^(L+h) amplitudes in LDS, and runs a list of rounds.  A round gathers, per
+// thread, the 2^RB amplitudes that differ in RB tile bits into registers,
+// optionally multiplies them by a diagonal phase, applies its operations
+// (butterflies on single register bits) and writes them back.
+constexpr int kRoundBits = 4;          // RB: register bits per round
+constexpr int kMaxTileBits = 14;       // LDS tile <= 2^14 amplitudes
+constexpr int kMaxDiagSlots = 4;       // diagonal layers fused into one pass
+
+enum TileOpKind : int32_t {
+  OP_MAT = 0,   // general 2x2: a0' = u00 a0 + u01 a1, a1' = u10 a0 + u11 a1 (coef: u00,u01,u10,u11)
+  OP_H = 1,     // Hadamard butterfly, scaled by 1/sqrt(2)
+  OP_QFT = 2,   // QFT stage on bit p: H butterfly, then a1' *= exp(i pi (i mod 2^p) / 2^p)
+                //   coef: 2^s intra-round twiddles (s = register bit of the op)
+  OP_DIAG = 3,  // diag(d0, d1) (coef: d0, d1)
+  OP_QFT_INV = 4,  // inverse of OP_QFT: a1 *= conj(twiddle), then H butterfly
+  OP_GRAD = 5,     // (adjoint only) accumulate 2 Re <lambda|K|phi>, K = coef (2x2)
+};
+
+struct TileOp {
+  int32_t kind;
+  int32_t rbit;    // register bit (0..RB-1) the op acts on
+  int32_t sbit;    // state bit position p
+  int32_t coef;    // offset into the pass's coefficient array (complex entries)
+  int32_t slot;    // OP_GRAD: gradient accumulator index; else -1
+  int32_t pad[3];
+};
+
+struct TileRound {
+  int32_t tbit[kRoundBits];  // tile-bit positions of register bits 0..RB-1 (ascending)
+  int32_t op_begin, op_end;  // ops [op_begin, op_end) of the pass
+  int32_t diag;              // -1 or a diagonal slot applied before the ops
+  int32_t diag_conj;         // 1: multiply by the conjugate phase (inverse)
+};
+
+// ---- diagonal layers ----------------------------------------------------------
+// phase(i) = prod_g LUT_g[count_g(i)],  count_g(i) = sum over the group's terms.
+enum DiagTermForm : int32_t {
+  DT_BITS = 0,       // popcount(i & mask)
+  DT_SHIFT_XOR = 1,  // popcount((i ^ (i >> shift)) & mask)  (bond p <-> p+shift mismatch)
+  DT_SHIFT_AND = 2,  // popcount((i & (i >> shift)) & mask)  (both bits set)
+  DT_PARITY = 3,     // parity(i & mask)                      (general Z-string)
+  DT_ALL = 4,        // (i & mask) == mask                    (multi-controlled)
+};
+
+struct DiagTerm {
+  int32_t form;
+  int32_t shift;
+  uint32_t mask;
+  int32_t pad;
+};
+
+struct DiagGroup {
+  int32_t term_begin, term_end;  // into the layer's term array
+  int32_t lut_begin;             // into the layer's LUT (count + 1 entries)
+  int32_t lut_len;
+};
+
+// ---- GF(2) affine gathers -----------------------------------------------------
+// out[y] = in[A y ^ cprime].  Tile subspace V (dimension d = 2c) contains
+// span(e_0..e_{c-1}) and A^{-1} span(e_0..e_{c-1}); every workgroup owns one
+// coset y0 + V so that both its reads and its writes are aligned runs of 2^c
+// amplitudes.
+constexpr int kGf2MaxC = 5;
+struct Gf2Args {
+  uint32_t n, c, d, n_free;
+  uint32_t cprime;
+  uint32_t acol[32];               // A e_j
+  uint32_t free_bits[32];          // coset representative positions
+  uint32_t au_hi[1 << kGf2MaxC];   // source offsets for the high source coordinates
+  uint32_t t_lo[1 << kGf2MaxC];    // tile coordinate of low source coordinates
+  uint32_t t_hi[1 << kGf2MaxC];    // tile coordinate of high source coordinates
+  uint32_t v_hi[1 << kGf2MaxC];    // destination offsets for high tile coordinates
+};
+
+}  // namespace qs

@@ -1,0 +1,1083 @@
+// Host planner: gate validation, structure detection, tile-pass scheduling and
+// numeric tables.  See planner.h for the contract.  No HIP calls in this file:
+// plans can be built and inspected without a GPU.
+#include "planner.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <sstream>
+#include <unordered_map>
+
+namespace qs {
+
+void fail(qs_status code, const std::string& msg) { throw Error{code, msg}; }
+
+static const double kPi = 3.14159265358979323846;
+// Collapse tolerance on complex128 window products (a few ulps): identity,
+// Hadamard and bit-flip recognition never swallows a real small rotation.
+static const double kCollapseTol = 8.0 * 1.1102230246251565e-16;
+
+// ---------------------------------------------------------------- Angle
+double Angle::eval(const std::vector<double>& p) const {
+  double v = c0;
+  for (auto& t : lin) v += t.second * p[t.first];
+  return v;
+}
+Angle Angle::plus(const Angle& o) const {
+  Angle r;
+  r.c0 = c0 + o.c0;
+  std::map<int32_t, double> m;
+  for (auto& t : lin) m[t.first] += t.second;
+  for (auto& t : o.lin) m[t.first] += t.second;
+  for (auto& t : m)
+    if (t.second != 0.0) r.lin.push_back(t);
+  return r;
+}
+Angle Angle::scaled(double s) const {
+  Angle r;
+  r.c0 = c0 * s;
+  for (auto& t : lin) r.lin.push_back({t.first, t.second * s});
+  return r;
+}
+bool Angle::same(const Angle& o) const {
+  if (std::memcmp(&c0, &o.c0, sizeof(double)) != 0) return false;
+  if (lin.size() != o.lin.size()) return false;
+  for (size_t i = 0; i < lin.size(); ++i)
+    if (lin[i].first != o.lin[i].first || std::memcmp(&lin[i].second, &o.lin[i].second, 8) != 0)
+      return false;
+  return true;
+}
+
+// ---------------------------------------------------------------- gates
+bool gate_is_diagonal(int k) {
+  switch (k) {
+    case QS_GATE_I: case QS_GATE_Z: case QS_GATE_S: case QS_GATE_SDG: case QS_GATE_T:
+    case QS_GATE_TDG: case QS_GATE_RZ: case QS_GATE_P: case QS_GATE_CZ: case QS_GATE_CPHASE:
+    case QS_GATE_RZZ: case QS_GATE_MCZ: case QS_GATE_MCP:
+      return true;
+    default:
+      return false;
+  }
+}
+
+static bool kind_has_angle(int k) {
+  switch (k) {
+    case QS_GATE_RX: case QS_GATE_RY: case QS_GATE_RZ: case QS_GATE_P: case QS_GATE_CPHASE:
+    case QS_GATE_RZZ: case QS_GATE_RXX: case QS_GATE_RYY: case QS_GATE_MCP:
+      return true;
+    default:
+      return false;
+  }
+}
+
+int gate_arity(const qs_gate& g) {
+  switch (g.kind) {
+    case QS_GATE_I: case QS_GATE_H: case QS_GATE_X: case QS_GATE_Y: case QS_GATE_Z:
+    case QS_GATE_S: case QS_GATE_SDG: case QS_GATE_T: case QS_GATE_TDG: case QS_GATE_SX:
+    case QS_GATE_RX: case QS_GATE_RY: case QS_GATE_RZ: case QS_GATE_P: case QS_GATE_U:
+      return 1;
+    case QS_GATE_CNOT: case QS_GATE_CZ: case QS_GATE_CPHASE: case QS_GATE_SWAP:
+    case QS_GATE_RZZ: case QS_GATE_RXX: case QS_GATE_RYY: case QS_GATE_CU:
+      return 2;
+    case QS_GATE_MCZ: case QS_GATE_MCP:
+      return 0;  // from mask
+    case QS_GATE_UNITARY:
+      return -1;  // from nw
+    default:
+      return -2;
+  }
+}
+
+std::vector<NGate> normalise_gates(int n, const qs_gate* g, size_t count, size_t n_params) {
+  if (n < 1 || n > QS_MAX_QUBITS) fail(QS_EINVAL, "qubit count out of range");
+  if (count > 0 && !g) fail(QS_EINVAL, "gate array is NULL");
+  std::vector<NGate> out;
+  out.reserve(count);
+  for (size_t i = 0; i < count; ++i) {
+    const qs_gate& q = g[i];
+    char where[64];
+    std::snprintf(where, sizeof where, "gate %zu: ", i);
+    int ar = gate_arity(q);
+    if (ar == -2) fail(QS_EINVAL, std::string(where) + "unknown kind");
+    NGate ng;
+    ng.kind = q.kind;
+    ng.index = (int32_t)i;
+    std::vector<int> wires;
+    if (ar == 0) {
+      if (q.mask == 0 || (n < 64 && (q.mask >> n) != 0))
+        fail(QS_EINVAL, std::string(where) + "multi-controlled mask empty or out of range");
+      for (int w = 0; w < n; ++w)
+        if ((q.mask >> w) & 1) wires.push_back(w);
+    } else {
+      int k = ar == -1 ? q.nw : ar;
+      if (ar == -1 && (k < 1 || k > QS_MAX_GATE_WIRES))
+        fail(QS_EINVAL, std::string(where) + "UNITARY wire count out of range");
+      if (q.nw != k) fail(QS_EINVAL, std::string(where) + "wire count does not match kind");
+      for (int j = 0; j < k; ++j) wires.push_back(q.wires[j]);
+    }
+    std::set<int> seen;
+    for (int w : wires) {
+      if (w < 0 || w >= n) fail(QS_EINVAL, std::string(where) + "wire out of range");
+      if (!seen.insert(w).second) fail(QS_EINVAL, std::string(where) + "duplicate wire");
+      ng.bits.push_back(n - 1 - w);
+    }
+    if (ar == 0)
+      for (int b : ng.bits) ng.all_mask |= 1u << b;
+    if (q.param >= 0) {
+      if (!kind_has_angle(q.kind)) fail(QS_EINVAL, std::string(where) + "parameter on a fixed gate");
+      if ((size_t)q.param >= n_params) fail(QS_EINVAL, std::string(where) + "parameter index out of range");
+      ng.angle.c0 = q.theta;
+      if (q.scale != 0.0) ng.angle.lin.push_back({q.param, q.scale});
+    } else if (q.param < -1) {
+      fail(QS_EINVAL, std::string(where) + "negative parameter index");
+    } else {
+      ng.angle.c0 = q.theta;
+    }
+    if (!std::isfinite(q.theta) || (q.param >= 0 && !std::isfinite(q.scale)))
+      fail(QS_EINVAL, std::string(where) + "non-finite angle");
+    if (q.kind == QS_GATE_U || q.kind == QS_GATE_CU || q.kind == QS_GATE_UNITARY) {
+      if (!q.mat) fail(QS_EINVAL, std::string(where) + "matrix missing");
+      int d = q.kind == QS_GATE_UNITARY ? (1 << q.nw) : 2;
+      ng.mat.resize((size_t)d * d);
+      for (int e = 0; e < d * d; ++e) {
+        double re = q.mat[2 * e], im = q.mat[2 * e + 1];
+        if (!std::isfinite(re) || !std::isfinite(im))
+          fail(QS_EINVAL, std::string(where) + "non-finite matrix entry");
+        ng.mat[e] = cd(re, im);
+      }
+    }
+    out.push_back(std::move(ng));
+  }
+  return out;
+}
+
+static std::vector<cd> m2(cd a, cd b, cd c, cd d) { return {a, b, c, d}; }
+
+std::vector<cd> gate_matrix(const NGate& g, const std::vector<double>& params) {
+  const cd I(0, 1);
+  double t = g.angle.eval(params);
+  double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
+  const double r = 1.0 / std::sqrt(2.0);
+  switch (g.kind) {
+    case QS_GATE_I: return m2(1, 0, 0, 1);
+    case QS_GATE_H: return m2(r, r, r, -r);
+    case QS_GATE_X: return m2(0, 1, 1, 0);
+    case QS_GATE_Y: return m2(0, -I, I, 0);
+    case QS_GATE_Z: return m2(1, 0, 0, -1);
+    case QS_GATE_S: return m2(1, 0, 0, I);
+    case QS_GATE_SDG: return m2(1, 0, 0, -I);
+    case QS_GATE_T: return m2(1, 0, 0, std::polar(1.0, kPi / 4));
+    case QS_GATE_TDG: return m2(1, 0, 0, std::polar(1.0, -kPi / 4));
+    case QS_GATE_SX: return m2(cd(0.5, 0.5), cd(0.5, -0.5), cd(0.5, -0.5), cd(0.5, 0.5));
+    case QS_GATE_RX: return m2(c, -I * s, -I * s, c);
+    case QS_GATE_RY: return m2(c, -s, s, c);
+    case QS_GATE_RZ: return m2(cd(c, -s), 0, 0, cd(c, s));
+    case QS_GATE_P: return m2(1, 0, 0, std::polar(1.0, t));
+    case QS_GATE_U: return g.mat;
+    default: break;
+  }
+  int k = (int)g.bits.size();
+  int d = 1 << k;
+  std::vector<cd> M((size_t)d * d, cd(0, 0));
+  auto id = [&]() { for (int i = 0; i < d; ++i) M[(size_t)i * d + i] = 1; };
+  switch (g.kind) {
+    case QS_GATE_CNOT: id(); M[10] = 0; M[15] = 0; M[11] = 1; M[14] = 1; break;
+    case QS_GATE_CZ: id(); M[15] = -1; break;
+    case QS_GATE_CPHASE: id(); M[15] = std::polar(1.0, t); break;
+    case QS_GATE_SWAP: M[0] = 1; M[6] = 1; M[9] = 1; M[15] = 1; break;
+    case QS_GATE_RZZ:
+      M[0] = cd(c, -s); M[5] = cd(c, s); M[10] = cd(c, s); M[15] = cd(c, -s); break;
+    case QS_GATE_RXX:
+      id(); for (int i = 0; i < 4; ++i) M[i * 4 + i] = c;
+      M[3] = M[6] = M[9] = M[12] = -I * s; break;
+    case QS_GATE_RYY:
+      id(); for (int i = 0; i < 4; ++i) M[i * 4 + i] = c;
+      M[3] = I * s; M[12] = I * s; M[6] = -I * s; M[9] = -I * s; break;
+    case QS_GATE_CU:
+      id(); M[10] = g.mat[0]; M[11] = g.mat[1]; M[14] = g.mat[2]; M[15] = g.mat[3]; break;
+    case QS_GATE_MCZ: id(); M[(size_t)d * d - 1] = -1; break;
+    case QS_GATE_MCP: id(); M[(size_t)d * d - 1] = std::polar(1.0, t); break;
+    case QS_GATE_UNITARY: return g.mat;
+    default: fail(QS_EINVAL, "no matrix for gate kind");
+  }
+  return M;
+}
+
+// 2x2 helpers
+static std::vector<cd> mul2(const std::vector<cd>& A, const std::vector<cd>& B) {
+  return {A[0] * B[0] + A[1] * B[2], A[0] * B[1] + A[1] * B[3],
+          A[2] * B[0] + A[3] * B[2], A[2] * B[1] + A[3] * B[3]};
+}
+static bool near2(const std::vector<cd>& A, cd a, cd b, cd c, cd d) {
+  cd ref[4] = {a, b, c, d};
+  for (int i = 0; i < 4; ++i)
+    if (std::abs(A[i] - ref[i]) > kCollapseTol) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------- diagonal terms
+// Terms of one diagonal gate: phase(i) = exp(i (global + sum angle_t f_t(i))).
+static void diag_terms_of(const NGate& g, std::vector<DiagTermIR>& terms, Angle& global) {
+  auto bitm = [&](int j) { return 1u << g.bits[j]; };
+  Angle a = g.angle;
+  switch (g.kind) {
+    case QS_GATE_I: return;
+    case QS_GATE_Z: terms.push_back({0, bitm(0), Angle{kPi, {}}}); return;
+    case QS_GATE_S: terms.push_back({0, bitm(0), Angle{kPi / 2, {}}}); return;
+    case QS_GATE_SDG: terms.push_back({0, bitm(0), Angle{-kPi / 2, {}}}); return;
+    case QS_GATE_T: terms.push_back({0, bitm(0), Angle{kPi / 4, {}}}); return;
+    case QS_GATE_TDG: terms.push_back({0, bitm(0), Angle{-kPi / 4, {}}}); return;
+    case QS_GATE_P: terms.push_back({0, bitm(0), a}); return;
+    case QS_GATE_RZ:  // exp(-i t/2) |0>, exp(+i t/2) |1>
+      global = global.plus(a.scaled(-0.5));
+      terms.push_back({0, bitm(0), a});
+      return;
+    case QS_GATE_CZ: terms.push_back({2, bitm(0) | bitm(1), Angle{kPi, {}}}); return;
+    case QS_GATE_CPHASE: terms.push_back({2, bitm(0) | bitm(1), a}); return;
+    case QS_GATE_RZZ:  // exp(-i t/2) on equal bits, exp(+i t/2) on different bits
+      global = global.plus(a.scaled(-0.5));
+      terms.push_back({1, bitm(0) | bitm(1), a});
+      return;
+    case QS_GATE_MCZ:
+    case QS_GATE_MCP: {
+      Angle aa = g.kind == QS_GATE_MCZ ? Angle{kPi, {}} : a;
+      int pc = __builtin_popcount(g.all_mask);
+      terms.push_back({pc == 1 ? 0 : pc == 2 ? 2 : 3, g.all_mask, aa});
+      return;
+    }
+    default: fail(QS_EINVAL, "not a diagonal gate");
+  }
+}
+
+static DiagIR build_diag(const std::vector<DiagTermIR>& raw, const Angle& global) {
+  // merge identical (type, mask) terms
+  std::vector<DiagTermIR> terms;
+  for (auto& t : raw) {
+    bool merged = false;
+    for (auto& u : terms)
+      if (u.type == t.type && u.mask == t.mask) { u.angle = u.angle.plus(t.angle); merged = true; break; }
+    if (!merged) terms.push_back(t);
+  }
+  DiagIR d;
+  d.global = global;
+  for (auto& t : terms) d.support |= t.mask;
+  // group by bit-identical symbolic angle, skipping exact zeros
+  std::vector<std::vector<const DiagTermIR*>> groups;
+  std::vector<Angle> gang;
+  for (auto& t : terms) {
+    if (t.angle.is_const() && t.angle.c0 == 0.0) continue;
+    size_t gi = 0;
+    for (; gi < gang.size(); ++gi)
+      if (gang[gi].same(t.angle)) break;
+    if (gi == gang.size()) { gang.push_back(t.angle); groups.emplace_back(); }
+    groups[gi].push_back(&t);
+  }
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    DiagGroupIR G;
+    G.angle = gang[gi];
+    uint32_t bits = 0;
+    std::map<std::pair<int, int>, uint32_t> shifted;  // (form, shift) -> lower-bit mask
+    for (auto* t : groups[gi]) {
+      int pc = __builtin_popcount(t->mask);
+      if (t->type == 0) {
+        bits |= t->mask;
+        G.max_count += 1;
+      } else if ((t->type == 1 || t->type == 2) && pc == 2) {
+        int lo = __builtin_ctz(t->mask);
+        int hi = 31 - __builtin_clz(t->mask);
+        shifted[{t->type == 1 ? DT_SHIFT_XOR : DT_SHIFT_AND, hi - lo}] |= 1u << lo;
+        G.max_count += 1;
+      } else if (t->type == 1 || t->type == 4) {
+        G.terms.push_back({DT_PARITY, 0, t->mask, 0});
+        G.max_count += 1;
+      } else {
+        G.terms.push_back({DT_ALL, 0, t->mask, 0});
+        G.max_count += 1;
+      }
+    }
+    if (bits) G.terms.insert(G.terms.begin(), DiagTerm{DT_BITS, 0, bits, 0});
+    for (auto& s : shifted) G.terms.push_back({s.first.first, s.first.second, s.second, 0});
+    d.groups.push_back(std::move(G));
+  }
+  return d;
+}
+
+DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj) {
+  DiagNumeric out;
+  double gl = d.global.eval(params);
+  cd gph = std::polar(1.0, std::remainder(gl, 2 * kPi));
+  if (d.groups.empty()) {
+    out.groups.push_back({0, 0, 0, 1});
+    out.lut.push_back(conj ? std::conj(gph) : gph);
+    return out;
+  }
+  for (size_t gi = 0; gi < d.groups.size(); ++gi) {
+    const DiagGroupIR& G = d.groups[gi];
+    DiagGroup dg;
+    dg.term_begin = (int32_t)out.terms.size();
+    for (auto& t : G.terms) out.terms.push_back(t);
+    dg.term_end = (int32_t)out.terms.size();
+    dg.lut_begin = (int32_t)out.lut.size();
+    dg.lut_len = G.max_count + 1;
+    double th = G.angle.eval(params);
+    for (int c = 0; c <= G.max_count; ++c) {
+      // angle * count in FP64, reduced mod 2 pi before the trigonometry
+      double ang = std::remainder(th * (double)c, 2 * kPi);
+      cd v = std::polar(1.0, ang);
+      if (gi == 0) v *= gph;
+      out.lut.push_back(conj ? std::conj(v) : v);
+    }
+    out.groups.push_back(dg);
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------- GF(2) maps
+// Row r of A: src bit r = parity(rows[r] & y).
+static void gf2_push_gate(Gf2IR& G, const NGate& g) {
+  // src map <- g o src map (gates are replayed in reverse order)
+  auto& A = G.rows;
+  if (g.kind == QS_GATE_X) {
+    G.cprime ^= 1u << g.bits[0];
+  } else if (g.kind == QS_GATE_CNOT) {
+    int c = g.bits[0], t = g.bits[1];
+    A[t] ^= A[c];
+    G.cprime ^= ((G.cprime >> c) & 1u) << t;
+  } else if (g.kind == QS_GATE_SWAP) {
+    int a = g.bits[0], b = g.bits[1];
+    std::swap(A[a], A[b]);
+    uint32_t d = ((G.cprime >> a) ^ (G.cprime >> b)) & 1u;
+    G.cprime ^= (d << a) | (d << b);
+  } else {
+    fail(QS_EINVAL, "not a permutation gate");
+  }
+}
+
+static Gf2IR build_gf2(int n, const std::vector<NGate>& gates, const std::vector<int>& idx) {
+  Gf2IR G;
+  G.rows.resize(n);
+  for (int r = 0; r < n; ++r) G.rows[r] = 1u << r;
+  for (auto it = idx.rbegin(); it != idx.rend(); ++it) gf2_push_gate(G, gates[*it]);
+  G.gates = idx;
+  return G;
+}
+
+// Compose: first apply F (out1[y] = in[A_F y ^ c_F]) then S (out2[y] = out1[A_S y ^ c_S])
+// => out2[y] = in[A_F (A_S y ^ c_S) ^ c_F].
+static Gf2IR compose_gf2(int n, const Gf2IR& F, const Gf2IR& S) {
+  auto apply = [&](const std::vector<uint32_t>& rows, uint32_t v) {
+    uint32_t r = 0;
+    for (int b = 0; b < n; ++b) r |= (uint32_t)(__builtin_popcount(rows[b] & v) & 1) << b;
+    return r;
+  };
+  Gf2IR R;
+  R.rows.assign(n, 0);
+  // column j of A_F A_S = A_F (A_S e_j)
+  for (int j = 0; j < n; ++j) {
+    uint32_t col = apply(F.rows, apply(S.rows, 1u << j));
+    for (int b = 0; b < n; ++b)
+      if ((col >> b) & 1) R.rows[b] |= 1u << j;
+  }
+  R.cprime = apply(F.rows, S.cprime) ^ F.cprime;
+  R.gates = F.gates;
+  R.gates.insert(R.gates.end(), S.gates.begin(), S.gates.end());
+  return R;
+}
+
+static uint32_t gf2_apply_rows(int n, const std::vector<uint32_t>& rows, uint32_t v) {
+  uint32_t r = 0;
+  for (int b = 0; b < n; ++b) r |= (uint32_t)(__builtin_popcount(rows[b] & v) & 1) << b;
+  return r;
+}
+
+// Reduced basis helper: insert v; returns true if v was independent.
+struct Gf2Basis {
+  uint32_t piv[32] = {0};  // piv[b]: basis vector with leading bit b
+  int dim = 0;
+  uint32_t reduce(uint32_t v) const {
+    for (int b = 31; b >= 0; --b)
+      if (((v >> b) & 1) && piv[b]) v ^= piv[b];
+    return v;
+  }
+  bool insert(uint32_t v) {
+    v = reduce(v);
+    if (!v) return false;
+    piv[31 - __builtin_clz(v)] = v;
+    ++dim;
+    return true;
+  }
+};
+
+Gf2Args gf2_args(int n, const Gf2IR& g, int c_bits) {
+  Gf2Args a;
+  std::memset(&a, 0, sizeof a);
+  int c = std::min(c_bits, n / 2);
+  if (c < 1) c = 1;
+  if (c > n) c = n;
+  int d = std::min(2 * c, n);
+  a.n = n;
+  a.c = c;
+  a.d = d;
+  a.cprime = g.cprime;
+  for (int j = 0; j < n; ++j) {
+    uint32_t col = 0;
+    for (int b = 0; b < n; ++b)
+      if ((g.rows[b] >> j) & 1) col |= 1u << b;
+    a.acol[j] = col;
+  }
+  // M = A^{-1}: M e_j is the y with A y = e_j; solve through an index table
+  // of the columns (Gaussian elimination with combination tracking).
+  std::vector<uint32_t> Mcol(n, 0);
+  {
+    // rows of the augmented system [A | I] reduced on columns of A
+    std::vector<uint32_t> colv(a.acol, a.acol + n);  // A e_j
+    std::vector<uint32_t> comb(n);
+    for (int j = 0; j < n; ++j) comb[j] = 1u << j;
+    // eliminate to obtain combinations whose image is e_b
+    std::vector<int> used(n, 0);
+    for (int b = 0; b < n; ++b) {
+      int pivot = -1;
+      for (int j = 0; j < n; ++j)
+        if (!used[j] && ((colv[j] >> b) & 1)) { pivot = j; break; }
+      if (pivot < 0) fail(QS_EINVAL, "permutation block is not invertible");
+      used[pivot] = 1;
+      for (int j = 0; j < n; ++j)
+        if (j != pivot && ((colv[j] >> b) & 1)) { colv[j] ^= colv[pivot]; comb[j] ^= comb[pivot]; }
+    }
+    for (int j = 0; j < n; ++j) {
+      int b = __builtin_ctz(colv[j]);
+      Mcol[b] = comb[j];  // A * comb[j] = e_b (as a combination of unit vectors)
+    }
+  }
+  // tile subspace V = span(e_0..e_{c-1}, M e_0..M e_{c-1}) padded to dimension d
+  Gf2Basis V;
+  std::vector<uint32_t> vb;  // destination basis v_0..v_{d-1}
+  for (int j = 0; j < c; ++j) { V.insert(1u << j); vb.push_back(1u << j); }
+  for (int j = 0; j < c && V.dim < d; ++j)
+    if (V.insert(Mcol[j])) vb.push_back(Mcol[j]);
+  for (int b = c; b < n && V.dim < d; ++b)
+    if (V.insert(1u << b)) vb.push_back(1u << b);
+  // source basis u_0..u_{d-1}: u_j = M e_j for j < c, completed from vb
+  Gf2Basis U;
+  std::vector<uint32_t> ub;
+  for (int j = 0; j < c; ++j) { U.insert(Mcol[j]); ub.push_back(Mcol[j]); }
+  for (auto v : vb)
+    if ((int)ub.size() < d && U.insert(v)) ub.push_back(v);
+  if ((int)ub.size() != d || (int)vb.size() != d) fail(QS_EINVAL, "internal: tile basis");
+  // coordinates in the v basis
+  std::unordered_map<uint32_t, uint32_t> coord;
+  for (uint32_t t = 0; t < (1u << d); ++t) {
+    uint32_t y = 0;
+    for (int j = 0; j < d; ++j)
+      if ((t >> j) & 1) y ^= vb[j];
+    coord[y] = t;
+  }
+  std::vector<uint32_t> ucoord(d);
+  for (int j = 0; j < d; ++j) ucoord[j] = coord.at(ub[j]);
+  int hi = d - c;
+  for (uint32_t s = 0; s < (1u << c); ++s) {
+    uint32_t t = 0;
+    for (int j = 0; j < c; ++j)
+      if ((s >> j) & 1) t ^= ucoord[j];
+    a.t_lo[s] = t;
+  }
+  for (uint32_t s = 0; s < (1u << hi); ++s) {
+    uint32_t t = 0, x = 0, y = 0;
+    for (int j = 0; j < hi; ++j)
+      if ((s >> j) & 1) {
+        t ^= ucoord[c + j];
+        x ^= gf2_apply_rows(n, g.rows, ub[c + j]);
+        y ^= vb[c + j];
+      }
+    a.t_hi[s] = t;
+    a.au_hi[s] = x;
+    a.v_hi[s] = y;
+  }
+  // complement: unit vectors independent of V
+  Gf2Basis C = V;
+  int nf = 0;
+  for (int b = 0; b < n; ++b)
+    if (C.insert(1u << b)) a.free_bits[nf++] = (uint32_t)b;
+  a.n_free = nf;
+  if (nf != n - d) fail(QS_EINVAL, "internal: coset complement");
+  return a;
+}
+
+// ---------------------------------------------------------------- plan building
+namespace {
+
+struct Sched {
+  int n;
+  int L;                                // low bits of high tiles
+  std::vector<std::array<int, 3>> grp;  // (L, a, h)
+  std::vector<uint32_t> gmask;
+};
+
+Sched make_groups(int n, int tile_bits, int low_bits) {
+  Sched s;
+  s.n = n;
+  s.L = low_bits;
+  if (n <= tile_bits) {
+    s.grp.push_back({n, n, 0});
+    s.gmask.push_back(n >= 32 ? 0xffffffffu : ((1u << n) - 1));
+    return s;
+  }
+  int m0 = tile_bits;
+  s.grp.push_back({m0, m0, 0});
+  s.gmask.push_back((1u << m0) - 1);
+  int rest = n - m0;
+  int hmax = tile_bits - low_bits;
+  int ng = (rest + hmax - 1) / hmax;
+  int a = m0;
+  for (int k = 0; k < ng; ++k) {
+    int h = rest / ng + (k < rest % ng ? 1 : 0);
+    s.grp.push_back({low_bits, a, h});
+    uint32_t m = (1u << low_bits) - 1;
+    for (int b = a; b < a + h; ++b) m |= 1u << b;
+    s.gmask.push_back(m);
+    a += h;
+  }
+  return s;
+}
+
+struct Item {
+  ItemIR ir;
+  uint32_t W = 0, R = 0;
+};
+
+class Builder {
+ public:
+  Builder(PlanIR& P, int tile_bits, int low_bits)
+      : P(P), n(P.n), sched(make_groups(P.n, tile_bits, low_bits)), window(P.n) {}
+
+  void run() {
+    const auto& G = P.gates;
+    size_t i = 0;
+    while (i < G.size()) {
+      const NGate& g = G[i];
+      size_t used = 0;
+      if (g.kind == QS_GATE_H && (used = qft_stage_len(i)) > 0) {
+        close_open();
+        add_op_item(OpIR{OP_QFT, g.bits[0], {}, false, -1});
+        last_qft_bit = g.bits[0];
+        i += used;
+        continue;
+      }
+      last_qft_bit = -1;
+      int k = g.kind;
+      if (k == QS_GATE_I) { ++i; continue; }
+      bool one = g.bits.size() == 1 && k != QS_GATE_MCZ && k != QS_GATE_MCP;
+      if (k == QS_GATE_X && open == PERM) {
+        perm.push_back((int)i);
+      } else if (one && gate_is_diagonal(k)) {
+        if (open == DIAG) diag.push_back((int)i);
+        else { open_block(WINDOW); window[g.bits[0]].push_back((int)i); }
+      } else if (one) {
+        open_block(WINDOW);
+        window[g.bits[0]].push_back((int)i);
+      } else if (gate_is_diagonal(k)) {
+        open_block(DIAG);
+        diag.push_back((int)i);
+      } else if (k == QS_GATE_CNOT || k == QS_GATE_SWAP) {
+        open_block(PERM);
+        perm.push_back((int)i);
+      } else if (k == QS_GATE_RXX) {
+        open_block(XX);
+        pp.push_back((int)i);
+      } else if (k == QS_GATE_RYY) {
+        open_block(YY);
+        pp.push_back((int)i);
+      } else {
+        close_open();
+        barrier({L_PLAIN, (int32_t)i});
+      }
+      ++i;
+    }
+    close_open();
+    flush_segment();
+  }
+
+ private:
+  enum Open { NONE, DIAG, WINDOW, PERM, XX, YY };
+  PlanIR& P;
+  int n;
+  Sched sched;
+  Open open = NONE;
+  std::vector<int> diag, perm, pp;
+  std::vector<std::vector<int>> window;
+  std::vector<Item> seg;
+  int last_qft_bit = -1;
+
+  // Number of gates of a QFT stage starting at gate i (H on bit p followed by
+  // CPHASE(pi / 2^(p-b)) on (b, p) for every b < p, in any order), or 0.
+  size_t qft_stage_len(size_t i) const {
+    const auto& G = P.gates;
+    int p = G[i].bits[0];
+    if (p == 0) return last_qft_bit == 1 ? 1 : 0;
+    if (i + (size_t)p >= G.size()) return 0;
+    uint32_t seen = 0;
+    for (int j = 1; j <= p; ++j) {
+      const NGate& c = G[i + j];
+      if (c.kind != QS_GATE_CPHASE || !c.angle.is_const()) return 0;
+      int a = c.bits[0], b = c.bits[1];
+      int other = a == p ? b : b == p ? a : -1;
+      if (other < 0 || other >= p) return 0;
+      if ((seen >> other) & 1) return 0;
+      double want = std::ldexp(kPi, -(p - other));
+      if (c.angle.c0 != want) return 0;
+      seen |= 1u << other;
+    }
+    return (size_t)p + 1;
+  }
+
+  void open_block(Open o) {
+    if (open != o) close_open();
+    open = o;
+  }
+
+  void close_open() {
+    switch (open) {
+      case DIAG: close_diag(); break;
+      case WINDOW: close_window(); break;
+      case PERM: close_perm(); break;
+      case XX: case YY: close_pp(); break;
+      default: break;
+    }
+    open = NONE;
+  }
+
+  void close_diag() {
+    std::vector<DiagTermIR> raw;
+    Angle gl;
+    for (int gi : diag) diag_terms_of(P.gates[gi], raw, gl);
+    diag.clear();
+    DiagIR d = build_diag(raw, gl);
+    if (d.groups.empty() && d.global.is_const() && d.global.c0 == 0.0) return;
+    add_diag_item(std::move(d));
+  }
+
+  void add_diag_item(DiagIR d) {
+    Item it;
+    it.ir = {1, (int32_t)P.diags.size()};
+    it.R = d.support;
+    P.diags.push_back(std::move(d));
+    seg.push_back(it);
+  }
+
+  void add_op_item(OpIR op) {
+    Item it;
+    it.ir = {0, (int32_t)P.ops.size()};
+    it.W = 1u << op.bit;
+    if (op.kind == OP_QFT) it.R = (op.bit == 0) ? 0u : ((1u << op.bit) - 1);
+    P.ops.push_back(std::move(op));
+    seg.push_back(it);
+  }
+
+  void close_window() {
+    std::vector<double> none;
+    bool all_x = true, any = false;
+    uint32_t xmask = 0;
+    std::vector<std::pair<int, std::vector<cd>>> prods;
+    for (int b = 0; b < n; ++b) {
+      auto& w = window[b];
+      if (w.empty()) continue;
+      bool fixed = true;
+      for (int gi : w) fixed = fixed && P.gates[gi].angle.is_const();
+      if (!fixed) { all_x = false; any = true; continue; }
+      std::vector<cd> U = gate_matrix(P.gates[w[0]], none);
+      for (size_t j = 1; j < w.size(); ++j) U = mul2(gate_matrix(P.gates[w[j]], none), U);
+      if (near2(U, 1, 0, 0, 1)) { w.clear(); continue; }
+      any = true;
+      if (near2(U, 0, 1, 1, 0)) xmask |= 1u << b;
+      else all_x = false;
+    }
+    if (!any) return;
+    if (all_x && xmask) {
+      std::vector<int> gl;
+      for (int b = 0; b < n; ++b) { for (int gi : window[b]) gl.push_back(gi); window[b].clear(); }
+      Gf2IR G;
+      G.rows.resize(n);
+      for (int r = 0; r < n; ++r) G.rows[r] = 1u << r;
+      G.cprime = xmask;
+      G.gates = gl;
+      barrier_gf2(std::move(G));
+      return;
+    }
+    for (int b = 0; b < n; ++b) {
+      auto& w = window[b];
+      if (w.empty()) continue;
+      bool fixed = true, diagonal = true;
+      for (int gi : w) {
+        fixed = fixed && P.gates[gi].angle.is_const();
+        diagonal = diagonal && gate_is_diagonal(P.gates[gi].kind);
+      }
+      OpIR op{OP_MAT, b, w, false, -1};
+      if (diagonal) op.kind = OP_DIAG;
+      else if (fixed) {
+        std::vector<cd> U = gate_matrix(P.gates[w[0]], none);
+        for (size_t j = 1; j < w.size(); ++j) U = mul2(gate_matrix(P.gates[w[j]], none), U);
+        const double r = 1.0 / std::sqrt(2.0);
+        if (near2(U, r, r, r, -r)) op.kind = OP_H;
+      }
+      add_op_item(std::move(op));
+      w.clear();
+    }
+  }
+
+  void close_perm() {
+    Gf2IR G = build_gf2(n, P.gates, perm);
+    perm.clear();
+    barrier_gf2(std::move(G));
+  }
+
+  void close_pp() {
+    // same-family run: basis change on the involved bits, ZZ-type diagonal, basis change back
+    bool yy = open == YY;
+    uint32_t inv = 0;
+    std::vector<DiagTermIR> raw;
+    Angle gl;
+    for (int gi : pp) {
+      const NGate& g = P.gates[gi];
+      inv |= (1u << g.bits[0]) | (1u << g.bits[1]);
+      NGate z = g;
+      z.kind = QS_GATE_RZZ;
+      diag_terms_of(z, raw, gl);
+    }
+    pp.clear();
+    for (int b = 0; b < n; ++b)
+      if ((inv >> b) & 1) add_op_item(OpIR{yy ? OP_MAT : OP_H, b, {}, true, yy ? 0 : -1});
+    add_diag_item(build_diag(raw, gl));
+    for (int b = 0; b < n; ++b)
+      if ((inv >> b) & 1) add_op_item(OpIR{yy ? OP_MAT : OP_H, b, {}, true, yy ? 1 : -1});
+  }
+
+  void barrier_gf2(Gf2IR G) {
+    // merge with an immediately preceding permutation layer
+    if (seg.empty() && !P.layers.empty() && P.layers.back().kind == L_GF2) {
+      Gf2IR& F = P.gf2s[P.layers.back().index];
+      F = compose_gf2(n, F, G);
+      return;
+    }
+    barrier({L_GF2, (int32_t)P.gf2s.size()});
+    P.gf2s.push_back(std::move(G));
+  }
+
+  void barrier(LayerIR L) {
+    flush_segment();
+    P.layers.push_back(L);
+  }
+
+  // ---- tile-pass scheduling of one segment ------------------------------------
+  void flush_segment() {
+    if (seg.empty()) return;
+    size_t N = seg.size();
+    std::vector<std::vector<int>> deps(N);
+    for (size_t j = 0; j < N; ++j)
+      for (size_t i = 0; i < j; ++i) {
+        bool conflict = (seg[i].W & (seg[j].W | seg[j].R)) || (seg[j].W & seg[i].R);
+        if (conflict) deps[j].push_back((int)i);
+      }
+    std::vector<char> done(N, 0);
+    size_t remaining = N;
+    while (remaining) {
+      int best = -1, best_ops = -1;
+      std::vector<int> best_list;
+      for (size_t g = 0; g < sched.grp.size(); ++g) {
+        std::vector<int> list;
+        int ops = scan(g, deps, done, list);
+        if (ops > best_ops) { best_ops = ops; best = (int)g; best_list = list; }
+      }
+      if (best_ops <= 0) {
+        // only diagonal layers are ready: run them as standalone passes
+        for (int idx : best_list) {
+          P.layers.push_back({L_DIAG, seg[idx].ir.index});
+          done[idx] = 1;
+          --remaining;
+        }
+        if (best_list.empty()) fail(QS_EINVAL, "internal: scheduler made no progress");
+        continue;
+      }
+      TilePassIR T;
+      T.L = sched.grp[best][0];
+      T.a = sched.grp[best][1];
+      T.h = sched.grp[best][2];
+      for (int idx : best_list) {
+        T.items.push_back(seg[idx].ir);
+        done[idx] = 1;
+        --remaining;
+      }
+      P.layers.push_back({L_TILE, (int32_t)P.passes.size()});
+      P.passes.push_back(std::move(T));
+    }
+    seg.clear();
+  }
+
+  int scan(size_t g, const std::vector<std::vector<int>>& deps, const std::vector<char>& done,
+           std::vector<int>& list) {
+    std::vector<char> taken(seg.size(), 0);
+    int ops = 0, ndiag = 0;
+    for (size_t j = 0; j < seg.size(); ++j) {
+      if (done[j]) continue;
+      bool ok = true;
+      for (int d : deps[j])
+        if (!done[d] && !taken[d]) { ok = false; break; }
+      if (!ok) continue;
+      if (seg[j].ir.type == 0) {
+        if ((seg[j].W & ~sched.gmask[g]) != 0) continue;
+        ++ops;
+      } else {
+        if (ndiag == kMaxDiagSlots) continue;
+        ++ndiag;
+      }
+      taken[j] = 1;
+      list.push_back((int)j);
+    }
+    return ops;
+  }
+};
+
+int tile_pos(const TilePassIR& T, int sb) {
+  if (sb < T.L) return sb;
+  if (sb >= T.a && sb < T.a + T.h) return T.L + (sb - T.a);
+  return -1;
+}
+int tile_state_bit(const TilePassIR& T, int tb) { return tb < T.L ? tb : T.a + (tb - T.L); }
+
+void finalize_pass(const PlanIR& P, TilePassIR& T) {
+  const int RB = kRoundBits;
+  int m = T.L + T.h;
+  T.rounds.clear();
+  T.ops.clear();
+  T.op_src.clear();
+  T.diag_slots.clear();
+  T.n_coef = 0;
+  std::vector<int> cur_bits;
+  std::vector<int> cur_ops;  // OpIR indices
+  int pending_diag = -1;
+  auto close = [&](bool force) {
+    if (cur_ops.empty() && pending_diag < 0 && !force) return;
+    TileRound r;
+    std::vector<int> bits = cur_bits;
+    for (int tb = 0; (int)bits.size() < RB && tb < m; ++tb)
+      if (std::find(bits.begin(), bits.end(), tb) == bits.end()) bits.push_back(tb);
+    std::sort(bits.begin(), bits.end());
+    for (int k = 0; k < RB; ++k) r.tbit[k] = bits[k];
+    r.op_begin = (int32_t)T.ops.size();
+    for (int oi : cur_ops) {
+      const OpIR& o = P.ops[oi];
+      TileOp op;
+      std::memset(&op, 0, sizeof op);
+      op.kind = o.kind;
+      op.sbit = o.bit;
+      int tb = tile_pos(T, o.bit);
+      op.rbit = (int32_t)(std::find(bits.begin(), bits.end(), tb) - bits.begin());
+      op.coef = T.n_coef;
+      op.slot = -1;
+      if (o.kind == OP_MAT) T.n_coef += 4;
+      else if (o.kind == OP_DIAG) T.n_coef += 2;
+      else if (o.kind == OP_QFT) T.n_coef += 1 << op.rbit;
+      T.ops.push_back(op);
+      T.op_src.push_back(oi);
+    }
+    r.op_end = (int32_t)T.ops.size();
+    r.diag = pending_diag;
+    r.diag_conj = 0;
+    T.rounds.push_back(r);
+    cur_bits.clear();
+    cur_ops.clear();
+    pending_diag = -1;
+  };
+  for (auto& it : T.items) {
+    if (it.type == 1) {
+      close(false);
+      pending_diag = (int)T.diag_slots.size();
+      T.diag_slots.push_back(it.index);
+      continue;
+    }
+    int tb = tile_pos(T, P.ops[it.index].bit);
+    if (tb < 0) fail(QS_EINVAL, "internal: op outside its tile");
+    bool have = std::find(cur_bits.begin(), cur_bits.end(), tb) != cur_bits.end();
+    if (!have && (int)cur_bits.size() == RB) close(false);
+    if (!have) cur_bits.push_back(tb);
+    cur_ops.push_back(it.index);
+  }
+  close(false);
+}
+
+}  // namespace
+
+PlanIR build_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOptions& opt,
+                  int tile_bits, int low_bits) {
+  PlanIR P;
+  P.n = n;
+  P.n_params = n_params;
+  P.opt = opt;
+  P.gates = std::move(gates);
+  P.tile_bits = tile_bits;
+  P.low_bits = low_bits;
+  if (opt.mode == QS_PLAIN || n < kRoundBits) {
+    for (size_t i = 0; i < P.gates.size(); ++i) P.layers.push_back({L_PLAIN, (int32_t)i});
+    return P;
+  }
+  Builder B(P, tile_bits, low_bits);
+  B.run();
+  for (auto& T : P.passes) finalize_pass(P, T);
+  return P;
+}
+
+// ---------------------------------------------------------------- numerics
+std::vector<cd> op_matrix(const PlanIR& P, const OpIR& op, const std::vector<double>& params) {
+  const double r = 1.0 / std::sqrt(2.0);
+  const cd I(0, 1);
+  if (op.fixed_h) {
+    if (op.fixed_mat == 0) return {r, -I * r, r, I * r};   // H S^dagger
+    if (op.fixed_mat == 1) return {r, r, I * r, -I * r};   // S H
+    return {r, r, r, -r};
+  }
+  if (op.kind == OP_H) return {r, r, r, -r};
+  std::vector<cd> U = gate_matrix(P.gates[op.gates[0]], params);
+  for (size_t j = 1; j < op.gates.size(); ++j) U = mul2(gate_matrix(P.gates[op.gates[j]], params), U);
+  return U;
+}
+
+std::vector<cd> pass_coefficients(const PlanIR& P, const TilePassIR& T, const std::vector<double>& params) {
+  std::vector<cd> coef((size_t)T.n_coef);
+  for (size_t k = 0; k < T.ops.size(); ++k) {
+    const TileOp& op = T.ops[k];
+    if (T.op_src[k] < 0) continue;
+    const OpIR& o = P.ops[T.op_src[k]];
+    if (op.kind == OP_MAT) {
+      auto U = op_matrix(P, o, params);
+      for (int e = 0; e < 4; ++e) coef[op.coef + e] = U[e];
+    } else if (op.kind == OP_DIAG) {
+      auto U = op_matrix(P, o, params);
+      coef[op.coef] = U[0];
+      coef[op.coef + 1] = U[3];
+    } else if (op.kind == OP_QFT) {
+      // intra-round twiddles: register bits below the op's bit
+      const TileRound* R = nullptr;
+      for (auto& r : T.rounds)
+        if ((int)k >= r.op_begin && (int)k < r.op_end) R = &r;
+      int s = op.rbit, p = op.sbit;
+      for (int kk = 0; kk < (1 << s); ++kk) {
+        double frac = 0.0;  // sum bit_t(kk) 2^(sb_t - p), exact in FP64
+        for (int t = 0; t < s; ++t)
+          if ((kk >> t) & 1) frac += std::ldexp(1.0, tile_state_bit(T, R->tbit[t]) - p);
+        coef[op.coef + kk] = std::polar(1.0, kPi * frac);
+      }
+    }
+  }
+  return coef;
+}
+
+// ---------------------------------------------------------------- describe
+static void jnum(std::ostringstream& o, double v) {
+  char b[40];
+  std::snprintf(b, sizeof b, "%.17g", v);
+  o << b;
+}
+static void jc(std::ostringstream& o, cd v) {
+  o << "[";
+  jnum(o, v.real());
+  o << ",";
+  jnum(o, v.imag());
+  o << "]";
+}
+
+static void describe_diag(std::ostringstream& o, const DiagIR& d, const std::vector<double>& params, bool bound) {
+  o << "{\"support\":" << d.support << ",\"groups\":[";
+  for (size_t g = 0; g < d.groups.size(); ++g) {
+    if (g) o << ",";
+    o << "{\"terms\":[";
+    for (size_t t = 0; t < d.groups[g].terms.size(); ++t) {
+      auto& tt = d.groups[g].terms[t];
+      if (t) o << ",";
+      o << "[" << tt.form << "," << tt.shift << "," << tt.mask << "]";
+    }
+    o << "],\"max_count\":" << d.groups[g].max_count << "}";
+  }
+  o << "]";
+  if (bound) {
+    DiagNumeric num = diag_numeric(d, params);
+    o << ",\"lut\":[";
+    for (size_t i = 0; i < num.lut.size(); ++i) { if (i) o << ","; jc(o, num.lut[i]); }
+    o << "],\"lut_groups\":[";
+    for (size_t i = 0; i < num.groups.size(); ++i) {
+      if (i) o << ",";
+      o << "[" << num.groups[i].term_begin << "," << num.groups[i].term_end << ","
+        << num.groups[i].lut_begin << "," << num.groups[i].lut_len << "]";
+    }
+    o << "],\"lut_terms\":[";
+    for (size_t i = 0; i < num.terms.size(); ++i) {
+      if (i) o << ",";
+      o << "[" << num.terms[i].form << "," << num.terms[i].shift << "," << num.terms[i].mask << "]";
+    }
+    o << "]";
+  }
+  o << "}";
+}
+
+std::string describe_json(const PlanIR& P, const std::vector<double>& params, bool bound) {
+  std::ostringstream o;
+  o << "{\"n\":" << P.n << ",\"n_params\":" << P.n_params << ",\"mode\":"
+    << (P.opt.mode == QS_PLAIN ? "\"plain\"" : "\"fused\"") << ",\"tile_bits\":" << P.tile_bits
+    << ",\"bound\":" << (bound ? "true" : "false") << ",\"layers\":[";
+  for (size_t li = 0; li < P.layers.size(); ++li) {
+    if (li) o << ",";
+    const LayerIR& L = P.layers[li];
+    if (L.kind == L_DIAG) {
+      o << "{\"kind\":\"diag\",\"diag\":";
+      describe_diag(o, P.diags[L.index], params, bound);
+      o << "}";
+    } else if (L.kind == L_GF2) {
+      const Gf2IR& G = P.gf2s[L.index];
+      o << "{\"kind\":\"gf2\",\"rows\":[";
+      for (size_t r = 0; r < G.rows.size(); ++r) { if (r) o << ","; o << G.rows[r]; }
+      o << "],\"cprime\":" << G.cprime << ",\"n_gates\":" << G.gates.size() << "}";
+    } else if (L.kind == L_PLAIN) {
+      const NGate& g = P.gates[L.index];
+      o << "{\"kind\":\"plain\",\"gate\":" << L.index << ",\"gate_kind\":" << g.kind << ",\"bits\":[";
+      for (size_t b = 0; b < g.bits.size(); ++b) { if (b) o << ","; o << g.bits[b]; }
+      o << "]}";
+    } else {
+      const TilePassIR& T = P.passes[L.index];
+      o << "{\"kind\":\"tile\",\"L\":" << T.L << ",\"a\":" << T.a << ",\"h\":" << T.h << ",\"rounds\":[";
+      for (size_t r = 0; r < T.rounds.size(); ++r) {
+        auto& R = T.rounds[r];
+        if (r) o << ",";
+        o << "{\"tbits\":[" << R.tbit[0] << "," << R.tbit[1] << "," << R.tbit[2] << "," << R.tbit[3]
+          << "],\"diag\":" << R.diag << ",\"ops\":[" << R.op_begin << "," << R.op_end << "]}";
+      }
+      o << "],\"ops\":[";
+      std::vector<cd> coef;
+      if (bound) coef = pass_coefficients(P, T, params);
+      for (size_t k = 0; k < T.ops.size(); ++k) {
+        auto& op = T.ops[k];
+        if (k) o << ",";
+        o << "{\"kind\":" << op.kind << ",\"bit\":" << op.sbit << ",\"rbit\":" << op.rbit;
+        if (bound) {
+          int nc = op.kind == OP_MAT ? 4 : op.kind == OP_DIAG ? 2 : op.kind == OP_QFT ? (1 << op.rbit) : 0;
+          o << ",\"coef\":[";
+          for (int e = 0; e < nc; ++e) { if (e) o << ","; jc(o, coef[op.coef + e]); }
+          o << "]";
+        }
+        o << "}";
+      }
+      o << "],\"diags\":[";
+      for (size_t s = 0; s < T.diag_slots.size(); ++s) {
+        if (s) o << ",";
+        describe_diag(o, P.diags[T.diag_slots[s]], params, bound);
+      }
+      o << "]}";
+    }
+  }
+  o << "]}";
+  return o.str();
+}
+
+}  // namespace qs

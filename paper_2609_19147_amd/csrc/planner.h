@@ -1,0 +1,154 @@
+// Host-side planner: validates a gate stream and rewrites it into layers.
+//
+// The rewrite is exact in exact arithmetic (paper, Section "Semantics-
+// Preserving Fusion"): only consecutive gates of one class are merged, gates
+// are reordered only when they commute, and numeric collapse tests (identity,
+// Hadamard, bit flip) use a tolerance of a few ulps on complex128 products so
+// that a small rotation such as RZ(1e-6) is never dropped.
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "layout.h"
+#include "qs.h"
+
+namespace qs {
+
+using cd = std::complex<double>;
+
+struct Error {
+  qs_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(qs_status code, const std::string& msg);
+
+// Angle = c0 + sum_k coef_k * params[k]  (kept symbolic so that parameters can
+// be re-bound without re-planning).
+struct Angle {
+  double c0 = 0.0;
+  std::vector<std::pair<int32_t, double>> lin;  // sorted by parameter index
+  bool is_const() const { return lin.empty(); }
+  double eval(const std::vector<double>& p) const;
+  Angle plus(const Angle& o) const;
+  Angle scaled(double s) const;
+  bool same(const Angle& o) const;  // bit-identical
+};
+
+// A validated gate with wires converted to state bit positions.
+struct NGate {
+  int32_t kind = 0;
+  std::vector<int> bits;   // listed order (controls first, target last)
+  uint32_t all_mask = 0;   // MCZ / MCP support
+  Angle angle;
+  std::vector<cd> mat;     // U, CU (2x2), UNITARY (2^k x 2^k)
+  int32_t index = 0;       // position in the stream
+};
+
+bool gate_is_diagonal(int kind);
+int gate_arity(const qs_gate& g);
+// Dense matrix of a gate (2^k x 2^k, row-major, first listed wire = most
+// significant row bit; MCZ/MCP over their sorted support bits, highest bit
+// first).  Angles evaluated with params.
+std::vector<cd> gate_matrix(const NGate& g, const std::vector<double>& params);
+
+// ---- layer IR -------------------------------------------------------------------
+struct DiagTermIR {
+  int32_t type;     // 0 BIT, 1 XOR pair, 2 AND pair, 3 ALL (k >= 3), 4 PARITY (k >= 3)
+  uint32_t mask;
+  Angle angle;
+};
+struct DiagGroupIR {
+  Angle angle;
+  std::vector<DiagTerm> terms;  // device count terms
+  int32_t max_count = 0;
+};
+struct DiagIR {
+  std::vector<DiagGroupIR> groups;
+  Angle global;
+  uint32_t support = 0;
+};
+
+// One butterfly operation of a tile pass.
+struct OpIR {
+  int32_t kind;  // TileOpKind
+  int32_t bit;   // state bit
+  // OP_MAT / OP_DIAG: the single-qubit window on this wire, gates in stream
+  // order (the op's matrix is their product).
+  std::vector<int32_t> gates;
+  bool fixed_h = false;  // OP_H produced by a basis change (no source gates)
+  int32_t fixed_mat = -1;  // basis-change matrix id (0: H S^dagger, 1: S H)
+};
+
+struct ItemIR {
+  int32_t type;  // 0 op, 1 diag
+  int32_t index; // into Plan::ops or Plan::diags
+};
+
+struct TilePassIR {
+  int32_t L, a, h;           // tile bits [0, L) U [a, a+h)
+  std::vector<ItemIR> items; // in execution order
+  // built by finalize(): rounds and ops in device form (coef offsets are
+  // relative to this pass's coefficient array)
+  std::vector<TileRound> rounds;
+  std::vector<TileOp> ops;
+  std::vector<int32_t> op_src;   // OpIR index per device op (or -1 for QFT-only ops)
+  std::vector<int32_t> diag_slots;  // DiagIR index per slot
+  int32_t n_coef = 0;
+};
+
+struct Gf2IR {
+  std::vector<uint32_t> rows;  // A rows: src bit r = parity(rows[r] & y)
+  uint32_t cprime = 0;
+  std::vector<int32_t> gates;  // source gates (for describe)
+};
+
+enum LayerKind : int32_t { L_DIAG = 0, L_TILE = 1, L_GF2 = 2, L_PLAIN = 3 };
+
+struct LayerIR {
+  int32_t kind;
+  int32_t index;  // into diags / passes / gf2s / plain gate index (into Plan::gates)
+};
+
+struct PlanOptions {
+  int mode = QS_FUSED;
+  int max_tile_bits = 0;  // 0 = default by dtype at apply time
+};
+
+struct PlanIR {
+  int n = 0;
+  size_t n_params = 0;
+  PlanOptions opt;
+  std::vector<NGate> gates;
+  std::vector<DiagIR> diags;
+  std::vector<OpIR> ops;
+  std::vector<TilePassIR> passes;
+  std::vector<Gf2IR> gf2s;
+  std::vector<LayerIR> layers;
+  int tile_bits = 13;  // tile size used to build the passes
+  int low_bits = 4;    // L of high tiles
+};
+
+// Validate + normalise the user's gates.
+std::vector<NGate> normalise_gates(int n, const qs_gate* g, size_t count, size_t n_params);
+// Build the plan.  tile_bits / low_bits fix the tile geometry.
+PlanIR build_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOptions& opt,
+                  int tile_bits, int low_bits);
+
+// ---- numeric materialisation ----------------------------------------------------
+// LUT of one diagonal layer (complex128) and per-pass coefficients.
+struct DiagNumeric {
+  std::vector<DiagTerm> terms;
+  std::vector<DiagGroup> groups;
+  std::vector<cd> lut;
+};
+DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj = false);
+std::vector<cd> pass_coefficients(const PlanIR& p, const TilePassIR& t, const std::vector<double>& params);
+cd op_matrix_entry(const PlanIR& p, const OpIR& op, const std::vector<double>& params, int r, int c);
+std::vector<cd> op_matrix(const PlanIR& p, const OpIR& op, const std::vector<double>& params);
+Gf2Args gf2_args(int n, const Gf2IR& g, int c_bits);
+
+std::string describe_json(const PlanIR& p, const std::vector<double>& params, bool bound);
+
+}  // namespace qs

@@ -1,0 +1,332 @@
+// Layer execution, plan device tables and reduction drivers.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+namespace qs {
+
+namespace {
+
+struct Blob {
+  std::vector<unsigned char> bytes;
+  template <class T>
+  size_t put(const std::vector<T>& v) {
+    size_t off = (bytes.size() + 15) & ~size_t(15);
+    bytes.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+template <class R>
+std::vector<cplx<R>> cast(const std::vector<cd>& v) {
+  std::vector<cplx<R>> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = {(R)v[i].real(), (R)v[i].imag()};
+  return o;
+}
+
+template <class R>
+void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
+  const PlanIR& P = p.ir;
+  d.diag_terms.assign(P.diags.size(), 0);
+  d.diag_groups.assign(P.diags.size(), 0);
+  d.diag_lut.assign(P.diags.size(), 0);
+  d.diag_ngroups.assign(P.diags.size(), 0);
+  for (size_t i = 0; i < P.diags.size(); ++i) {
+    DiagNumeric num = diag_numeric(P.diags[i], p.params);
+    d.diag_terms[i] = b.put(num.terms);
+    d.diag_groups[i] = b.put(num.groups);
+    d.diag_lut[i] = b.put(cast<R>(num.lut));
+    d.diag_ngroups[i] = (int)num.groups.size();
+  }
+  d.pass_rounds.assign(P.passes.size(), 0);
+  d.pass_ops.assign(P.passes.size(), 0);
+  d.pass_coef.assign(P.passes.size(), 0);
+  for (size_t i = 0; i < P.passes.size(); ++i) {
+    const TilePassIR& T = P.passes[i];
+    d.pass_rounds[i] = b.put(T.rounds);
+    d.pass_ops[i] = b.put(T.ops);
+    d.pass_coef[i] = b.put(cast<R>(pass_coefficients(P, T, p.params)));
+  }
+  b.put(std::vector<double>(2, 0.0));  // never zero bytes
+}
+
+}  // namespace
+
+}  // namespace qs
+
+using namespace qs;
+
+const PlanDev& qs_plan::device_for(qs_dtype dt) {
+  PlanDev& d = dev[dt];
+  if (gf2.size() != ir.gf2s.size()) {
+    gf2.clear();
+    for (auto& g : ir.gf2s) gf2.push_back(gf2_args(ir.n, g, kGf2MaxC));
+  }
+  if (d.valid) return d;
+  Blob b;
+  if (dt == QS_C64) build_blob<float>(*this, d, b);
+  else build_blob<double>(*this, d, b);
+  if (d.blob && d.bytes != b.bytes.size()) {
+    hipFree(d.blob);
+    d.blob = nullptr;
+  }
+  if (!d.blob) check_hip(hipMalloc(&d.blob, b.bytes.size()), "hipMalloc(plan tables)");
+  d.bytes = b.bytes.size();
+  check_hip(hipMemcpy(d.blob, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice), "hipMemcpy(plan tables)");
+  d.valid = true;
+  return d;
+}
+
+void qs_plan::refresh_device() {
+  bool any = dev[0].blob || dev[1].blob;
+  if (!any) return;
+  // kernels already enqueued may still read the tables
+  check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  for (int k = 0; k < 2; ++k)
+    if (dev[k].blob) {
+      dev[k].valid = false;
+      device_for((qs_dtype)k);
+    }
+}
+
+namespace qs {
+
+namespace {
+
+DiagDev diag_dev(const PlanDev& d, const char* base, int i, bool conj) {
+  DiagDev D;
+  D.terms = (const DiagTerm*)(base + d.diag_terms[i]);
+  D.groups = (const DiagGroup*)(base + d.diag_groups[i]);
+  D.lut = base + d.diag_lut[i];
+  D.n_groups = d.diag_ngroups[i];
+  D.conj = conj ? 1 : 0;
+  return D;
+}
+
+template <class R>
+void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
+  const PlanDev& d = p.device_for(s.dtype);
+  const char* base = (const char*)d.blob;
+  const PlanIR& P = p.ir;
+  const int max_bits = s.dtype == QS_C64 ? 14 : 13;
+  for (size_t li = first; li < last; ++li) {
+    const LayerIR& L = P.layers[li];
+    switch (L.kind) {
+      case L_DIAG:
+        launch_diag<R>((cplx<R>*)s.cur_ptr(), s.n, diag_dev(d, base, L.index, false), s.stream);
+        break;
+      case L_TILE: {
+        const TilePassIR& T = P.passes[L.index];
+        if (T.L + T.h > max_bits) fail(QS_EINVAL, "tile too large for this dtype");
+        TileKArgs<R> A;
+        std::memset(&A, 0, sizeof A);
+        A.psi = (cplx<R>*)s.cur_ptr();
+        A.rounds = (const TileRound*)(base + d.pass_rounds[L.index]);
+        A.ops = (const TileOp*)(base + d.pass_ops[L.index]);
+        A.coef = (const cplx<R>*)(base + d.pass_coef[L.index]);
+        for (size_t k = 0; k < T.diag_slots.size(); ++k) A.diag[k] = diag_dev(d, base, T.diag_slots[k], false);
+        A.L = T.L;
+        A.a = T.a;
+        A.h = T.h;
+        A.m = T.L + T.h;
+        A.n_rounds = (uint32_t)T.rounds.size();
+        A.n = s.n;
+        launch_tile<R>(A, s.stream);
+        break;
+      }
+      case L_GF2: {
+        s.ensure_other();
+        launch_gf2<R>((const cplx<R>*)s.buf[s.cur], (cplx<R>*)s.buf[1 - s.cur], p.gf2[L.index], s.stream);
+        s.cur = 1 - s.cur;
+        break;
+      }
+      case L_PLAIN:
+        apply_plain_gate(s, P.gates[L.index], p.params);
+        break;
+      default:
+        fail(QS_EINVAL, "internal: unknown layer kind");
+    }
+  }
+}
+
+template <class R>
+void plain_t(qs_state& s, const NGate& g, const std::vector<double>& params) {
+  cplx<R>* psi = (cplx<R>*)s.cur_ptr();
+  const int n = s.n;
+  std::vector<cd> M = gate_matrix(g, params);
+  std::vector<cplx<R>> m = cast<R>(M);
+  const auto& b = g.bits;
+  switch (g.kind) {
+    case QS_GATE_I:
+      return;
+    case QS_GATE_X:
+      launch_flip<R>(psi, n, b[0], s.stream);
+      return;
+    case QS_GATE_Z: case QS_GATE_S: case QS_GATE_SDG: case QS_GATE_T: case QS_GATE_TDG: case QS_GATE_P:
+      launch_phase_mask<R>(psi, n, 1u << b[0], m[3], s.stream);
+      return;
+    case QS_GATE_RZ:
+      launch_diag1<R>(psi, n, b[0], m[0], m[3], s.stream);
+      return;
+    case QS_GATE_CNOT:
+      launch_cflip<R>(psi, n, b[0], b[1], s.stream);
+      return;
+    case QS_GATE_CZ: case QS_GATE_CPHASE:
+      launch_phase_mask<R>(psi, n, (1u << b[0]) | (1u << b[1]), m[15], s.stream);
+      return;
+    case QS_GATE_MCZ: case QS_GATE_MCP:
+      launch_phase_mask<R>(psi, n, g.all_mask, m.back(), s.stream);
+      return;
+    case QS_GATE_SWAP:
+      launch_swap<R>(psi, n, b[0], b[1], s.stream);
+      return;
+    case QS_GATE_RZZ:
+      launch_parity_phase<R>(psi, n, (1u << b[0]) | (1u << b[1]), m[0], m[5], s.stream);
+      return;
+    case QS_GATE_CU: {
+      const cplx<R> u[4] = {m[10], m[11], m[14], m[15]};  // target block of the controlled matrix
+      launch_cmat1<R>(psi, n, b[0], b[1], u, s.stream);
+      return;
+    }
+    default:
+      break;
+  }
+  if (b.size() == 1) {
+    launch_mat1<R>(psi, n, b[0], m.data(), s.stream);
+  } else if (b.size() == 2) {
+    launch_mat2<R>(psi, n, b[0], b[1], m.data(), s.stream);
+  } else {
+    if (!s.matbuf) check_hip(hipMalloc(&s.matbuf, 64 * 64 * sizeof(cplx<double>)), "hipMalloc");
+    check_hip(hipMemcpyAsync(s.matbuf, m.data(), m.size() * sizeof(cplx<R>), hipMemcpyHostToDevice, s.stream),
+              "hipMemcpyAsync");
+    launch_matk<R>(psi, n, (int)b.size(), b.data(), (const cplx<R>*)s.matbuf, s.stream);
+    s.sync();  // the staging buffer is reused by the next dense gate
+  }
+}
+
+template <class Ra, class Rb>
+std::complex<double> overlap_t(qs_state& a, qs_state& b) {
+  a.ensure_red();
+  launch_overlap<Ra, Rb>((const cplx<Ra>*)a.cur_ptr(), (const cplx<Rb>*)b.cur_ptr(), 1ull << a.n, a.red_partials,
+                         a.red_out, a.stream);
+  double o[2];
+  check_hip(hipMemcpyAsync(o, a.red_out, sizeof o, hipMemcpyDeviceToHost, a.stream), "hipMemcpyAsync");
+  a.sync();
+  return {o[0], o[1]};
+}
+
+template <class Ra, class Rb>
+double distance_t(qs_state& a, qs_state& b, double ar, double ai, double bs) {
+  a.ensure_red();
+  launch_distance2<Ra, Rb>((const cplx<Ra>*)a.cur_ptr(), (const cplx<Rb>*)b.cur_ptr(), 1ull << a.n, ar, ai, bs,
+                           a.red_partials, a.red_out, a.stream);
+  double o;
+  check_hip(hipMemcpyAsync(&o, a.red_out, sizeof o, hipMemcpyDeviceToHost, a.stream), "hipMemcpyAsync");
+  a.sync();
+  return o;
+}
+
+}  // namespace
+
+void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last) {
+  if (s.dtype == QS_C64) apply_layers_t<float>(s, p, first, last);
+  else apply_layers_t<double>(s, p, first, last);
+}
+
+void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params) {
+  if (s.dtype == QS_C64) plain_t<float>(s, g, params);
+  else plain_t<double>(s, g, params);
+}
+
+double state_norm2(qs_state& s) {
+  s.ensure_red();
+  if (s.dtype == QS_C64)
+    launch_norm2<float>((const cplx<float>*)s.cur_ptr(), 1ull << s.n, s.red_partials, s.red_out, s.stream);
+  else
+    launch_norm2<double>((const cplx<double>*)s.cur_ptr(), 1ull << s.n, s.red_partials, s.red_out, s.stream);
+  double o;
+  check_hip(hipMemcpyAsync(&o, s.red_out, sizeof o, hipMemcpyDeviceToHost, s.stream), "hipMemcpyAsync");
+  s.sync();
+  return o;
+}
+
+std::complex<double> state_overlap(qs_state& a, qs_state& b) {
+  if (a.stream != b.stream) b.sync();
+  if (a.dtype == QS_C64 && b.dtype == QS_C64) return overlap_t<float, float>(a, b);
+  if (a.dtype == QS_C64) return overlap_t<float, double>(a, b);
+  if (b.dtype == QS_C64) return overlap_t<double, float>(a, b);
+  return overlap_t<double, double>(a, b);
+}
+
+double state_infidelity(qs_state& a, qs_state& b) {
+  const double na = state_norm2(a), nb = state_norm2(b);
+  if (!(na > 0) || !(nb > 0)) fail(QS_EINVAL, "zero state");
+  const std::complex<double> ov = state_overlap(a, b);
+  const double ph = std::arg(ov);
+  const double ar = std::cos(ph) / std::sqrt(na), ai = std::sin(ph) / std::sqrt(na), bs = 1.0 / std::sqrt(nb);
+  if (a.stream != b.stream) b.sync();
+  double D;
+  if (a.dtype == QS_C64 && b.dtype == QS_C64) D = distance_t<float, float>(a, b, ar, ai, bs);
+  else if (a.dtype == QS_C64) D = distance_t<float, double>(a, b, ar, ai, bs);
+  else if (b.dtype == QS_C64) D = distance_t<double, float>(a, b, ar, ai, bs);
+  else D = distance_t<double, double>(a, b, ar, ai, bs);
+  return std::max(0.0, D * (1.0 - D / 4.0));
+}
+
+std::vector<double> state_expect(qs_state& s, const qs_pauli* terms, size_t n_terms) {
+  const int n = s.n;
+  std::vector<double> out(n_terms, 0.0);
+  std::map<uint32_t, std::vector<size_t>> by_x;
+  std::vector<uint32_t> zb(n_terms);
+  std::vector<int> ny(n_terms);
+  for (size_t t = 0; t < n_terms; ++t) {
+    const qs_pauli& P = terms[t];
+    if (!std::isfinite(P.coeff)) fail(QS_EINVAL, "non-finite Pauli coefficient");
+    if (n < 64 && ((P.x_mask >> n) || (P.z_mask >> n))) fail(QS_EINVAL, "Pauli mask out of range");
+    uint32_t x = 0, z = 0;
+    for (int q = 0; q < n; ++q) {
+      if ((P.x_mask >> q) & 1) x |= 1u << (n - 1 - q);
+      if ((P.z_mask >> q) & 1) z |= 1u << (n - 1 - q);
+    }
+    zb[t] = z;
+    ny[t] = __builtin_popcount(x & z) & 3;
+    by_x[x].push_back(t);
+  }
+  s.ensure_red();
+  for (auto& kv : by_x) {
+    const auto& idx = kv.second;
+    for (size_t c0 = 0; c0 < idx.size(); c0 += kMaxTermsPerLaunch) {
+      int nt = (int)std::min<size_t>(kMaxTermsPerLaunch, idx.size() - c0);
+      uint32_t zz[kMaxTermsPerLaunch];
+      int yy[kMaxTermsPerLaunch];
+      for (int k = 0; k < nt; ++k) {
+        zz[k] = zb[idx[c0 + k]];
+        yy[k] = ny[idx[c0 + k]];
+      }
+      if (kv.first == 0) {
+        if (s.dtype == QS_C64)
+          launch_expect_z<float>((const cplx<float>*)s.cur_ptr(), n, zz, nt, s.red_partials, s.red_out, s.stream);
+        else
+          launch_expect_z<double>((const cplx<double>*)s.cur_ptr(), n, zz, nt, s.red_partials, s.red_out, s.stream);
+      } else {
+        if (s.dtype == QS_C64)
+          launch_expect_x<float>((const cplx<float>*)s.cur_ptr(), n, kv.first, zz, yy, nt, s.red_partials, s.red_out,
+                                 s.stream);
+        else
+          launch_expect_x<double>((const cplx<double>*)s.cur_ptr(), n, kv.first, zz, yy, nt, s.red_partials,
+                                  s.red_out, s.stream);
+      }
+      double o[kMaxTermsPerLaunch];
+      check_hip(hipMemcpyAsync(o, s.red_out, sizeof o, hipMemcpyDeviceToHost, s.stream), "hipMemcpyAsync");
+      s.sync();
+      for (int k = 0; k < nt; ++k) out[idx[c0 + k]] = terms[idx[c0 + k]].coeff * o[k];
+    }
+  }
+  return out;
+}
+
+}  // namespace qs

@@ -1,0 +1,73 @@
+// Runtime objects behind the C ABI: states, plans with their device tables,
+// layer execution and the reduction drivers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <vector>
+
+#include "kernels.h"
+#include "planner.h"
+#include "qs.h"
+
+struct qs_state {
+  int n = 0;
+  qs_dtype dtype = QS_C64;
+  int device = 0;
+  void* buf[2] = {nullptr, nullptr};
+  bool owned[2] = {false, false};
+  int cur = 0;
+  bool view = false;  // owned by a batch
+  hipStream_t stream = nullptr;
+  double* red_partials = nullptr;
+  double* red_out = nullptr;
+  void* matbuf = nullptr;  // device staging for dense plain gates
+
+  size_t amp_bytes() const;
+  size_t state_bytes() const;
+  void* cur_ptr() const { return buf[cur]; }
+  void ensure_other();
+  void ensure_red();
+  void sync();
+  ~qs_state();
+};
+
+namespace qs {
+
+// Device tables of a plan for one precision.
+struct PlanDev {
+  void* blob = nullptr;
+  size_t bytes = 0;
+  bool valid = false;
+  std::vector<size_t> diag_terms, diag_groups, diag_lut;
+  std::vector<int> diag_ngroups;
+  std::vector<size_t> pass_rounds, pass_ops, pass_coef;
+  std::vector<size_t> plain_mat;  // per layer (only dense plain gates), else 0
+};
+
+void check_hip(hipError_t e, const char* what);
+
+}  // namespace qs
+
+struct qs_plan {
+  qs::PlanIR ir;
+  std::vector<double> params;
+  bool bound = false;
+  qs::PlanDev dev[2];
+  std::vector<qs::Gf2Args> gf2;  // host-side kernel arguments per GF(2) layer
+
+  void refresh_device();  // rebuild the tables of every precision already on the device
+  const qs::PlanDev& device_for(qs_dtype dt);
+  ~qs_plan();
+};
+
+namespace qs {
+
+void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last);
+void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params);
+double state_norm2(qs_state& s);
+std::complex<double> state_overlap(qs_state& a, qs_state& b);
+double state_infidelity(qs_state& a, qs_state& b);
+std::vector<double> state_expect(qs_state& s, const qs_pauli* terms, size_t n_terms);
+
+}  // namespace qs

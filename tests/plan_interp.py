@@ -1,0 +1,102 @@
+"""Test-side numpy interpreter of a described plan (``Plan.describe()``).
+
+Applies the layers exactly as the plan states them -- tile passes round by
+round, diagonal layers from their FP64 lookup tables, GF(2) gathers from
+their row masks -- so the planner's rewrite can be checked against the
+one-gate-at-a-time oracle on the CPU, without a GPU.  QFT stages use the
+plain stage definition (butterfly on bit p, then exp(i pi (i mod 2^p) / 2^p)
+on the bit-p = 1 half).  Plain layers call the oracle's gate application.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import statevec as sv
+
+
+def _popc(x):
+    return np.bitwise_count(x).astype(np.int64)
+
+
+def diag_phase(d, n):
+    I = np.arange(1 << n, dtype=np.uint64)
+    lut = np.array([complex(a, b) for a, b in d["lut"]])
+    ph = np.ones(1 << n, dtype=np.complex128)
+    terms = d["lut_terms"]
+    for tb, te, lb, ll in d["lut_groups"]:
+        cnt = np.zeros(1 << n, dtype=np.int64)
+        for form, shift, mask in terms[tb:te]:
+            m = np.uint64(mask)
+            s = np.uint64(shift)
+            if form == 0:
+                cnt += _popc(I & m)
+            elif form == 1:
+                cnt += _popc((I ^ (I >> s)) & m)
+            elif form == 2:
+                cnt += _popc((I & (I >> s)) & m)
+            elif form == 3:
+                cnt += _popc(I & m) & 1
+            else:
+                cnt += ((I & m) == m).astype(np.int64)
+        assert cnt.max() < ll
+        ph *= lut[lb + cnt]
+    return ph
+
+
+def apply_bit_2x2(psi, n, b, U):
+    v = psi.reshape(1 << (n - 1 - b), 2, 1 << b)
+    x = v[:, 0, :].copy()
+    y = v[:, 1, :].copy()
+    v[:, 0, :] = U[0][0] * x + U[0][1] * y
+    v[:, 1, :] = U[1][0] * x + U[1][1] * y
+
+
+def apply_layer(psi, n, L, stream, params):
+    k = L["kind"]
+    if k == "diag":
+        return psi * diag_phase(L["diag"], n)
+    if k == "gf2":
+        rows = [np.uint64(r) for r in L["rows"]]
+        y = np.arange(1 << n, dtype=np.uint64)
+        src = np.zeros_like(y)
+        for r, row in enumerate(rows):
+            src |= (_popc(y & row) & 1).astype(np.uint64) << np.uint64(r)
+        src ^= np.uint64(L["cprime"])
+        return psi[src.astype(np.int64)]
+    if k == "plain":
+        return sv.apply_gate(psi, n, stream[L["gate"]], params)
+    assert k == "tile"
+    psi = psi.copy()
+    r2 = 1 / math.sqrt(2)
+    for R in L["rounds"]:
+        if R["diag"] >= 0:
+            psi *= diag_phase(L["diags"][R["diag"]], n)
+        for op in L["ops"][R["ops"][0]:R["ops"][1]]:
+            b = op["bit"]
+            c = [complex(a, bb) for a, bb in op.get("coef", [])]
+            if op["kind"] == 0:
+                apply_bit_2x2(psi, n, b, [[c[0], c[1]], [c[2], c[3]]])
+            elif op["kind"] == 3:
+                apply_bit_2x2(psi, n, b, [[c[0], 0], [0, c[1]]])
+            elif op["kind"] == 1:
+                apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
+            elif op["kind"] == 2:
+                apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
+                i = np.arange(1 << n, dtype=np.int64)
+                low = i & ((1 << b) - 1)
+                tw = np.exp(1j * math.pi * low / (1 << b))
+                sel = ((i >> b) & 1) == 1
+                psi[sel] *= tw[sel]
+            else:
+                raise AssertionError(f"unexpected op kind {op['kind']}")
+    return psi
+
+
+def run_plan(desc, psi0, stream, params=None):
+    n = desc["n"]
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    for L in desc["layers"]:
+        psi = apply_layer(psi, n, L, stream, params)
+    return psi

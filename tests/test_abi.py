@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every symbol include/qs.h declares
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "qs.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:qs_status|const char\*)\s+(qs_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    syms = header_symbols()
+    for name in ("qs_alloc", "qs_apply_layer", "qs_expect", "qs_adjoint_grad", "qs_plan_create",
+                 "qs_apply_gates", "qs_batch_run", "qs_infidelity"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2609_19147_amd import _lib
+    lib = _lib.lib()
+    missing = [s for s in header_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert sorted(_lib.EXPORTED) == header_symbols()
+
+
+def test_version_and_error_message():
+    from paper_2609_19147_amd import _lib
+    lib = _lib.lib()
+    assert b"gfx950" in lib.qs_version()
+    h = ctypes.c_void_p()
+    rc = lib.qs_plan_create(0, None, 0, 0, None, ctypes.byref(h))
+    assert rc == _lib.QS_EINVAL
+    assert b"qubit count" in lib.qs_last_error()
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    from paper_2609_19147_amd import _lib
+    lib = _lib.lib()
+    assert lib.qs_norm2(None, None) == _lib.QS_EINVAL
+    assert lib.qs_apply_layer(None, None, 0, 0) == _lib.QS_EINVAL
+    assert lib.qs_alloc(40, 0, None, None, 0, None, ctypes.byref(ctypes.c_void_p())) == _lib.QS_EINVAL
+    assert lib.qs_alloc(4, 7, None, None, 0, None, ctypes.byref(ctypes.c_void_p())) == _lib.QS_EINVAL
+
+
+def test_extension_missing_fails_loudly(monkeypatch, tmp_path):
+    from paper_2609_19147_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        _lib.lib()

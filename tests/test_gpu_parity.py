@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (floating point): state infidelity <= 1e-10 in complex64 and <= 1e-24
+in complex128 (normalised, cancellation-free form), element-wise amplitude
+agreement to a tolerance derived from float32 rounding; permutations are
+bit-exact.  Inputs are seeded; the oracle starts from the device-rounded
+input values.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import closed, metrics, statevec as sv
+
+pytestmark = pytest.mark.gpu
+
+INF64 = 1e-10
+INF128 = 1e-24
+
+
+@pytest.fixture(scope="module")
+def qs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2609_19147_amd as q
+    q._lib.lib()
+    return q
+
+
+def start(qs, n, dtype, seed=12):
+    psi0 = W.gaussian_state(n, seed)
+    nd = np.complex64 if dtype == "c64" else np.complex128
+    psi0 = psi0.astype(nd)
+    st = qs.State(n, dtype, init=None)
+    st.upload(psi0)
+    return st, psi0.astype(np.complex128)
+
+
+def compare(qs, st, ref, dtype, n):
+    got = st.download().astype(np.complex128)
+    inf = metrics.infidelity(got, ref)
+    bar = INF64 if dtype == "c64" else INF128
+    assert inf <= bar, (n, dtype, inf)
+    # element-wise: float32 rounding per operation, relative to the typical amplitude
+    amp = 1.0 / math.sqrt(1 << n)
+    atol = (5e-6 if dtype == "c64" else 1e-13) * amp * max(1.0, math.sqrt(n))
+    assert np.max(np.abs(got - ref)) <= atol * 20, np.max(np.abs(got - ref)) / amp
+    return inf
+
+
+# ------------------------------------------------------------------ config 1: 12q QFT
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["plain", "fused"])
+def test_qft12_gate_by_gate_and_fused(qs, dtype, mode):
+    n = 12
+    st, psi0 = start(qs, n, dtype)
+    stream = W.qft_stream(n)
+    if mode == "plain":
+        qs.apply_gates(st, stream)
+    else:
+        qs.apply(st, qs.Plan(n, stream))
+    ref = sv.run(psi0, n, stream)
+    compare(qs, st, ref, dtype, n)
+    assert abs(qs.norm2(st) - metrics.norm2(ref)) < (1e-6 if dtype == "c64" else 1e-14)
+
+
+# ------------------------------------------------------------------ mixed streams
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (3, 2), (4, 3), (5, 4), (9, 5), (13, 6), (14, 7), (17, 8)])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_random_streams_plain_and_fused(qs, n, seed, dtype):
+    kinds = None if n >= 2 else ("H", "X", "Y", "Z", "S", "T", "SX", "RX", "RY", "RZ", "P", "U")
+    stream = W.random_stream(n, 150, seed, kinds)
+    ref = None
+    for mode in ("plain", "fused"):
+        st, psi0 = start(qs, n, dtype, seed)
+        if ref is None:
+            ref = sv.run(psi0, n, stream)
+        if mode == "plain":
+            qs.apply_gates(st, stream)
+        else:
+            qs.apply(st, qs.Plan(n, stream))
+        compare(qs, st, ref, dtype, n)
+
+
+@pytest.mark.parametrize("tile_bits", [5, 8, 13, 14])
+def test_tile_geometries(qs, tile_bits):
+    n = 18
+    stream = W.qft_stream(n) + W.tfim_strang_stream(n, 1.0, 0.8, 0.05, 2, h_layer=False) + W.wht_stream(n)
+    st, psi0 = start(qs, n, "c64", 3)
+    plan = qs.Plan(n, stream, max_tile_bits=tile_bits)
+    qs.apply(st, plan)
+    compare(qs, st, sv.run(psi0, n, stream), "c64", n)
+
+
+def test_multi_qubit_and_controlled(qs):
+    n = 11
+    rng = np.random.default_rng(4)
+    stream = (W.wht_stream(n) + [W.G("MCZ", 0, 3, 7), W.G("MCP", 1, 2, 9, 10, theta=0.3),
+                                 W.G("UNITARY", 5, 1, 8, mat=W.random_unitary(8, rng)),
+                                 W.G("UNITARY", 2, 6, mat=W.random_unitary(4, rng)),
+                                 W.G("CU", 4, 0, mat=W.random_unitary(2, rng))] + W.random_stream(n, 40, 9))
+    for mode in ("plain", "fused"):
+        st, psi0 = start(qs, n, "c128", 5)
+        if mode == "plain":
+            qs.apply_gates(st, stream)
+        else:
+            qs.apply(st, qs.Plan(n, stream))
+        compare(qs, st, sv.run(psi0, n, stream), "c128", n)
+
+
+# ------------------------------------------------------------------ permutations (bit-exact)
+@pytest.mark.parametrize("n", [2, 7, 12, 20])
+def test_gf2_gather_bit_exact(qs, n):
+    stream = W.random_perm_block(n, 200, 31)
+    tag = W.index_tag_state(n).astype(np.complex64)
+    for mode in ("plain", "fused"):
+        st = qs.State(n, "c64", init=None)
+        st.upload(tag)
+        if mode == "plain":
+            qs.apply_gates(st, stream)
+        else:
+            qs.apply(st, qs.Plan(n, stream))
+        got = st.download()
+        src = closed.perm_source(n, stream, np.arange(1 << n, dtype=np.uint64)).astype(np.int64)
+        assert np.array_equal(got, tag[src]), mode
+
+
+def test_ghz(qs):
+    n = 16
+    st = qs.State(n, "c64")
+    qs.apply(st, qs.Plan(n, W.ghz_stream(n)))
+    a = qs.amplitudes(st, [0, (1 << n) - 1, 1, 12345])
+    assert np.allclose(a[:2], 1 / math.sqrt(2), atol=1e-7) and np.all(a[2:] == 0)
+
+
+def test_grover_success(qs):
+    n, k = 12, 8
+    marked = 0b101100111010
+    st = qs.State(n, "c128")
+    qs.apply(st, qs.Plan(n, W.grover_stream(n, marked, k)))
+    th = math.asin(1 / math.sqrt(1 << n))
+    p = abs(qs.amplitudes(st, [marked])[0]) ** 2
+    assert abs(p - math.sin((2 * k + 1) * th) ** 2) < 1e-12
+
+
+# ------------------------------------------------------------------ reductions
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_expectations_norm_overlap(qs, dtype):
+    n = 13
+    st, psi = start(qs, n, dtype, 21)
+    terms = W.xxz_terms(n, 0.5) + W.z_terms(n) + W.x_terms(n) + [(0.7, 0, 0), W.pauli(0.3, {0: "Y", 5: "X", 12: "Z"})]
+    tot, per = qs.expect(st, terms, per_term=True)
+    ref = sv.expect_terms(psi, n, terms)
+    tol = 1e-7 if dtype == "c64" else 1e-13
+    assert np.max(np.abs(per - ref)) < tol
+    assert abs(tot - ref.sum()) < tol * len(terms)
+    assert abs(qs.norm2(st) - metrics.norm2(psi)) < 1e-12
+    st2, psi2 = start(qs, n, dtype, 22)
+    ov = qs.overlap(st, st2)
+    assert abs(ov - np.vdot(psi, psi2)) < 1e-12
+    assert abs(qs.infidelity(st, st2) - metrics.infidelity(psi, psi2)) < 1e-12
+    assert qs.infidelity(st, st) < 1e-28
+
+
+def test_xxz_closed_forms_on_device(qs):
+    n = 20
+    terms = W.xxz_terms(n, 0.5)
+    assert abs(qs.expect(qs.State(n, "c128"), terms) - 0.5 * (n - 1)) < 1e-12
+    assert abs(qs.expect(qs.State(n, "c128", init="plus"), terms) - (n - 1)) < 1e-11
+    neel = int("01" * (n // 2), 2)
+    assert abs(qs.expect(qs.State(n, "c128").set_basis(neel), terms) + 0.5 * (n - 1)) < 1e-12
+
+
+def test_reductions_are_deterministic(qs):
+    n = 22
+    st, _ = start(qs, n, "c64", 2)
+    a = [qs.norm2(st) for _ in range(3)]
+    b = [qs.expect(st, W.xxz_terms(n, 0.5)) for _ in range(3)]
+    assert len(set(a)) == 1 and len(set(b)) == 1
+
+
+# ------------------------------------------------------------------ invariants
+def test_plan_then_inverse_returns_input(qs):
+    n = 15
+    stream = W.random_stream(n, 200, 13)
+    st, psi0 = start(qs, n, "c128", 13)
+    qs.apply(st, qs.Plan(n, stream))
+    qs.apply(st, qs.Plan(n, sv.inverse_stream(stream)))
+    assert metrics.infidelity(st.download(), psi0) < INF128
+
+
+def test_error_paths_do_not_touch_the_state(qs):
+    n = 6
+    st, psi0 = start(qs, n, "c64", 1)
+    with pytest.raises(qs.QsError):
+        qs.apply(st, qs.Plan(7, W.wht_stream(7)))
+    with pytest.raises(qs.QsError):
+        qs.apply_gates(st, [W.G("H", 0), W.G("CNOT", 2, 2)])
+    p = qs.Plan(n, [W.G("RX", 0, param=0)], n_params=1)
+    with pytest.raises(qs.QsError):
+        qs.apply(st, p)  # parameters not bound
+    assert np.array_equal(st.download(), psi0.astype(np.complex64))

@@ -1,0 +1,194 @@
+"""Planner semantics on the CPU: plans built through the C ABI, interpreted
+in numpy from their description, compared with the one-gate-at-a-time oracle.
+Permutation layers are compared bit-exactly on index-tag states."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import metrics, statevec as sv
+from tests.plan_interp import run_plan
+
+qs = pytest.importorskip("paper_2609_19147_amd")
+
+
+def plan_of(n, stream, n_params=0, params=None, **kw):
+    p = qs.Plan(n, stream, n_params=n_params, **kw)
+    if params is not None:
+        p.set_params(params)
+    return p
+
+
+def check_plan(n, stream, psi0=None, params=None, n_params=0, tol=1e-12, **kw):
+    p = plan_of(n, stream, n_params, params, **kw)
+    d = p.describe()
+    psi0 = W.gaussian_state(n, 17) if psi0 is None else psi0
+    got = run_plan(d, psi0, stream, params)
+    ref = sv.run(psi0, n, stream, params)
+    assert np.max(np.abs(got - ref)) < tol, d["layers"][:3]
+    return d
+
+
+def kinds(d):
+    return [L["kind"] for L in d["layers"]]
+
+
+@pytest.mark.parametrize("n", [4, 6, 9, 12])
+def test_qft_stream_fuses_to_tile_passes(n):
+    d = check_plan(n, W.qft_stream(n))
+    assert set(kinds(d)) == {"tile"}
+    ops = [op for L in d["layers"] for op in L["ops"]]
+    assert [op["kind"] for op in ops] == [2] * n          # one QFT stage op per qubit
+    assert [op["bit"] for op in ops] == list(range(n - 1, -1, -1))
+
+
+@pytest.mark.parametrize("n", [5, 13, 16])
+def test_qft_pass_structure_and_semantics(n):
+    d = check_plan(n, W.qft_stream(n), tol=1e-11)
+    assert len(d["layers"]) == (1 if n <= 13 else 2)
+
+
+def test_pass_counts_at_30_qubits():
+    # structure only (no state at this size): QFT and Walsh take 3 tile passes,
+    # a 200-gate random permutation block is one gather
+    for stream, want in ((W.qft_stream(30), ["tile"] * 3), (W.wht_stream(30), ["tile"] * 3),
+                         (W.random_perm_block(30, 200, 31), ["gf2"])):
+        assert kinds(qs.Plan(30, stream).describe()) == want
+    # the Walsh butterflies on high bits commute with the remaining (lower) QFT
+    # stages, so the composed circuit still needs only three tile passes
+    both = W.qft_stream(30) + W.wht_stream(30) + W.random_perm_block(30, 200, 31)
+    assert kinds(qs.Plan(30, both).describe()) == ["tile"] * 3 + ["gf2"]
+
+
+@pytest.mark.parametrize("n", [4, 7, 10])
+def test_walsh_layer(n):
+    d = check_plan(n, W.wht_stream(n))
+    assert set(kinds(d)) == {"tile"}
+    assert all(op["kind"] == 1 for L in d["layers"] for op in L["ops"])
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (8, 2), (11, 3)])
+def test_permutation_block_bit_exact(n, seed):
+    stream = W.random_perm_block(n, 60, seed)
+    d = qs.Plan(n, stream).describe()
+    assert kinds(d) == ["gf2"]
+    tag = W.index_tag_state(n)
+    assert np.array_equal(run_plan(d, tag, stream), sv.run(tag, n, stream))
+
+
+def test_ghz_chain_is_one_gather():
+    n = 10
+    st = W.ghz_stream(n)
+    d = check_plan(n, st, psi0=sv.basis(n, 0))
+    assert kinds(d) == ["tile", "gf2"]
+
+
+def test_tfim_strang_fuses_diagonals_into_passes():
+    n = 10
+    st = W.tfim_strang_stream(n, 1.0, 0.8, 0.05, 6)
+    d = check_plan(n, st, psi0=sv.basis(n, 0), tol=1e-12)
+    assert set(kinds(d)) == {"tile"}
+    # n <= tile bits: the evolution needs one pass per four fused diagonal layers
+    assert len(d["layers"]) == 2
+    d25 = qs.Plan(25, W.tfim_strang_stream(25, 1.0, 0.8, 0.05, 40)).describe()
+    assert set(kinds(d25)) == {"tile"}
+    # 25 qubits need three bit groups: the first window takes three passes and
+    # every later step two (the diagonal rides inside a pass)
+    assert len(d25["layers"]) <= 2 * 40 + 3
+
+
+@pytest.mark.parametrize("n,seed", [(4, 0), (5, 1), (6, 2), (7, 3), (8, 4), (9, 5)])
+def test_random_mixed_streams(n, seed):
+    st = W.random_stream(n, 120, seed)
+    check_plan(n, st, tol=1e-12)
+
+
+def test_random_mixed_streams_small_tiles():
+    n = 9
+    st = W.random_stream(n, 150, 7)
+    # 5-bit tiles force several groups and high tiles at n = 9
+    check_plan(n, st, tol=1e-12, max_tile_bits=5)
+    check_plan(10, W.qft_stream(10) + W.tfim_strang_stream(10, 1, 0.8, 0.1, 3), tol=1e-12, max_tile_bits=6)
+
+
+def test_xx_yy_runs():
+    n = 7
+    st = ([W.G("H", q) for q in range(n)] + [W.G("RXX", q, q + 1, theta=0.3 + 0.1 * q) for q in range(n - 1)]
+          + [W.G("RYY", q, (q + 2) % n, theta=-0.7) for q in range(n)] + [W.G("RX", 2, theta=0.2)])
+    check_plan(n, st, tol=1e-12)
+
+
+def test_parametrised_qaoa_and_hea():
+    rng = np.random.default_rng(3)
+    inst = W.qaoa_instances(1, 5, depth=3, n_choices=(8,))[0]
+    st = W.qaoa_stream(inst, param_offset=0)
+    params = rng.uniform(0, math.pi, size=6)
+    check_plan(8, st, psi0=sv.basis(8, 0), params=params, n_params=6)
+    st = W.hea_stream(6, 3)
+    params = W.hea_params(6, 3, 1)
+    check_plan(6, st, psi0=sv.basis(6, 0), params=params, n_params=len(params))
+
+
+def test_identity_windows_vanish_but_small_rotations_survive():
+    n = 5
+    d = qs.Plan(n, [W.G("H", 1), W.G("H", 1), W.G("X", 2), W.G("X", 2)]).describe()
+    assert d["layers"] == []
+    # RZ(1e-6) is a real rotation: it must not be dropped as identity
+    st = [W.G("RZ", 3, theta=1e-6)]
+    d = check_plan(n, st, tol=1e-15)
+    assert d["layers"] != []
+    psi0 = W.gaussian_state(n, 1)
+    got = run_plan(d, psi0, st)
+    assert np.max(np.abs(got - psi0)) > 1e-8
+
+
+def test_window_collapsing_to_x_becomes_a_bit_flip():
+    n = 6
+    st = [W.G("H", 2), W.G("H", 2), W.G("X", 2), W.G("Y", 4), W.G("Z", 4)]  # Z Y = -i X... not X
+    d = qs.Plan(n, st[:3]).describe()
+    assert kinds(d) == ["gf2"] and d["layers"][0]["cprime"] == 1 << (n - 1 - 2)
+    check_plan(n, st, tol=1e-14)
+
+
+def test_multi_controlled_and_dense_gates():
+    n = 6
+    rng = np.random.default_rng(2)
+    U = W.random_unitary(8, rng)
+    st = [W.G("H", q) for q in range(n)] + [W.G("MCZ", 0, 2, 5), W.G("MCP", 1, 3, 4, 5, theta=0.4),
+                                              W.G("UNITARY", 4, 0, 2, mat=U), W.G("CU", 3, 1, mat=W.random_unitary(2, rng))]
+    check_plan(n, st, tol=1e-12)
+
+
+def test_grover_plan():
+    n = 8
+    st = W.grover_stream(n, 0b10110011, 3)
+    check_plan(n, st, psi0=sv.basis(n, 0), tol=1e-12)
+
+
+def test_plain_mode_is_one_layer_per_gate():
+    n = 6
+    st = W.random_stream(n, 40, 4)
+    d = check_plan(n, st, mode="plain")
+    assert kinds(d) == ["plain"] * len([g for g in st])
+
+
+@pytest.mark.parametrize("bad", [
+    [W.G("CNOT", 1, 1)],
+    [W.G("H", 7)],
+    [W.G("RX", -1, theta=0.1)],
+    [W.G("RY", 0, param=3)],
+    [W.G("H", 0, param=0)],
+])
+def test_invalid_streams_are_rejected(bad):
+    with pytest.raises(qs.QsError) as e:
+        qs.Plan(5, bad, n_params=1)
+    assert e.value.code == -1
+
+
+def test_params_must_be_bound_and_sized():
+    p = qs.Plan(3, [W.G("RX", 0, param=0)], n_params=1)
+    with pytest.raises(qs.QsError):
+        p.set_params([0.1, 0.2])
+    with pytest.raises(qs.QsError):
+        p.set_params([float("nan")])
