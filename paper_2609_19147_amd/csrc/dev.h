@@ -19,6 +19,47 @@ struct alignas(4 * sizeof(R)) cplx2 {
   cplx<R> a, b;
 };
 
+// Streaming (non-temporal) global accesses: state passes touch every byte
+// once, so they should not displace reusable lines from the caches.
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ cplx2<float> ld_nt(const cplx2<float>* p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+  return {{v.x, v.y}, {v.z, v.w}};
+}
+__device__ __forceinline__ cplx2<double> ld_nt(const cplx2<double>* p) {
+  const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p) + 1);
+  return {{a.x, a.y}, {b.x, b.y}};
+}
+__device__ __forceinline__ void st_nt(cplx2<float>* p, const cplx2<float>& v) {
+  const nt_f4 w = {v.a.re, v.a.im, v.b.re, v.b.im};
+  __builtin_nontemporal_store(w, reinterpret_cast<nt_f4*>(p));
+}
+__device__ __forceinline__ void st_nt(cplx2<double>* p, const cplx2<double>& v) {
+  const nt_d2 a = {v.a.re, v.a.im}, b = {v.b.re, v.b.im};
+  __builtin_nontemporal_store(a, reinterpret_cast<nt_d2*>(p));
+  __builtin_nontemporal_store(b, reinterpret_cast<nt_d2*>(p) + 1);
+}
+__device__ __forceinline__ cplx<float> ld_nt(const cplx<float>* p) {
+  const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cplx<double> ld_nt(const cplx<double>* p) {
+  const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void st_nt(cplx<float>* p, const cplx<float>& v) {
+  const nt_f2 w = {v.re, v.im};
+  __builtin_nontemporal_store(w, reinterpret_cast<nt_f2*>(p));
+}
+__device__ __forceinline__ void st_nt(cplx<double>* p, const cplx<double>& v) {
+  const nt_d2 w = {v.re, v.im};
+  __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p));
+}
+
 template <class R>
 __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};

@@ -33,6 +33,23 @@ __global__ void convert_kernel(cplx<Rd>* dst, const cplx<Rs>* src, uint64_t N) {
     dst[i] = {(Rd)src[i].re, (Rd)src[i].im};
 }
 
+// Same-dtype copy: 16-byte accesses, four in flight per thread, one pass.
+template <class R>
+__global__ void __launch_bounds__(kThreads) copy_kernel(cplx2<R>* __restrict__ dst, const cplx2<R>* __restrict__ src,
+                                                        uint64_t npairs) {
+  const uint64_t step = (uint64_t)gridDim.x * kThreads;
+  uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x;
+  for (; i + 3 * step < npairs; i += 4 * step) {
+    cplx2<R> v0 = ld_nt(src + i), v1 = ld_nt(src + i + step), v2 = ld_nt(src + i + 2 * step),
+             v3 = ld_nt(src + i + 3 * step);
+    st_nt(dst + i, v0);
+    st_nt(dst + i + step, v1);
+    st_nt(dst + i + 2 * step, v2);
+    st_nt(dst + i + 3 * step, v3);
+  }
+  for (; i < npairs; i += step) dst[i] = src[i];
+}
+
 template <class R>
 __global__ void gather_kernel(const cplx<R>* psi, const uint64_t* idx, cplx<R>* out, uint64_t count) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
@@ -44,11 +61,11 @@ __global__ void gather_kernel(const cplx<R>* psi, const uint64_t* idx, cplx<R>* 
 template <class R>
 __global__ void __launch_bounds__(kThreads) diag_kernel(cplx<R>* psi, uint64_t npairs, DiagDev D) {
   for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < npairs; t += (uint64_t)gridDim.x * kThreads) {
-    cplx2<R> v = reinterpret_cast<cplx2<R>*>(psi)[t];
+    cplx2<R> v = ld_nt(reinterpret_cast<cplx2<R>*>(psi) + t);
     const uint32_t i = (uint32_t)(2 * t);
     v.a = cmul(v.a, diag_phase<R>(i, D));
     v.b = cmul(v.b, diag_phase<R>(i + 1, D));
-    reinterpret_cast<cplx2<R>*>(psi)[t] = v;
+    st_nt(reinterpret_cast<cplx2<R>*>(psi) + t, v);
   }
 }
 
@@ -80,6 +97,32 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
   __syncthreads();
   const uint32_t D = 1u << A.d;
   const uint32_t lomask = nlo - 1u;
+  if (D == kThreads * 4) {
+    // full tiles: four independent loads in flight per thread, then four stores
+    cplx<R> v[4];
+    uint32_t t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t s = threadIdx.x + kThreads * k;
+      const uint32_t slo = s & lomask, shi = s >> A.c;
+      v[k] = ld_nt(in + (x0 ^ slo ^ au[shi]));
+      t[k] = tl[slo] ^ th[shi];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) T[t[k]] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t tt = threadIdx.x + kThreads * k;
+      v[k] = T[tt];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t tt = threadIdx.x + kThreads * k;
+      st_nt(out + (y0 ^ (tt & lomask) ^ vh[tt >> A.c]), v[k]);
+    }
+    return;
+  }
   for (uint32_t s = threadIdx.x; s < D; s += kThreads) {
     const uint32_t slo = s & lomask, shi = s >> A.c;
     const uint32_t x = x0 ^ slo ^ au[shi];
@@ -106,6 +149,12 @@ void launch_fill_uniform(cplx<R>* psi, uint64_t N, double v, hipStream_t s) {
 }
 template <class Rd, class Rs>
 void launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, uint64_t N, hipStream_t s) {
+  if (sizeof(Rd) == sizeof(Rs) && N >= 2) {
+    const uint64_t npairs = N / 2;
+    QS_LAUNCH("copy", s, copy_kernel<Rd>, dim3(grid_for(npairs, kThreads * 4)), dim3(kThreads), 0, s,
+              reinterpret_cast<cplx2<Rd>*>(dst), reinterpret_cast<const cplx2<Rd>*>(src), npairs);
+    return;
+  }
   QS_LAUNCH("convert", s, (convert_kernel<Rd, Rs>), dim3(grid_for(N, kThreads * 4)), dim3(kThreads), 0, s, dst, src,
             N);
 }

@@ -56,6 +56,7 @@ struct TileKArgs {
   uint32_t L, a, h, m;
   uint32_t n_rounds;
   uint32_t n;
+  double scale;  // 2^(-k/2) for the pass's k unscaled butterflies
 };
 template <class R> void launch_tile(const TileKArgs<R>& A, hipStream_t s);
 

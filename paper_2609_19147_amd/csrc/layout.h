@@ -27,6 +27,8 @@ enum TileOpKind : int32_t {
   OP_H = 1,     // Hadamard butterfly, scaled by 1/sqrt(2)
   OP_QFT = 2,   // QFT stage on bit p: H butterfly, then a1' *= exp(i pi (i mod 2^p) / 2^p)
                 //   coef: 2^s intra-round twiddles (s = register bit of the op)
+                // H and QFT butterflies are applied unscaled (a0 + a1, a0 - a1); the
+                // pass multiplies by its accumulated 2^(-k/2) once, at the store.
   OP_DIAG = 3,  // diag(d0, d1) (coef: d0, d1)
   OP_QFT_INV = 4,  // inverse of OP_QFT: a1 *= conj(twiddle), then H butterfly
   OP_GRAD = 5,     // (adjoint only) accumulate 2 Re <lambda|K|phi>, K = coef (2x2)
@@ -38,14 +40,41 @@ struct TileOp {
   int32_t sbit;    // state bit position p
   int32_t coef;    // offset into the pass's coefficient array (complex entries)
   int32_t slot;    // OP_GRAD: gradient accumulator index; else -1
-  int32_t pad[3];
+  int32_t square;  // OP_QFT: 1 = the group twiddle is the square of the previous op's
+  int32_t pad[2];
 };
+
+// LDS layout of a tile: position j is stored at element j + 2 (j >> 5) (two
+// pad elements every 32), which keeps pairs 16-byte aligned, spreads the
+// strided round accesses over the banks, and is additive over disjoint bits:
+// lds(g | o) = lds(g) + lds(o).
+// Round patterns with straight-line code in the kernel (ops of other rounds
+// run through a generic per-op loop).
+enum TileRoundType : int32_t {
+  RT_GENERIC = 0,  // planner-internal only: never reaches a kernel
+  RT_QFT4 = 1,     // QFT stages on register bits 3, 2, 1, 0 (the ops, in that order)
+  RT_QFT4_H4 = 2,  // RT_QFT4 followed by H on register bits 3, 2, 1, 0
+  RT_H4 = 3,       // H on every register bit
+  RT_MAT4 = 4,     // one single-qubit op per register bit (any kinds), as 2x2
+                   // matrices in coef[coef4 + 4 r ...] for register bit r
+                   // (identity where a bit has no op; H unscaled)
+  RT_MAT4_RX = 5,  // RT_MAT4 where every matrix is [[a, -ib], [-ib, a]] (a, b real):
+                   //   coef[coef4 + r] = (a, b)
+  RT_MAT4_RY = 6,  // RT_MAT4 where every matrix is [[a, -b], [b, a]] (a, b real)
+  RT_QFT1 = 7,     // one QFT (or inverse QFT) stage, on any register bit
+};
+// The planner splits a round matching none of the patterns into a sequence of
+// rounds over the same register bits (RT_MAT4 groups and RT_QFT1 stages).
 
 struct TileRound {
   int32_t tbit[kRoundBits];  // tile-bit positions of register bits 0..RB-1 (ascending)
   int32_t op_begin, op_end;  // ops [op_begin, op_end) of the pass
   int32_t diag;              // -1 or a diagonal slot applied before the ops
   int32_t diag_conj;         // 1: multiply by the conjugate phase (inverse)
+  int32_t type;              // TileRoundType
+  int32_t coef4;             // RT_MAT4*: coefficient offset of the four matrices
+  int32_t pad[2];
+  uint32_t loff[1 << kRoundBits];  // LDS element offset of register element j
 };
 
 // ---- diagonal layers ----------------------------------------------------------

@@ -848,6 +848,46 @@ int tile_pos(const TilePassIR& T, int sb) {
 }
 int tile_state_bit(const TilePassIR& T, int tb) { return tb < T.L ? tb : T.a + (tb - T.L); }
 
+// Conflict test between two tile ops (same rule as the pass scheduler): an op
+// writes its bit; a QFT stage on bit p also reads every bit below p.
+bool ops_conflict(const OpIR& a, const OpIR& b) {
+  uint32_t Wa = 1u << a.bit, Wb = 1u << b.bit;
+  uint32_t Ra = a.kind == OP_QFT && a.bit ? (1u << a.bit) - 1 : 0;
+  uint32_t Rb = b.kind == OP_QFT && b.bit ? (1u << b.bit) - 1 : 0;
+  return (Wa & (Wb | Rb)) || (Wb & Ra);
+}
+
+uint32_t lds_off(uint32_t pos) { return pos + ((pos >> 5) << 1); }
+
+// Pattern of a round's op list (see TileRoundType).  RT_MAT4 may be refined to
+// the RX / RY forms when the plan's numbers are bound.
+int32_t classify_round(const PlanIR& P, const TilePassIR& T, const TileRound& r) {
+  (void)P;
+  const int n = r.op_end - r.op_begin;
+  auto op = [&](int k) -> const TileOp& { return T.ops[r.op_begin + k]; };
+  auto is = [&](int k, int kind, int rbit) { return op(k).kind == kind && op(k).rbit == rbit; };
+  if (n == 4 && is(0, OP_QFT, 3) && is(1, OP_QFT, 2) && is(2, OP_QFT, 1) && is(3, OP_QFT, 0)) return RT_QFT4;
+  if (n == 8 && is(0, OP_QFT, 3) && is(1, OP_QFT, 2) && is(2, OP_QFT, 1) && is(3, OP_QFT, 0)) {
+    uint32_t hb = 0;
+    for (int k = 4; k < 8; ++k)
+      if (op(k).kind == OP_H) hb |= 1u << op(k).rbit;
+    if (hb == 15u) return RT_QFT4_H4;
+  }
+  if (n == 1 && (op(0).kind == OP_QFT || op(0).kind == OP_QFT_INV)) return RT_QFT1;
+  if (n > 4) return RT_GENERIC;
+  uint32_t seen = 0;
+  bool all_h = true;
+  for (int k = 0; k < n; ++k) {
+    const TileOp& o = op(k);
+    if (o.kind != OP_MAT && o.kind != OP_DIAG && o.kind != OP_H) return RT_GENERIC;
+    if ((seen >> o.rbit) & 1) return RT_GENERIC;
+    seen |= 1u << o.rbit;
+    all_h = all_h && o.kind == OP_H;
+  }
+  if (all_h && n == 4) return RT_H4;
+  return RT_MAT4;
+}
+
 void finalize_pass(const PlanIR& P, TilePassIR& T) {
   const int RB = kRoundBits;
   int m = T.L + T.h;
@@ -856,19 +896,25 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
   T.op_src.clear();
   T.diag_slots.clear();
   T.n_coef = 0;
-  std::vector<int> cur_bits;
-  std::vector<int> cur_ops;  // OpIR indices
+  T.n_butterfly = 0;
   int pending_diag = -1;
-  auto close = [&](bool force) {
-    if (cur_ops.empty() && pending_diag < 0 && !force) return;
+  auto emit_round = [&](std::vector<int> bits, const std::vector<int>& ops) {
     TileRound r;
-    std::vector<int> bits = cur_bits;
+    std::memset(&r, 0, sizeof r);
     for (int tb = 0; (int)bits.size() < RB && tb < m; ++tb)
       if (std::find(bits.begin(), bits.end(), tb) == bits.end()) bits.push_back(tb);
     std::sort(bits.begin(), bits.end());
     for (int k = 0; k < RB; ++k) r.tbit[k] = bits[k];
+    for (int j = 0; j < (1 << RB); ++j) {
+      uint32_t o = 0;
+      for (int k = 0; k < RB; ++k)
+        if ((j >> k) & 1) o |= 1u << bits[k];
+      r.loff[j] = lds_off(o);
+    }
     r.op_begin = (int32_t)T.ops.size();
-    for (int oi : cur_ops) {
+    int prev_qft_bit = -1;
+    bool prev_fresh = false;
+    for (int oi : ops) {
       const OpIR& o = P.ops[oi];
       TileOp op;
       std::memset(&op, 0, sizeof op);
@@ -881,32 +927,109 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
       if (o.kind == OP_MAT) T.n_coef += 4;
       else if (o.kind == OP_DIAG) T.n_coef += 2;
       else if (o.kind == OP_QFT) T.n_coef += 1 << op.rbit;
+      if (o.kind == OP_QFT) {
+        // exp(i pi low_p / 2^p) = (exp(i pi low_{p+1} / 2^{p+1}))^2 when bit p is a
+        // round bit (zero in the group base); square at most once in a row
+        op.square = (prev_qft_bit == o.bit + 1 && prev_fresh) ? 1 : 0;
+        prev_fresh = !op.square;
+        prev_qft_bit = o.bit;
+      }
+      if (o.kind == OP_H || o.kind == OP_QFT) T.n_butterfly += 1;
       T.ops.push_back(op);
       T.op_src.push_back(oi);
     }
     r.op_end = (int32_t)T.ops.size();
     r.diag = pending_diag;
     r.diag_conj = 0;
-    T.rounds.push_back(r);
-    cur_bits.clear();
-    cur_ops.clear();
+    r.type = classify_round(P, T, r);
     pending_diag = -1;
+    if (r.type != RT_GENERIC) {
+      if (r.type == RT_MAT4) {
+        r.coef4 = T.n_coef;
+        T.n_coef += 16;
+      }
+      T.rounds.push_back(r);
+      return;
+    }
+    // split: consecutive single-qubit ops on distinct register bits form one
+    // RT_MAT4 round; every QFT stage becomes an RT_QFT1 round
+    int k = r.op_begin;
+    bool first = true;
+    while (k < r.op_end) {
+      TileRound q = r;
+      q.diag = first ? r.diag : -1;
+      first = false;
+      q.op_begin = k;
+      if (T.ops[k].kind == OP_QFT || T.ops[k].kind == OP_QFT_INV) {
+        q.op_end = k + 1;
+        q.type = RT_QFT1;
+        q.coef4 = -1;
+        T.ops[k].square = 0;  // the stage it would square now sits in another round
+      } else {
+        uint32_t seen = 0;
+        int e = k;
+        while (e < r.op_end && T.ops[e].kind != OP_QFT && T.ops[e].kind != OP_QFT_INV &&
+               !((seen >> T.ops[e].rbit) & 1)) {
+          seen |= 1u << T.ops[e].rbit;
+          ++e;
+        }
+        q.op_end = e;
+        q.type = RT_MAT4;
+        q.coef4 = T.n_coef;
+        T.n_coef += 16;
+      }
+      k = q.op_end;
+      T.rounds.push_back(q);
+    }
   };
+  // Ops between two diagonal items are packed into rounds greedily: each
+  // round takes, in stream order, every op whose conflicting predecessors are
+  // done and whose bit fits in the round's four register bits.
+  auto pack = [&](const std::vector<int>& seg_ops) {
+    size_t N = seg_ops.size();
+    std::vector<char> done(N, 0);
+    size_t left = N;
+    while (left) {
+      std::vector<int> bits, ops;
+      bool progress = true;
+      while (progress) {
+        progress = false;
+        for (size_t j = 0; j < N; ++j) {
+          if (done[j]) continue;
+          const OpIR& o = P.ops[seg_ops[j]];
+          bool ready = true;
+          for (size_t i = 0; i < j && ready; ++i)
+            if (!done[i] && ops_conflict(P.ops[seg_ops[i]], o)) ready = false;
+          if (!ready) continue;
+          int tb = tile_pos(T, o.bit);
+          if (tb < 0) fail(QS_EINVAL, "internal: op outside its tile");
+          bool have = std::find(bits.begin(), bits.end(), tb) != bits.end();
+          if (!have && (int)bits.size() == RB) continue;
+          if (!have) bits.push_back(tb);
+          ops.push_back(seg_ops[j]);
+          done[j] = 1;
+          --left;
+          progress = true;
+        }
+      }
+      emit_round(bits, ops);
+    }
+  };
+  std::vector<int> seg_ops;
   for (auto& it : T.items) {
     if (it.type == 1) {
-      close(false);
+      if (!seg_ops.empty()) pack(seg_ops);
+      seg_ops.clear();
+      if (pending_diag >= 0) emit_round({}, {});  // two diagonals in a row
       pending_diag = (int)T.diag_slots.size();
       T.diag_slots.push_back(it.index);
       continue;
     }
-    int tb = tile_pos(T, P.ops[it.index].bit);
-    if (tb < 0) fail(QS_EINVAL, "internal: op outside its tile");
-    bool have = std::find(cur_bits.begin(), cur_bits.end(), tb) != cur_bits.end();
-    if (!have && (int)cur_bits.size() == RB) close(false);
-    if (!have) cur_bits.push_back(tb);
-    cur_ops.push_back(it.index);
+    seg_ops.push_back(it.index);
   }
-  close(false);
+  if (!seg_ops.empty()) pack(seg_ops);
+  if (pending_diag >= 0) emit_round({}, {});
+  T.scale = std::pow(0.5, 0.5 * T.n_butterfly);
 }
 
 }  // namespace
@@ -947,6 +1070,21 @@ std::vector<cd> op_matrix(const PlanIR& P, const OpIR& op, const std::vector<dou
 
 std::vector<cd> pass_coefficients(const PlanIR& P, const TilePassIR& T, const std::vector<double>& params) {
   std::vector<cd> coef((size_t)T.n_coef);
+  for (const TileRound& r : T.rounds) {
+    if (r.type != RT_MAT4) continue;
+    for (int b = 0; b < 4; ++b) {
+      coef[r.coef4 + 4 * b] = 1.0;
+      coef[r.coef4 + 4 * b + 3] = 1.0;
+    }
+    for (int k = r.op_begin; k < r.op_end; ++k) {
+      const TileOp& op = T.ops[k];
+      std::vector<cd> U;
+      if (op.kind == OP_H) U = {1.0, 1.0, 1.0, -1.0};  // unscaled butterfly
+      else U = op_matrix(P, P.ops[T.op_src[k]], params);
+      if (op.kind == OP_DIAG) U = {U[0], 0.0, 0.0, U[3]};
+      for (int e = 0; e < 4; ++e) coef[r.coef4 + 4 * op.rbit + e] = U[e];
+    }
+  }
   for (size_t k = 0; k < T.ops.size(); ++k) {
     const TileOp& op = T.ops[k];
     if (T.op_src[k] < 0) continue;
@@ -969,6 +1107,45 @@ std::vector<cd> pass_coefficients(const PlanIR& P, const TilePassIR& T, const st
         for (int t = 0; t < s; ++t)
           if ((kk >> t) & 1) frac += std::ldexp(1.0, tile_state_bit(T, R->tbit[t]) - p);
         coef[op.coef + kk] = std::polar(1.0, kPi * frac);
+      }
+    }
+  }
+  return coef;
+}
+
+std::vector<TileRound> pass_rounds(const PlanIR& P, const TilePassIR& T, const std::vector<cd>& coef) {
+  (void)P;
+  std::vector<TileRound> rounds = T.rounds;
+  for (TileRound& r : rounds) {
+    if (r.type != RT_MAT4) continue;
+    bool rx = true, ry = true;
+    for (int b = 0; b < 4; ++b) {
+      const cd* U = &coef[r.coef4 + 4 * b];
+      rx = rx && U[0] == U[3] && U[0].imag() == 0.0 && U[1] == U[2] && U[1].real() == 0.0;
+      ry = ry && U[0] == U[3] && U[0].imag() == 0.0 && U[1] == -U[2] && U[1].imag() == 0.0 && U[2].imag() == 0.0;
+    }
+    if (rx) r.type = RT_MAT4_RX;
+    else if (ry) r.type = RT_MAT4_RY;
+  }
+  return rounds;
+}
+
+// Device coefficient array: RX / RY rounds store (a, b) per register bit at
+// coef4 + r instead of the full matrices.
+std::vector<cd> pass_coefficients_device(const PlanIR& P, const TilePassIR& T, const std::vector<double>& params,
+                                         std::vector<TileRound>& rounds) {
+  std::vector<cd> coef = pass_coefficients(P, T, params);
+  rounds = pass_rounds(P, T, coef);
+  for (const TileRound& r : rounds) {
+    if (r.type == RT_MAT4_RX) {
+      for (int b = 0; b < 4; ++b) {
+        const cd* U = &coef[r.coef4 + 4 * b];
+        coef[r.coef4 + b] = cd(U[0].real(), -U[1].imag());
+      }
+    } else if (r.type == RT_MAT4_RY) {
+      for (int b = 0; b < 4; ++b) {
+        const cd* U = &coef[r.coef4 + 4 * b];
+        coef[r.coef4 + b] = cd(U[0].real(), U[2].real());
       }
     }
   }
@@ -1051,7 +1228,8 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
         auto& R = T.rounds[r];
         if (r) o << ",";
         o << "{\"tbits\":[" << R.tbit[0] << "," << R.tbit[1] << "," << R.tbit[2] << "," << R.tbit[3]
-          << "],\"diag\":" << R.diag << ",\"ops\":[" << R.op_begin << "," << R.op_end << "]}";
+          << "],\"diag\":" << R.diag << ",\"type\":" << R.type << ",\"ops\":[" << R.op_begin << "," << R.op_end
+          << "]}";
       }
       o << "],\"ops\":[";
       std::vector<cd> coef;
@@ -1059,7 +1237,8 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
       for (size_t k = 0; k < T.ops.size(); ++k) {
         auto& op = T.ops[k];
         if (k) o << ",";
-        o << "{\"kind\":" << op.kind << ",\"bit\":" << op.sbit << ",\"rbit\":" << op.rbit;
+        o << "{\"kind\":" << op.kind << ",\"bit\":" << op.sbit << ",\"rbit\":" << op.rbit
+          << ",\"square\":" << op.square;
         if (bound) {
           int nc = op.kind == OP_MAT ? 4 : op.kind == OP_DIAG ? 2 : op.kind == OP_QFT ? (1 << op.rbit) : 0;
           o << ",\"coef\":[";

@@ -96,6 +96,8 @@ struct TilePassIR {
   std::vector<int32_t> op_src;   // OpIR index per device op (or -1 for QFT-only ops)
   std::vector<int32_t> diag_slots;  // DiagIR index per slot
   int32_t n_coef = 0;
+  int32_t n_butterfly = 0;  // unscaled H / QFT butterflies in the pass
+  double scale = 1.0;       // 2^(-n_butterfly/2), applied at the store
 };
 
 struct Gf2IR {
@@ -145,6 +147,9 @@ struct DiagNumeric {
 };
 DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj = false);
 std::vector<cd> pass_coefficients(const PlanIR& p, const TilePassIR& t, const std::vector<double>& params);
+// Device form of a pass's rounds and coefficients (RX / RY refinements applied).
+std::vector<cd> pass_coefficients_device(const PlanIR& p, const TilePassIR& t, const std::vector<double>& params,
+                                         std::vector<TileRound>& rounds);
 cd op_matrix_entry(const PlanIR& p, const OpIR& op, const std::vector<double>& params, int r, int c);
 std::vector<cd> op_matrix(const PlanIR& p, const OpIR& op, const std::vector<double>& params);
 Gf2Args gf2_args(int n, const Gf2IR& g, int c_bits);

@@ -47,9 +47,11 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
   d.pass_coef.assign(P.passes.size(), 0);
   for (size_t i = 0; i < P.passes.size(); ++i) {
     const TilePassIR& T = P.passes[i];
-    d.pass_rounds[i] = b.put(T.rounds);
+    std::vector<TileRound> rounds;
+    std::vector<cd> coef = pass_coefficients_device(P, T, p.params, rounds);
+    d.pass_rounds[i] = b.put(rounds);
     d.pass_ops[i] = b.put(T.ops);
-    d.pass_coef[i] = b.put(cast<R>(pass_coefficients(P, T, p.params)));
+    d.pass_coef[i] = b.put(cast<R>(coef));
   }
   b.put(std::vector<double>(2, 0.0));  // never zero bytes
 }
@@ -135,6 +137,7 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
         A.m = T.L + T.h;
         A.n_rounds = (uint32_t)T.rounds.size();
         A.n = s.n;
+        A.scale = T.scale;
         launch_tile<R>(A, s.stream);
         break;
       }

@@ -192,3 +192,22 @@ def test_params_must_be_bound_and_sized():
         p.set_params([0.1, 0.2])
     with pytest.raises(qs.QsError):
         p.set_params([float("nan")])
+
+
+@pytest.mark.parametrize("tile_bits", [5, 6, 9, 13])
+def test_twiddle_squaring_stays_inside_a_round(tile_bits):
+    # a QFT stage may reuse the squared twiddle of the stage one bit above
+    # only when that stage is computed freshly in the same round
+    n = 18
+    st = W.qft_stream(n) + W.wht_stream(n) + W.tfim_strang_stream(n, 1, 0.8, 0.05, 1, h_layer=False)
+    d = qs.Plan(n, st, max_tile_bits=tile_bits).describe()
+    for L in d["layers"]:
+        if L["kind"] != "tile":
+            continue
+        for R in L["rounds"]:
+            ops = L["ops"][R["ops"][0]:R["ops"][1]]
+            for k, op in enumerate(ops):
+                if op["square"]:
+                    prev = [o for o in ops[:k] if o["kind"] == 2]
+                    assert R["type"] in (1, 2), R
+                    assert prev and prev[-1]["bit"] == op["bit"] + 1 and not prev[-1]["square"]

@@ -361,3 +361,20 @@ def random_unitary(dim: int, rng: np.random.Generator) -> np.ndarray:
     q, r = np.linalg.qr(z)
     d = np.diagonal(r)
     return q * (d / np.abs(d))
+
+
+def gaussian_state_torch(n: int, seed: int, dtype: str = "c64", out=None):
+    """Seeded i.i.d. complex Gaussian state generated on the GPU with torch's
+    Philox generator, normalised in FP64 (for sizes where a host state would be
+    impractical, e.g. 30 qubits).  Writes into ``out`` when given."""
+    import torch
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    psi = out if out is not None else torch.empty(1 << n, dtype=tdt, device="cuda")
+    chunk = 1 << 26
+    for s in range(0, 1 << n, chunk):
+        psi[s:s + chunk] = torch.randn(min(chunk, (1 << n) - s), dtype=tdt, device="cuda", generator=g)
+    nrm = torch.linalg.vector_norm(psi.view(torch.float32 if dtype == "c64" else torch.float64), dtype=torch.float64)
+    psi /= nrm.to(psi.real.dtype)
+    return psi
