@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
                                                        Gf2Args A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
-  __shared__ uint32_t tl[1 << kGf2MaxC], th[1 << kGf2MaxC], au[1 << kGf2MaxC], vh[1 << kGf2MaxC];
+  __shared__ uint32_t tl[1 << kGf2MaxC], th[1 << kGf2MaxC], au[1 << kGf2MaxC], vh[1 << kGf2MaxC],
+      hx[1 << kGf2MaxC];
   const uint32_t nlo = 1u << A.c;
   const uint32_t nhi = 1u << (A.d - A.c);
   for (uint32_t k = threadIdx.x; k < nlo; k += kThreads) tl[k] = A.t_lo[k];
@@ -86,6 +87,7 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
     th[k] = A.t_hi[k];
     au[k] = A.au_hi[k];
     vh[k] = A.v_hi[k];
+    hx[k] = A.hx[k];
   }
   // coset representative and its source
   const uint32_t coset = blockIdx.x;
@@ -106,7 +108,8 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
       const uint32_t s = threadIdx.x + kThreads * k;
       const uint32_t slo = s & lomask, shi = s >> A.c;
       v[k] = ld_nt(in + (x0 ^ slo ^ au[shi]));
-      t[k] = tl[slo] ^ th[shi];
+      const uint32_t tk = tl[slo] ^ th[shi];
+      t[k] = tk ^ hx[tk >> A.c];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) T[t[k]] = v[k];
@@ -114,7 +117,7 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t tt = threadIdx.x + kThreads * k;
-      v[k] = T[tt];
+      v[k] = T[tt ^ hx[tt >> A.c]];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -126,12 +129,13 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
   for (uint32_t s = threadIdx.x; s < D; s += kThreads) {
     const uint32_t slo = s & lomask, shi = s >> A.c;
     const uint32_t x = x0 ^ slo ^ au[shi];
-    T[tl[slo] ^ th[shi]] = in[x];
+    const uint32_t tk = tl[slo] ^ th[shi];
+    T[tk ^ hx[tk >> A.c]] = in[x];
   }
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < D; t += kThreads) {
     const uint32_t y = y0 ^ (t & lomask) ^ vh[t >> A.c];
-    out[y] = T[t];
+    out[y] = T[t ^ hx[t >> A.c]];
   }
 }
 

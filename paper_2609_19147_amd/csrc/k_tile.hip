@@ -246,6 +246,46 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
           op_ry<3>(a, c[3]);
           break;
         }
+        case RT_OP1: {
+          const TileOp op = A.ops[R_.op_begin];
+          const cplx<R>* c = A.coef + op.coef;
+          if (op.kind == OP_H) {
+            switch (op.rbit) {
+              case 0: op_h<0>(a); break;
+              case 1: op_h<1>(a); break;
+              case 2: op_h<2>(a); break;
+              default: op_h<3>(a); break;
+            }
+          } else if (op.kind == OP_DIAG) {
+            switch (op.rbit) {
+              case 0: op_diag<0>(a, c); break;
+              case 1: op_diag<1>(a, c); break;
+              case 2: op_diag<2>(a, c); break;
+              default: op_diag<3>(a, c); break;
+            }
+          } else {
+            switch (op.rbit) {
+              case 0: op_mat<0>(a, c); break;
+              case 1: op_mat<1>(a, c); break;
+              case 2: op_mat<2>(a, c); break;
+              default: op_mat<3>(a, c); break;
+            }
+          }
+          break;
+        }
+        case RT_QH1: {
+          const TileOp op = A.ops[R_.op_begin];
+          const int p = op.sbit;
+          const cplx<R> w = cispi<R>(p == 0 ? 0u : (gglobal & ((1u << p) - 1u)), p);
+          const cplx<R>* E = A.coef + op.coef;
+          switch (op.rbit) {
+            case 0: op_qft<0>(a, w, E, false); op_h<0>(a); break;
+            case 1: op_qft<1>(a, w, E, false); op_h<1>(a); break;
+            case 2: op_qft<2>(a, w, E, false); op_h<2>(a); break;
+            default: op_qft<3>(a, w, E, false); op_h<3>(a); break;
+          }
+          break;
+        }
         default: {  // RT_QFT1
           const TileOp op = A.ops[R_.op_begin];
           const int p = op.sbit;  // a lone stage always evaluates its twiddle

@@ -62,6 +62,8 @@ enum TileRoundType : int32_t {
                    //   coef[coef4 + r] = (a, b)
   RT_MAT4_RY = 6,  // RT_MAT4 where every matrix is [[a, -b], [b, a]] (a, b real)
   RT_QFT1 = 7,     // one QFT (or inverse QFT) stage, on any register bit
+  RT_QH1 = 8,      // one QFT stage followed by H on the same register bit
+  RT_OP1 = 9,      // one single-qubit op (MAT, DIAG or H) on any register bit
 };
 // The planner splits a round matching none of the patterns into a sequence of
 // rounds over the same register bits (RT_MAT4 groups and RT_QFT1 stages).
@@ -115,6 +117,7 @@ struct Gf2Args {
   uint32_t t_lo[1 << kGf2MaxC];    // tile coordinate of low source coordinates
   uint32_t t_hi[1 << kGf2MaxC];    // tile coordinate of high source coordinates
   uint32_t v_hi[1 << kGf2MaxC];    // destination offsets for high tile coordinates
+  uint32_t hx[1 << kGf2MaxC];      // LDS swizzle: tile coordinate t lives at t ^ hx[t >> c]
 };
 
 }  // namespace qs

@@ -498,6 +498,45 @@ Gf2Args gf2_args(int n, const Gf2IR& g, int c_bits) {
     a.au_hi[s] = x;
     a.v_hi[s] = y;
   }
+  // LDS swizzle: a linear h on the high tile coordinate with t_lo ^ h(t_hi)
+  // injective over the 2^c low source coordinates, so the scattered writes of
+  // 2^c consecutive lanes hit distinct banks (reads of consecutive t stay
+  // conflict-free because the XOR permutes within aligned blocks of 2^c)
+  {
+    const uint32_t lo_mask = (1u << c) - 1;
+    auto injective = [&](const uint32_t* hcol) {
+      uint64_t seen = 0;
+      for (uint32_t s = 0; s < (1u << c); ++s) {
+        uint32_t t = a.t_lo[s];
+        uint32_t th = t >> c, h = 0;
+        for (int j = 0; j < hi; ++j)
+          if ((th >> j) & 1) h ^= hcol[j];
+        uint32_t v = (t ^ h) & lo_mask;
+        if ((seen >> v) & 1) return false;
+        seen |= 1ull << v;
+      }
+      return true;
+    };
+    uint32_t hcol[32] = {0};
+    bool ok = injective(hcol);
+    uint64_t rng = 0x9e3779b97f4a7c15ull ^ (uint64_t)g.cprime;
+    for (int tries = 0; !ok && tries < 4096; ++tries) {
+      for (int j = 0; j < hi; ++j) {
+        rng ^= rng << 13;
+        rng ^= rng >> 7;
+        rng ^= rng << 17;
+        hcol[j] = (uint32_t)rng & lo_mask;
+      }
+      ok = injective(hcol);
+    }
+    if (!ok) std::memset(hcol, 0, sizeof hcol);  // keep the (conflicting) identity layout
+    for (uint32_t v = 0; v < (1u << hi); ++v) {
+      uint32_t h = 0;
+      for (int j = 0; j < hi; ++j)
+        if ((v >> j) & 1) h ^= hcol[j];
+      a.hx[v] = h;
+    }
+  }
   // complement: unit vectors independent of V
   Gf2Basis C = V;
   int nf = 0;
@@ -874,6 +913,8 @@ int32_t classify_round(const PlanIR& P, const TilePassIR& T, const TileRound& r)
     if (hb == 15u) return RT_QFT4_H4;
   }
   if (n == 1 && (op(0).kind == OP_QFT || op(0).kind == OP_QFT_INV)) return RT_QFT1;
+  if (n == 2 && op(0).kind == OP_QFT && op(1).kind == OP_H && op(0).rbit == op(1).rbit) return RT_QH1;
+  if (n == 1 && (op(0).kind == OP_MAT || op(0).kind == OP_DIAG || op(0).kind == OP_H)) return RT_OP1;
   if (n > 4) return RT_GENERIC;
   uint32_t seen = 0;
   bool all_h = true;
@@ -965,6 +1006,11 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
         q.type = RT_QFT1;
         q.coef4 = -1;
         T.ops[k].square = 0;  // the stage it would square now sits in another round
+        if (T.ops[k].kind == OP_QFT && k + 1 < r.op_end && T.ops[k + 1].kind == OP_H &&
+            T.ops[k + 1].rbit == T.ops[k].rbit) {
+          q.op_end = k + 2;
+          q.type = RT_QH1;
+        }
       } else {
         uint32_t seen = 0;
         int e = k;
@@ -974,9 +1020,14 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
           ++e;
         }
         q.op_end = e;
-        q.type = RT_MAT4;
-        q.coef4 = T.n_coef;
-        T.n_coef += 16;
+        if (e - k == 1) {
+          q.type = RT_OP1;
+          q.coef4 = -1;
+        } else {
+          q.type = RT_MAT4;
+          q.coef4 = T.n_coef;
+          T.n_coef += 16;
+        }
       }
       k = q.op_end;
       T.rounds.push_back(q);
