@@ -182,6 +182,11 @@ qs_status qs_plan_num_layers(const qs_plan* p, size_t* out);
  * full length + 1. */
 qs_status qs_plan_describe(const qs_plan* p, char* buf, size_t cap, size_t* needed);
 qs_status qs_plan_free(qs_plan* p);
+/* A new plan applying the inverse of p (layers in reverse order, each layer
+ * inverted: U^dagger windows, inverse QFT stages, conjugated phase tables,
+ * inverse permutation), sharing p's current parameter values; free it with
+ * qs_plan_free.  Used by the adjoint sweep; also usable to un-compute. */
+qs_status qs_plan_inverse(const qs_plan* p, qs_plan** out);
 
 /* Apply layers [first, first + count) of a plan to a state (asynchronous, on
  * the state's stream).  count = (size_t)-1 applies through the last layer. */

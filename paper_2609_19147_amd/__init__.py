@@ -21,8 +21,9 @@ import numpy as np
 from . import _lib
 from ._lib import QsError, QsGate, QsPauli, QsPlanOpts, check, lib
 
-__all__ = ["State", "Plan", "apply", "apply_gates", "expect", "norm2", "overlap", "infidelity",
-           "amplitudes", "to_c_gates", "to_c_terms", "profile", "QsError", "version"]
+__all__ = ["State", "StateView", "Batch", "Plan", "apply", "apply_gates", "expect", "norm2", "overlap", "infidelity",
+           "amplitudes", "to_c_gates", "to_c_terms", "profile", "QsError", "version", "adjoint_grad",
+           "energy_function"]
 
 
 def version() -> str:
@@ -109,8 +110,9 @@ class State:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value and _lib._lib is not None:
-            _lib._lib.qs_free(h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and L is not None:
+            L.qs_free(h)
             self.h = None
 
     # -- initialisation
@@ -153,6 +155,65 @@ class State:
         check(lib().qs_sync(self.h))
 
 
+class StateView:
+    """A state owned by a Batch (no torch tensor; read it with download())."""
+
+    def __init__(self, handle, n, dtype, owner):
+        self.h = handle
+        self.n = n
+        self.dtype = dtype
+        self._owner = owner
+
+    download = State.download
+    upload = State.upload
+
+
+class Batch:
+    """Many circuits in one device arena, run as one recorded HIP graph."""
+
+    def __init__(self, plans, init: str = "plus", dtype: str = "c64", stream=None):
+        import torch
+        self.plans = list(plans)
+        self.n = [p.n for p in self.plans]
+        self.dtype = dtype
+        nq = (C.c_int * len(self.plans))(*self.n)
+        ph = (C.c_void_p * len(self.plans))(*[p.h.value for p in self.plans])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = C.c_void_p()
+        check(lib().qs_batch_create(len(self.plans), nq, ph, 1 if init == "plus" else 0,
+                                    _lib.QS_C64 if dtype == "c64" else _lib.QS_C128,
+                                    C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and L is not None:
+            L.qs_batch_free(h)
+            self.h = None
+
+    def refresh(self) -> None:
+        check(lib().qs_batch_refresh(self.h))
+
+    def run(self) -> None:
+        check(lib().qs_batch_run(self.h))
+
+    def expect_diag(self, observables) -> np.ndarray:
+        arrs = [to_c_terms(o) for o in observables]
+        ptrs = (C.POINTER(QsPauli) * len(arrs))(*[C.cast(a, C.POINTER(QsPauli)) for a in arrs])
+        cnt = (C.c_size_t * len(arrs))(*[len(o) for o in observables])
+        out = np.zeros(len(arrs))
+        check(lib().qs_batch_expect_diag(self.h, ptrs, cnt, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def state(self, i: int) -> StateView:
+        v = C.c_void_p()
+        check(lib().qs_batch_state(self.h, i, C.byref(v)))
+        return StateView(v, self.n[i], self.dtype, self)
+
+
 # ------------------------------------------------------------------ plans
 class Plan:
     """A fused (or plain) layer plan of a gate stream, built on the host."""
@@ -172,8 +233,9 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value and _lib._lib is not None:
-            _lib._lib.qs_plan_free(h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and L is not None:
+            L.qs_plan_free(h)
             self.h = None
 
     def set_params(self, params) -> "Plan":
@@ -185,6 +247,14 @@ class Plan:
         out = C.c_size_t()
         check(lib().qs_plan_num_layers(self.h, C.byref(out)))
         return out.value
+
+    def inverse(self) -> "Plan":
+        """Plan of the inverse circuit (shares the current parameter values)."""
+        h = C.c_void_p()
+        check(lib().qs_plan_inverse(self.h, C.byref(h)))
+        q = Plan.__new__(Plan)
+        q.n, q.gates, q.n_params, q.h = self.n, self.gates, self.n_params, h
+        return q
 
     def describe(self) -> dict:
         need = C.c_size_t()
@@ -242,6 +312,40 @@ def amplitudes(state: State, idx) -> np.ndarray:
     check(lib().qs_amplitudes(state.h, idx.ctypes.data_as(C.POINTER(C.c_uint64)), idx.size,
                               out.ctypes.data_as(C.c_void_p)))
     return out
+
+
+def adjoint_grad(state: State, plan: Plan, terms):
+    """Energy <psi_L|H|psi_L> and its gradient w.r.t. the plan's parameters by
+    the adjoint method; ``state`` holds psi_0 on entry and psi_L on return."""
+    arr = to_c_terms(terms)
+    e = C.c_double()
+    g = np.zeros(plan.n_params)
+    check(lib().qs_adjoint_grad(state.h, plan.h, arr, len(terms), C.byref(e),
+                                g.ctypes.data_as(C.POINTER(C.c_double)), plan.n_params))
+    return e.value, g
+
+
+def energy_function():
+    """torch.autograd.Function computing E(params) = <psi(params)|H|psi(params)>
+    from |0...0> with the adjoint backward of the library."""
+    import torch
+
+    class QsEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, params, plan, terms, dtype="c64"):
+            p = params.detach().to("cpu", torch.float64).numpy()
+            plan.set_params(p)
+            st = State(plan.n, dtype, init="zero")
+            e, g = adjoint_grad(st, plan, terms)
+            ctx.save_for_backward(torch.as_tensor(g, dtype=params.dtype, device=params.device))
+            return torch.tensor(e, dtype=params.dtype, device=params.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None, None, None
+
+    return QsEnergy
 
 
 class profile:

@@ -48,8 +48,12 @@ thread_local hipEvent_t g_prof_cur = nullptr;
 thread_local const char* g_prof_name = nullptr;
 }  // namespace
 
+// Graph capture must not record profiling events.
+static bool g_prof_suspended = false;
+void prof_suspend(bool on) { g_prof_suspended = on; }
+
 void prof_begin(const char* name, hipStream_t s) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || g_prof_suspended) return;
   hipEvent_t e;
   check_hip(hipEventCreate(&e), "hipEventCreate");
   check_hip(hipEventRecord(e, s), "hipEventRecord");
@@ -57,7 +61,7 @@ void prof_begin(const char* name, hipStream_t s) {
   g_prof_name = name;
 }
 void prof_end(hipStream_t s) {
-  if (!g_prof_on || !g_prof_cur) return;
+  if (!g_prof_on || g_prof_suspended || !g_prof_cur) return;
   hipEvent_t e;
   check_hip(hipEventCreate(&e), "hipEventCreate");
   check_hip(hipEventRecord(e, s), "hipEventRecord");
@@ -292,6 +296,7 @@ extern "C" qs_status qs_plan_set_params(qs_plan* p, const double* params, size_t
       if (!std::isfinite(params[i])) fail(QS_EINVAL, "non-finite parameter");
     p->params.assign(params, params + n_params);
     p->bound = true;
+    p->version += 1;
     p->refresh_device();
   });
 }
@@ -319,6 +324,18 @@ extern "C" qs_status qs_plan_describe(const qs_plan* p, char* buf, size_t cap, s
 qs_plan::~qs_plan() {
   for (auto& d : dev)
     if (d.blob) hipFree(d.blob);
+  delete inv;
+}
+
+extern "C" qs_status qs_plan_inverse(const qs_plan* p, qs_plan** out) {
+  return guarded([&] {
+    if (!p || !out) fail(QS_EINVAL, "NULL argument");
+    auto q = std::make_unique<qs_plan>();
+    q->ir = invert_plan(p->ir);
+    q->params = p->params;
+    q->bound = p->bound;
+    *out = q.release();
+  });
 }
 
 extern "C" qs_status qs_plan_free(qs_plan* p) {

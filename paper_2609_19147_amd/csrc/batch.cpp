@@ -1,15 +1,394 @@
-// Batched execution of many circuits (placeholder until the batched kernels land).
+// Batched execution of many circuits: one device arena for all states, one
+// launch per (qubit count, layer slot) covering every instance of that size,
+// the whole sequence recorded once as a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
 #include "runtime.h"
 
 using namespace qs;
 
-extern "C" qs_status qs_batch_create(size_t, const int*, const qs_plan* const*, int, qs_dtype, void*, qs_batch**) {
-  return QS_EUNSUPPORTED;
+namespace qs {
+void prof_suspend(bool on);
 }
-extern "C" qs_status qs_batch_refresh(qs_batch*) { return QS_EUNSUPPORTED; }
-extern "C" qs_status qs_batch_run(qs_batch*) { return QS_EUNSUPPORTED; }
-extern "C" qs_status qs_batch_expect_diag(qs_batch*, const qs_pauli* const*, const size_t*, double*) {
-  return QS_EUNSUPPORTED;
+
+struct qs_batch {
+  size_t n_inst = 0;
+  qs_dtype dtype = QS_C64;
+  int init = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<int> nq;
+  std::vector<qs_plan*> plans;
+  void* arena = nullptr;
+  std::vector<size_t> offset;  // amplitude offset of each instance
+  std::vector<std::unique_ptr<qs_state>> views;
+  struct Group {
+    int n;
+    std::vector<size_t> inst;
+  };
+  std::vector<Group> groups;
+  void* desc = nullptr;  // device descriptors of the batched tile launches
+  size_t desc_bytes = 0;
+  std::vector<std::vector<size_t>> slot_desc;  // per group, per layer: byte offset into desc (or -1)
+  double* red = nullptr;
+  size_t red_doubles = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  size_t amp_bytes() const { return dtype == QS_C64 ? 8 : 16; }
+  ~qs_batch();
+};
+
+qs_batch::~qs_batch() {
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  if (stream) hipStreamSynchronize(stream);
+  if (desc) hipFree(desc);
+  if (red) hipFree(red);
+  if (arena) hipFree(arena);
+  if (own_stream && stream) hipStreamDestroy(stream);
 }
-extern "C" qs_status qs_batch_state(qs_batch*, size_t, qs_state**) { return QS_EUNSUPPORTED; }
-extern "C" qs_status qs_batch_free(qs_batch*) { return QS_OK; }
+
+namespace {
+
+std::string shape_signature(const PlanIR& P) {
+  std::string sig;
+  for (const LayerIR& L : P.layers) {
+    char b[64];
+    if (L.kind == L_TILE) {
+      const TilePassIR& T = P.passes[L.index];
+      std::snprintf(b, sizeof b, "T%d.%d.%d;", T.L, T.a, T.h);
+    } else {
+      std::snprintf(b, sizeof b, "K%d;", L.kind);
+    }
+    sig += b;
+  }
+  return sig;
+}
+
+template <class R>
+void build_descs(qs_batch& B) {
+  // one TileKArgs per (group, tile layer, instance), laid out contiguously per launch
+  std::vector<unsigned char> host;
+  B.slot_desc.assign(B.groups.size(), {});
+  for (size_t gi = 0; gi < B.groups.size(); ++gi) {
+    const auto& G = B.groups[gi];
+    const PlanIR& P0 = B.plans[G.inst[0]]->ir;
+    B.slot_desc[gi].assign(P0.layers.size(), (size_t)-1);
+    for (size_t li = 0; li < P0.layers.size(); ++li) {
+      if (P0.layers[li].kind != L_TILE) continue;
+      size_t off = (host.size() + 255) & ~size_t(255);
+      host.resize(off + G.inst.size() * sizeof(TileKArgs<R>));
+      for (size_t k = 0; k < G.inst.size(); ++k) {
+        size_t i = G.inst[k];
+        qs_plan& p = *B.plans[i];
+        const PlanDev& d = p.device_for(B.dtype);
+        const char* base = (const char*)d.blob;
+        const LayerIR& L = p.ir.layers[li];
+        const TilePassIR& T = p.ir.passes[L.index];
+        TileKArgs<R> A;
+        std::memset(&A, 0, sizeof A);
+        A.psi = (cplx<R>*)((char*)B.arena + B.offset[i] * B.amp_bytes());
+        A.rounds = (const TileRound*)(base + d.pass_rounds[L.index]);
+        A.ops = (const TileOp*)(base + d.pass_ops[L.index]);
+        A.coef = (const cplx<R>*)(base + d.pass_coef[L.index]);
+        A.diag = d.pass_diag[L.index] ? (const DiagDev*)(base + d.pass_diag[L.index]) : nullptr;
+        A.L = T.L;
+        A.a = T.a;
+        A.h = T.h;
+        A.m = T.L + T.h;
+        A.n_rounds = (uint32_t)T.rounds.size();
+        A.n = p.ir.n;
+        A.scale = T.scale;
+        std::memcpy(host.data() + off + k * sizeof A, &A, sizeof A);
+      }
+      B.slot_desc[gi][li] = off;
+    }
+  }
+  if (host.empty()) host.resize(16);
+  if (B.desc && B.desc_bytes != host.size()) {
+    hipFree(B.desc);
+    B.desc = nullptr;
+  }
+  if (!B.desc) check_hip(hipMalloc(&B.desc, host.size()), "hipMalloc(batch descriptors)");
+  B.desc_bytes = host.size();
+  check_hip(hipMemcpy(B.desc, host.data(), host.size(), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+template <class R>
+void record(qs_batch& B) {
+  // initial states, then every layer slot of every group
+  for (const auto& G : B.groups) {
+    const size_t first = G.inst[0];
+    cplx<R>* base = (cplx<R>*)((char*)B.arena + B.offset[first] * B.amp_bytes());
+    const uint64_t N = (uint64_t)G.inst.size() << G.n;  // instances of a group are contiguous
+    if (B.init == 1) {
+      const double v = std::ldexp(1.0, -G.n / 2) * ((G.n & 1) ? std::sqrt(0.5) : 1.0);
+      launch_fill_uniform<R>(base, N, v, B.stream);
+    } else {
+      // |0...0> for each instance
+      launch_fill_uniform<R>(base, N, 0.0, B.stream);
+      for (size_t i : G.inst)
+        launch_fill_basis<R>((cplx<R>*)((char*)B.arena + B.offset[i] * B.amp_bytes()), 1ull << G.n, 0, B.stream);
+    }
+  }
+  for (size_t gi = 0; gi < B.groups.size(); ++gi) {
+    const auto& G = B.groups[gi];
+    const PlanIR& P0 = B.plans[G.inst[0]]->ir;
+    for (size_t li = 0; li < P0.layers.size(); ++li) {
+      const LayerIR& L0 = P0.layers[li];
+      if (L0.kind == L_TILE) {
+        const TilePassIR& T = P0.passes[L0.index];
+        bool has_diag = false;
+        for (size_t i : G.inst) {
+          const qs_plan& p = *B.plans[i];
+          has_diag = has_diag || !p.ir.passes[p.ir.layers[li].index].diag_slots.empty();
+        }
+        launch_tile_batched<R>((const TileKArgs<R>*)((char*)B.desc + B.slot_desc[gi][li]), (uint32_t)G.inst.size(),
+                               (uint32_t)G.n, (uint32_t)(T.L + T.h), has_diag, B.stream);
+      } else {
+        // other layer kinds: one launch per instance
+        for (size_t i : G.inst) apply_layers(*B.views[i], *B.plans[i], li, li + 1);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" qs_status qs_batch_create(size_t n_inst, const int* n_qubits, const qs_plan* const* plans, int init,
+                                     qs_dtype dtype, void* stream, qs_batch** out) {
+  qs_batch* raw = nullptr;
+  try {
+    if (!out || !n_qubits || !plans || n_inst == 0) fail(QS_EINVAL, "empty batch or NULL argument");
+    if (dtype != QS_C64 && dtype != QS_C128) fail(QS_EINVAL, "unknown dtype");
+    if (init != 0 && init != 1) fail(QS_EINVAL, "init must be 0 or 1");
+    auto B = std::make_unique<qs_batch>();
+    B->n_inst = n_inst;
+    B->dtype = dtype;
+    B->init = init;
+    B->nq.assign(n_qubits, n_qubits + n_inst);
+    for (size_t i = 0; i < n_inst; ++i) {
+      qs_plan* p = const_cast<qs_plan*>(plans[i]);
+      if (!p) fail(QS_EINVAL, "NULL plan");
+      if (p->ir.n != n_qubits[i]) fail(QS_EINVAL, "plan and instance qubit counts differ");
+      if (!p->bound) fail(QS_EINVAL, "plan parameters are not bound");
+      for (const LayerIR& L : p->ir.layers) {
+        if (L.kind == L_GF2) fail(QS_EUNSUPPORTED, "permutation layers are not supported in batches");
+        if (L.kind == L_PLAIN && p->ir.gates[L.index].bits.size() > 2)
+          fail(QS_EUNSUPPORTED, "dense gates on more than two qubits are not supported in batches");
+      }
+      B->plans.push_back(p);
+    }
+    // group instances by qubit count and layer shape, lay states out group by group
+    std::map<std::pair<int, std::string>, size_t> gidx;
+    for (size_t i = 0; i < n_inst; ++i) {
+      auto key = std::make_pair(n_qubits[i], shape_signature(B->plans[i]->ir));
+      auto it = gidx.find(key);
+      if (it == gidx.end()) {
+        gidx[key] = B->groups.size();
+        B->groups.push_back({n_qubits[i], {}});
+        it = gidx.find(key);
+      }
+      B->groups[it->second].inst.push_back(i);
+    }
+    B->offset.assign(n_inst, 0);
+    size_t total = 0;
+    for (auto& G : B->groups)
+      for (size_t i : G.inst) {
+        B->offset[i] = total;
+        total += 1ull << G.n;
+      }
+    const size_t bytes = total * B->amp_bytes();
+    size_t fr = 0, tot = 0;
+    check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    if (bytes > fr) fail(QS_ENOMEM, "batch states do not fit in free device memory");
+    if (hipMalloc(&B->arena, bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of the batch arena failed");
+    if (stream) {
+      B->stream = (hipStream_t)stream;
+    } else {
+      check_hip(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking), "hipStreamCreate");
+      B->own_stream = true;
+    }
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    for (size_t i = 0; i < n_inst; ++i) {
+      auto v = std::make_unique<qs_state>();
+      v->n = n_qubits[i];
+      v->dtype = dtype;
+      v->device = dev;
+      v->buf[0] = (char*)B->arena + B->offset[i] * B->amp_bytes();
+      v->view = true;
+      v->stream = B->stream;
+      B->views.push_back(std::move(v));
+    }
+    raw = B.release();
+    qs_status st = qs_batch_refresh(raw);
+    if (st != QS_OK) {
+      std::string msg = g_last_error;
+      delete raw;
+      fail(st, msg);
+    }
+    *out = raw;
+    return QS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return QS_EINVAL;
+  }
+}
+
+extern "C" qs_status qs_batch_refresh(qs_batch* b) {
+  try {
+    if (!b) fail(QS_EINVAL, "batch is NULL");
+    for (auto* p : b->plans)
+      if (!p->bound) fail(QS_EINVAL, "plan parameters are not bound");
+    check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    if (b->exec) {
+      hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    if (b->graph) {
+      hipGraphDestroy(b->graph);
+      b->graph = nullptr;
+    }
+    if (b->dtype == QS_C64) build_descs<float>(*b);
+    else build_descs<double>(*b);
+    prof_suspend(true);
+    check_hip(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      if (b->dtype == QS_C64) record<float>(*b);
+      else record<double>(*b);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      hipStreamEndCapture(b->stream, &g);
+      if (g) hipGraphDestroy(g);
+      prof_suspend(false);
+      throw;
+    }
+    check_hip(hipStreamEndCapture(b->stream, &b->graph), "hipStreamEndCapture");
+    prof_suspend(false);
+    check_hip(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    return QS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+}
+
+extern "C" qs_status qs_batch_run(qs_batch* b) {
+  try {
+    if (!b || !b->exec) fail(QS_EINVAL, "batch is NULL or not recorded");
+    prof_begin("batch_graph", b->stream);
+    check_hip(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+    prof_end(b->stream);
+    return QS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+}
+
+extern "C" qs_status qs_batch_expect_diag(qs_batch* b, const qs_pauli* const* obs, const size_t* n_terms,
+                                          double* out) {
+  try {
+    if (!b || !obs || !n_terms || !out) fail(QS_EINVAL, "NULL argument");
+    // observables -> count tables (host), then one batched reduction per group
+    std::vector<unsigned char> host;
+    std::vector<ObsDev> od(b->n_inst);
+    std::vector<size_t> t_off(b->n_inst), g_off(b->n_inst), w_off(b->n_inst);
+    auto put = [&](const void* src, size_t bytes) {
+      size_t off = (host.size() + 15) & ~size_t(15);
+      host.resize(off + bytes + 16);
+      if (bytes) std::memcpy(host.data() + off, src, bytes);
+      return off;
+    };
+    std::vector<double> c0(b->n_inst);
+    std::vector<int> ng(b->n_inst);
+    for (size_t i = 0; i < b->n_inst; ++i) {
+      if (n_terms[i] && !obs[i]) fail(QS_EINVAL, "NULL observable");
+      DiagIR D = diag_observable(b->nq[i], obs[i], n_terms[i]);
+      DiagNumeric num = diag_numeric(D, {});
+      std::vector<double> w;
+      for (auto& G : D.groups) w.push_back(G.angle.c0);
+      // diag_numeric's first group has lut entries; only terms/groups are used here
+      t_off[i] = put(num.terms.data(), num.terms.size() * sizeof(DiagTerm));
+      g_off[i] = put(num.groups.data(), num.groups.size() * sizeof(DiagGroup));
+      w_off[i] = put(w.data(), w.size() * sizeof(double));
+      c0[i] = D.global.c0;
+      ng[i] = (int)D.groups.size();
+    }
+    size_t obs_off = (host.size() + 255) & ~size_t(255);
+    host.resize(obs_off + b->n_inst * sizeof(ObsDev));
+    size_t need_red = 0;
+    for (auto& G : b->groups) need_red = std::max(need_red, batch_observable_partials((uint32_t)G.inst.size(), G.n));
+    void* dev = nullptr;
+    check_hip(hipMalloc(&dev, host.size() + sizeof(double) * (b->n_inst + need_red + 16)), "hipMalloc");
+    struct Guard {
+      void* p;
+      ~Guard() { hipFree(p); }
+    } guard{dev};
+    char* base = (char*)dev;
+    double* dout = (double*)(base + ((host.size() + 255) & ~size_t(255)));
+    double* partials = dout + b->n_inst + 8;
+    // descriptors in group order
+    std::vector<size_t> pos(b->n_inst);
+    size_t k = 0;
+    for (auto& G : b->groups)
+      for (size_t i : G.inst) pos[i] = k++;
+    for (size_t i = 0; i < b->n_inst; ++i) {
+      ObsDev o;
+      std::memset(&o, 0, sizeof o);
+      o.psi = b->views[i]->buf[0];
+      o.terms = (const DiagTerm*)(base + t_off[i]);
+      o.groups = (const DiagGroup*)(base + g_off[i]);
+      o.w = (const double*)(base + w_off[i]);
+      o.n_groups = ng[i];
+      o.c0 = c0[i];
+      std::memcpy(host.data() + obs_off + pos[i] * sizeof(ObsDev), &o, sizeof o);
+    }
+    check_hip(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync");
+    size_t first = 0;
+    for (auto& G : b->groups) {
+      const ObsDev* od_dev = (const ObsDev*)(base + obs_off) + first;
+      if (b->dtype == QS_C64)
+        launch_batch_observable<float>(od_dev, (uint32_t)G.inst.size(), G.n, partials, dout + first, b->stream);
+      else
+        launch_batch_observable<double>(od_dev, (uint32_t)G.inst.size(), G.n, partials, dout + first, b->stream);
+      first += G.inst.size();
+    }
+    std::vector<double> res(b->n_inst);
+    check_hip(hipMemcpyAsync(res.data(), dout, b->n_inst * sizeof(double), hipMemcpyDeviceToHost, b->stream),
+              "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    for (size_t i = 0; i < b->n_inst; ++i) out[i] = res[pos[i]];
+    return QS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+}
+
+extern "C" qs_status qs_batch_state(qs_batch* b, size_t i, qs_state** view) {
+  if (!b || !view || i >= b->n_inst) {
+    g_last_error = "bad batch index";
+    return QS_EINVAL;
+  }
+  *view = b->views[i].get();
+  return QS_OK;
+}
+
+extern "C" qs_status qs_batch_free(qs_batch* b) {
+  delete b;
+  return QS_OK;
+}

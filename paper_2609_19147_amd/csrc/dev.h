@@ -60,6 +60,24 @@ __device__ __forceinline__ void st_nt(cplx<double>* p, const cplx<double>& v) {
   __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p));
 }
 
+// Read-only per-launch tables (round and op descriptors, coefficients, count
+// terms) are read through constant-address-space pointers: the compiler then
+// treats them as invariant and uses scalar loads for uniform addresses, which
+// it cannot prove safe for global pointers across the workgroup barriers of a
+// tile pass.  Fields are read one by one (a struct cannot be copied out of
+// that address space).
+#define QS_CONST __attribute__((address_space(4)))
+template <class T>
+using cptr = const QS_CONST T*;
+template <class T>
+__device__ __forceinline__ cptr<T> to_const(const T* p) {
+  return (cptr<T>)p;
+}
+template <class R>
+__device__ __forceinline__ cplx<R> ldc(cptr<cplx<R>> p, int k) {
+  return {p[k].re, p[k].im};
+}
+
 template <class R>
 __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
@@ -147,6 +165,78 @@ __device__ __forceinline__ cplx<R> diag_phase(uint32_t i, const DiagDev& D) {
   }
   if (D.conj) ph.im = -ph.im;
   return ph;
+}
+
+// Counts of NJ basis indices i0 | off[j] of one group at once.  i0 has every
+// bit of every off[j] clear and off[] is the same across the workgroup, so
+// each term is read once and its count splits into a part of i0, evaluated
+// once, and a part of off[j]:
+//   BITS       popc(i0 & m) + popc(off & m)
+//   SHIFT_XOR  popc(((i0 ^ i0 >> s) & m) ^ ((off ^ off >> s) & m))   (xor is linear)
+//   SHIFT_AND  popc(v & (v >> s) & m) with v = i0 | off
+//   PARITY     parity(i0 & m) ^ parity(off & m)
+//   ALL        ((i0 | off) & m) == m
+template <int NJ>
+__device__ __forceinline__ void diag_counts(uint32_t i0, const uint32_t (&off)[NJ], const DiagTerm* terms_, int tb,
+                                            int te, int (&cnt)[NJ]) {
+  const cptr<DiagTerm> terms = to_const(terms_);
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) cnt[j] = 0;
+  for (int t = tb; t < te; ++t) {
+    const uint32_t m = terms[t].mask;
+    const int s = terms[t].shift;
+    switch (terms[t].form) {
+      case DT_BITS: {
+        const int c0 = popc(i0 & m);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) cnt[j] += c0 + popc(off[j] & m);
+        break;
+      }
+      case DT_SHIFT_XOR: {
+        const uint32_t y = (i0 ^ (i0 >> s)) & m;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) cnt[j] += popc(y ^ ((off[j] ^ (off[j] >> s)) & m));
+        break;
+      }
+      case DT_SHIFT_AND: {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const uint32_t v = i0 | off[j];
+          cnt[j] += popc(v & (v >> s) & m);
+        }
+        break;
+      }
+      case DT_PARITY: {
+        const int p0 = popc(i0 & m) & 1;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) cnt[j] += p0 ^ (popc(off[j] & m) & 1);
+        break;
+      }
+      default: {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) cnt[j] += ((i0 | off[j]) & m) == m ? 1 : 0;
+        break;
+      }
+    }
+  }
+}
+
+// a[j] *= phase(i0 | off[j]) for NJ amplitudes (same conditions as diag_counts).
+template <class R, int NJ>
+__device__ __forceinline__ void diag_apply(cplx<R>* a, uint32_t i0, const uint32_t (&off)[NJ], const DiagDev& D) {
+  const cplx<R>* __restrict__ lut = (const cplx<R>*)D.lut;
+  const cptr<DiagGroup> groups = to_const(D.groups);
+  for (int g = 0; g < D.n_groups; ++g) {
+    const int lb = groups[g].lut_begin;
+    int cnt[NJ];
+    diag_counts<NJ>(i0, off, D.terms, groups[g].term_begin, groups[g].term_end, cnt);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      cplx<R> v = lut[lb + cnt[j]];
+      if (D.conj) v.im = -v.im;
+      a[j] = cmul(a[j], v);
+    }
+  }
 }
 
 }  // namespace qs

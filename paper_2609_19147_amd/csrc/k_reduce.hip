@@ -1,8 +1,9 @@
 // FP64 reductions over a state: norms, overlaps, distances and Pauli
 // expectations.  Every amplitude is upcast to FP64; each thread keeps a
 // Neumaier (compensated) sum per output, the workgroup folds its threads'
-// sums pairwise, and a one-block kernel folds the workgroup partials in a
-// fixed order, so results are bitwise repeatable for a given size.
+// sums pairwise, and a second kernel (one workgroup per output) folds the
+// workgroup partials in a fixed order, so results are bitwise repeatable for
+// a given size.
 #include "kernels.h"
 
 namespace qs {
@@ -56,13 +57,30 @@ __global__ void __launch_bounds__(kThreads) reduce_kernel(F f, uint64_t count, d
   }
 }
 
+// Fold of a block's per-thread sums in a fixed pairwise order (every thread
+// of the block must call it).
+__device__ __forceinline__ Acc block_fold(Acc a, Acc* red) {
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int stride = kThreads / 2; stride > 0; stride >>= 1) {
+    if ((int)threadIdx.x < stride) red[threadIdx.x] = ncombine(red[threadIdx.x], red[threadIdx.x + stride]);
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// One workgroup per output: thread x folds partials x, x + kThreads, ... in
+// order, then the workgroup folds its threads pairwise.
 template <int NV>
-__global__ void finalize_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ out) {
-  const int v = threadIdx.x;
-  if (v >= NV) return;
+__global__ void __launch_bounds__(kThreads) finalize_kernel(const double* __restrict__ partials, int nblocks,
+                                                            double* __restrict__ out) {
+  const int v = blockIdx.x;
   Acc a = {0.0, 0.0};
-  for (int b = 0; b < nblocks; ++b) a = ncombine(a, Acc{partials[(b * NV + v) * 2], partials[(b * NV + v) * 2 + 1]});
-  out[v] = a.s + a.c;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads)
+    a = ncombine(a, Acc{partials[(b * NV + v) * 2], partials[(b * NV + v) * 2 + 1]});
+  __shared__ Acc red[kThreads];
+  a = block_fold(a, red);
+  if (threadIdx.x == 0) out[v] = a.s + a.c;
 }
 
 template <class R>
@@ -158,6 +176,130 @@ struct ExpectXF {
   }
 };
 
+template <class R>
+struct PairRhoF {
+  const cplx<R>* phi;
+  const cplx<R>* lam;
+  uint32_t b;
+  __device__ void operator()(uint64_t t, Acc* acc) const {
+    const uint32_t i0 = insert0((uint32_t)t, b), i1 = i0 | (1u << b);
+    const cplx<R> p0 = phi[i0], p1 = phi[i1], l0 = lam[i0], l1 = lam[i1];
+    const double p0r = p0.re, p0i = p0.im, p1r = p1.re, p1i = p1.im;
+    const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
+    // conj(l_r) * p_c
+    nadd(acc[0], l0r * p0r + l0i * p0i);
+    nadd(acc[1], l0r * p0i - l0i * p0r);
+    nadd(acc[2], l0r * p1r + l0i * p1i);
+    nadd(acc[3], l0r * p1i - l0i * p1r);
+    nadd(acc[4], l1r * p0r + l1i * p0i);
+    nadd(acc[5], l1r * p0i - l1i * p0r);
+    nadd(acc[6], l1r * p1r + l1i * p1i);
+    nadd(acc[7], l1r * p1i - l1i * p1r);
+  }
+};
+
+template <class R>
+struct DiagGradF {
+  const cplx<R>* phi;
+  const cplx<R>* lam;
+  DiagDev D;
+  int g0, ng;
+  __device__ void operator()(uint64_t t, Acc* acc) const {
+    const uint32_t i = (uint32_t)t;
+    const cplx<R> p = phi[i], l = lam[i];
+    const double im = (double)l.re * p.im - (double)l.im * p.re;  // Im(conj(l) p)
+#pragma unroll
+    for (int k = 0; k < kMaxTermsPerLaunch; ++k) {
+      if (k >= ng) break;
+      const DiagGroup G = D.groups[g0 + k];
+      nadd(acc[k], im * (double)diag_count<R>(i, D.terms, G.term_begin, G.term_end));
+    }
+  }
+};
+
+// Batched diagonal observable: block b covers chunk (b & (2^cs - 1)) of
+// instance (b >> cs); each chunk is 2^ls consecutive amplitudes.
+template <class R>
+__global__ void __launch_bounds__(kThreads) batch_obs_kernel(const ObsDev* __restrict__ obs, uint32_t cs, uint32_t ls,
+                                                             double* __restrict__ partials) {
+  const ObsDev& O = obs[blockIdx.x >> cs];
+  const cplx2<R>* __restrict__ psi = (const cplx2<R>*)O.psi;
+  const uint32_t base = (blockIdx.x & ((1u << cs) - 1u)) << ls;
+  const uint32_t len = 1u << ls;
+  constexpr int K = 4;  // pairs per thread per step
+  Acc acc = {0.0, 0.0};
+  if (len >= 2u * K * kThreads) {
+    // thread x owns amplitudes 2x | (j & 1) | (j >> 1) 2 kThreads of each step
+    uint32_t off[2 * K];
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) off[j] = (uint32_t)(j & 1) | (uint32_t)(j >> 1) * (2u * kThreads);
+    for (uint32_t c = 0; c < len; c += 2u * K * kThreads) {
+      const uint32_t i0 = base + c + 2u * threadIdx.x;
+      double p[2 * K], v[2 * K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const cplx2<R> x = psi[(i0 >> 1) + k * kThreads];
+        p[2 * k] = abs2d(x.a);
+        p[2 * k + 1] = abs2d(x.b);
+      }
+#pragma unroll
+      for (int j = 0; j < 2 * K; ++j) v[j] = O.c0;
+      for (int g = 0; g < O.n_groups; ++g) {
+        const DiagGroup G = O.groups[g];
+        int cnt[2 * K];
+        diag_counts<2 * K>(i0, off, O.terms, G.term_begin, G.term_end, cnt);
+        const double w = O.w[g];
+#pragma unroll
+        for (int j = 0; j < 2 * K; ++j) v[j] += w * (double)cnt[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 2 * K; ++j) nadd(acc, p[j] * v[j]);
+    }
+  } else {
+    const uint32_t off[2] = {0u, 1u};
+    for (uint32_t t = threadIdx.x; t < len / 2; t += kThreads) {
+      const uint32_t i0 = base + 2u * t;
+      const cplx2<R> x = psi[i0 >> 1];
+      const double p[2] = {abs2d(x.a), abs2d(x.b)};
+      double v[2] = {O.c0, O.c0};
+      for (int g = 0; g < O.n_groups; ++g) {
+        const DiagGroup G = O.groups[g];
+        int cnt[2];
+        diag_counts<2>(i0, off, O.terms, G.term_begin, G.term_end, cnt);
+        v[0] += O.w[g] * (double)cnt[0];
+        v[1] += O.w[g] * (double)cnt[1];
+      }
+      nadd(acc, p[0] * v[0]);
+      nadd(acc, p[1] * v[1]);
+    }
+  }
+  __shared__ Acc red[kThreads];
+  acc = block_fold(acc, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = acc.s;
+    partials[2 * blockIdx.x + 1] = acc.c;
+  }
+}
+
+// One workgroup per instance folds its 2^cs chunk partials.
+__global__ void __launch_bounds__(kThreads) batch_obs_finalize(const double* __restrict__ partials, uint32_t cs,
+                                                               double* __restrict__ out) {
+  const uint32_t inst = blockIdx.x;
+  Acc a = {0.0, 0.0};
+  for (uint32_t c = threadIdx.x; c < (1u << cs); c += kThreads) {
+    const uint32_t b = (inst << cs) + c;
+    a = ncombine(a, Acc{partials[2 * b], partials[2 * b + 1]});
+  }
+  __shared__ Acc red[kThreads];
+  a = block_fold(a, red);
+  if (threadIdx.x == 0) out[inst] = a.s + a.c;
+}
+
+inline void batch_obs_shape(uint32_t n, uint32_t* cs, uint32_t* ls) {
+  *ls = n < 14 ? n : 14;
+  *cs = n - *ls;
+}
+
 inline int nblocks_for(uint64_t count) {
   uint64_t b = (count + kThreads - 1) / kThreads;
   if (b > (uint64_t)kRedBlocks) b = kRedBlocks;
@@ -168,7 +310,7 @@ template <int NV, class F>
 void run_reduce(const char* name, F f, uint64_t count, double* partials, double* out, hipStream_t s) {
   const int nb = nblocks_for(count);
   QS_LAUNCH(name, s, (reduce_kernel<NV, F>), dim3(nb), dim3(kThreads), 0, s, f, count, partials);
-  QS_LAUNCH("reduce_finalize", s, finalize_kernel<NV>, dim3(1), dim3(64), 0, s, partials, nb, out);
+  QS_LAUNCH("reduce_finalize", s, finalize_kernel<NV>, dim3(NV), dim3(kThreads), 0, s, partials, nb, out);
 }
 
 }  // namespace
@@ -210,6 +352,43 @@ void launch_expect_x(const cplx<R>* psi, int n, uint32_t x, const uint32_t* z, c
   ExpectXF<R> f{psi, M, nt, x, h};
   run_reduce<kMaxTermsPerLaunch>("reduce_expect_x", f, (1ull << n) / 2, partials, out, s);
 }
+
+template <class R>
+void launch_pair_rho(const cplx<R>* phi, const cplx<R>* lam, int n, int b, double* partials, double* out,
+                     hipStream_t s) {
+  run_reduce<8>("reduce_pair_rho", PairRhoF<R>{phi, lam, (uint32_t)b}, (1ull << n) / 2, partials, out, s);
+}
+template <class R>
+void launch_diag_grad(const cplx<R>* phi, const cplx<R>* lam, int n, const DiagDev& D, int g0, int ng,
+                      double* partials, double* out, hipStream_t s) {
+  run_reduce<kMaxTermsPerLaunch>("reduce_diag_grad", DiagGradF<R>{phi, lam, D, g0, ng}, 1ull << n, partials, out, s);
+}
+template void launch_pair_rho<float>(const cplx<float>*, const cplx<float>*, int, int, double*, double*, hipStream_t);
+template void launch_pair_rho<double>(const cplx<double>*, const cplx<double>*, int, int, double*, double*,
+                                      hipStream_t);
+template void launch_diag_grad<float>(const cplx<float>*, const cplx<float>*, int, const DiagDev&, int, int, double*,
+                                      double*, hipStream_t);
+template void launch_diag_grad<double>(const cplx<double>*, const cplx<double>*, int, const DiagDev&, int, int,
+                                       double*, double*, hipStream_t);
+
+size_t batch_observable_partials(uint32_t count, uint32_t n) {
+  uint32_t cs, ls;
+  batch_obs_shape(n, &cs, &ls);
+  return 2ull * ((size_t)count << cs);
+}
+
+template <class R>
+void launch_batch_observable(const ObsDev* obs_dev, uint32_t count, uint32_t n, double* partials, double* out,
+                             hipStream_t s) {
+  uint32_t cs, ls;
+  batch_obs_shape(n, &cs, &ls);
+  QS_LAUNCH("batch_observable", s, batch_obs_kernel<R>, dim3(count << cs), dim3(kThreads), 0, s, obs_dev, cs, ls,
+            partials);
+  QS_LAUNCH("batch_observable_finalize", s, batch_obs_finalize, dim3(count), dim3(kThreads), 0, s, partials, cs,
+            out);
+}
+template void launch_batch_observable<float>(const ObsDev*, uint32_t, uint32_t, double*, double*, hipStream_t);
+template void launch_batch_observable<double>(const ObsDev*, uint32_t, uint32_t, double*, double*, hipStream_t);
 
 template void launch_norm2<float>(const cplx<float>*, uint64_t, double*, double*, hipStream_t);
 template void launch_norm2<double>(const cplx<double>*, uint64_t, double*, double*, hipStream_t);

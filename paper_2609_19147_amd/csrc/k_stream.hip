@@ -8,6 +8,7 @@ namespace qs {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kDiagPairsPerThread = 4;
 
 inline unsigned grid_for(uint64_t work, int per_block) {
   uint64_t b = (work + per_block - 1) / per_block;
@@ -60,12 +61,36 @@ __global__ void gather_kernel(const cplx<R>* psi, const uint64_t* idx, cplx<R>* 
 // amplitudes per 16-byte access; the phase tables are small and stay cached.
 template <class R>
 __global__ void __launch_bounds__(kThreads) diag_kernel(cplx<R>* psi, uint64_t npairs, DiagDev D) {
-  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < npairs; t += (uint64_t)gridDim.x * kThreads) {
-    cplx2<R> v = ld_nt(reinterpret_cast<cplx2<R>*>(psi) + t);
-    const uint32_t i = (uint32_t)(2 * t);
-    v.a = cmul(v.a, diag_phase<R>(i, D));
-    v.b = cmul(v.b, diag_phase<R>(i + 1, D));
-    st_nt(reinterpret_cast<cplx2<R>*>(psi) + t, v);
+  cplx2<R>* __restrict__ p2 = reinterpret_cast<cplx2<R>*>(psi);
+  constexpr int K = kDiagPairsPerThread;
+  const uint64_t nchunks = npairs / (kThreads * K);
+  if (nchunks > 0) {
+    // chunks of K * kThreads pairs: thread x owns pairs x + k kThreads, i.e.
+    // amplitudes 2x | (j & 1) | (j >> 1) 2 kThreads of the chunk
+    uint32_t off[2 * K];
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) off[j] = (uint32_t)(j & 1) | (uint32_t)(j >> 1) * (2u * kThreads);
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+      const uint64_t t0 = c * (uint64_t)(kThreads * K) + threadIdx.x;
+      cplx<R> a[2 * K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const cplx2<R> v = ld_nt(p2 + t0 + k * kThreads);
+        a[2 * k] = v.a;
+        a[2 * k + 1] = v.b;
+      }
+      diag_apply<R, 2 * K>(a, (uint32_t)(2 * t0), off, D);
+#pragma unroll
+      for (int k = 0; k < K; ++k) st_nt(p2 + t0 + k * kThreads, cplx2<R>{a[2 * k], a[2 * k + 1]});
+    }
+  } else {
+    const uint32_t off[2] = {0u, 1u};
+    for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < npairs; t += (uint64_t)gridDim.x * kThreads) {
+      const cplx2<R> v = ld_nt(p2 + t);
+      cplx<R> a[2] = {v.a, v.b};
+      diag_apply<R, 2>(a, (uint32_t)(2 * t), off, D);
+      st_nt(p2 + t, cplx2<R>{a[0], a[1]});
+    }
   }
 }
 
@@ -139,7 +164,48 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
   }
 }
 
+// out_i = sum_t c_t s_t(i) psi_{i ^ x_t}; consecutive terms sharing x reuse the read.
+template <class R>
+__global__ void __launch_bounds__(kThreads) pauli_apply_kernel(const cplx<R>* __restrict__ psi,
+                                                               cplx<R>* __restrict__ out, uint64_t N,
+                                                               const uint32_t* __restrict__ xs,
+                                                               const uint32_t* __restrict__ zs,
+                                                               const double* __restrict__ cs, int nt) {
+  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < N; t += (uint64_t)gridDim.x * kThreads) {
+    const uint32_t i = (uint32_t)t;
+    double accr = 0.0, acci = 0.0;
+    uint32_t xprev = 0xffffffffu;
+    double pr = 0.0, pi = 0.0;
+    for (int k = 0; k < nt; ++k) {
+      const uint32_t x = xs[k];
+      if (x != xprev) {
+        const cplx<R> v = psi[i ^ x];
+        pr = v.re;
+        pi = v.im;
+        xprev = x;
+      }
+      const double sg = (popc((i ^ x) & zs[k]) & 1) ? -1.0 : 1.0;
+      const double cr = sg * cs[2 * k], ci = sg * cs[2 * k + 1];
+      accr += cr * pr - ci * pi;
+      acci += cr * pi + ci * pr;
+    }
+    out[i] = {(R)accr, (R)acci};
+  }
+}
+
 }  // namespace
+
+template <class R>
+void launch_pauli_apply(const cplx<R>* psi, cplx<R>* out, int n, const uint32_t* x_dev, const uint32_t* z_dev,
+                        const double* c_dev, int n_terms, hipStream_t s) {
+  const uint64_t N = 1ull << n;
+  QS_LAUNCH("pauli_apply", s, pauli_apply_kernel<R>, dim3(grid_for(N, kThreads)), dim3(kThreads), 0, s, psi, out, N,
+            x_dev, z_dev, c_dev, n_terms);
+}
+template void launch_pauli_apply<float>(const cplx<float>*, cplx<float>*, int, const uint32_t*, const uint32_t*,
+                                        const double*, int, hipStream_t);
+template void launch_pauli_apply<double>(const cplx<double>*, cplx<double>*, int, const uint32_t*, const uint32_t*,
+                                         const double*, int, hipStream_t);
 
 template <class R>
 void launch_fill_basis(cplx<R>* psi, uint64_t N, uint64_t index, hipStream_t s) {

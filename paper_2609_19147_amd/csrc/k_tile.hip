@@ -38,8 +38,8 @@ struct Ctx {
 };
 
 template <int S, class R>
-__device__ __forceinline__ void op_mat(cplx<R>* a, const cplx<R>* __restrict__ u) {
-  const cplx<R> u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+__device__ __forceinline__ void op_mat(cplx<R>* a, cptr<cplx<R>> u) {
+  const cplx<R> u00 = ldc(u, 0), u01 = ldc(u, 1), u10 = ldc(u, 2), u11 = ldc(u, 3);
 #pragma unroll
   for (int j = 0; j < RN; ++j) {
     if (j & (1 << S)) continue;
@@ -50,8 +50,8 @@ __device__ __forceinline__ void op_mat(cplx<R>* a, const cplx<R>* __restrict__ u
 }
 
 template <int S, class R>
-__device__ __forceinline__ void op_diag(cplx<R>* a, const cplx<R>* __restrict__ u) {
-  const cplx<R> d0 = u[0], d1 = u[1];
+__device__ __forceinline__ void op_diag(cplx<R>* a, cptr<cplx<R>> u) {
+  const cplx<R> d0 = ldc(u, 0), d1 = ldc(u, 1);
 #pragma unroll
   for (int j = 0; j < RN; ++j) a[j] = cmul((j & (1 << S)) ? d1 : d0, a[j]);
 }
@@ -70,18 +70,19 @@ __device__ __forceinline__ void op_h(cplx<R>* a) {
 
 // Unscaled QFT stage on register bit S: a1' = (a0 - a1) * w * E[k], with w the
 // group twiddle (bits outside the round) and E[k] the intra-round factor of
-// the register bits below S.
-template <int S, class R>
-__device__ __forceinline__ void op_qft(cplx<R>* a, cplx<R> w, const cplx<R>* __restrict__ E, bool inverse) {
+// the register bits below S.  The inverse stage undoes it: a1 <- a1 conj(w E[k]),
+// then the butterfly.
+template <int S, class R, bool kInv>
+__device__ __forceinline__ void op_qft(cplx<R>* a, cplx<R> w, cptr<cplx<R>> E) {
   // pairs (j, j | 2^S) with j = k + hi * 2^(S+1): the twiddle depends on k only
 #pragma unroll
   for (int k = 0; k < (1 << S); ++k) {
-    const cplx<R> tw = k == 0 ? w : cmul(w, E[k]);
+    const cplx<R> tw = k == 0 ? w : cmul(w, ldc(E, k));
 #pragma unroll
     for (int hi = 0; hi < (RN >> (S + 1)); ++hi) {
       const int j = k + (hi << (S + 1));
       const cplx<R> x = a[j], y = a[j | (1 << S)];
-      if (!inverse) {
+      if (!kInv) {
         a[j] = cadd(x, y);
         a[j | (1 << S)] = cmul(csub(x, y), tw);
       } else {
@@ -94,26 +95,26 @@ __device__ __forceinline__ void op_qft(cplx<R>* a, cplx<R> w, const cplx<R>* __r
 }
 
 // ---- straight-line round patterns -------------------------------------------
+// Group twiddle of a stage with stage bit p: exp(i pi (g mod 2^p) / 2^p), or the
+// square of the previous stage's (bit p + 1 of the same round) when flagged.
 template <class R>
-__device__ __forceinline__ cplx<R> qft_w(const TileOp& op, uint32_t gglobal, cplx<R> wprev) {
-  if (op.square) return cmul(wprev, wprev);
-  const int p = op.sbit;
+__device__ __forceinline__ cplx<R> qft_w(cptr<TileOp> op, uint32_t gglobal, cplx<R> wprev) {
+  if (op->square) return cmul(wprev, wprev);
+  const int p = op->sbit;
   const uint32_t low = p == 0 ? 0u : (gglobal & ((1u << p) - 1u));
   return cispi<R>(low, p);
 }
 
 template <class R>
-__device__ __forceinline__ void round_qft4(cplx<R>* a, const TileOp* __restrict__ ops, const cplx<R>* __restrict__ coef,
-                                           uint32_t gglobal) {
-  const TileOp o3 = ops[0], o2 = ops[1], o1 = ops[2], o0 = ops[3];
-  cplx<R> w = qft_w<R>(o3, gglobal, cplx<R>{R(1), R(0)});
-  op_qft<3>(a, w, coef + o3.coef, false);
-  w = qft_w<R>(o2, gglobal, w);
-  op_qft<2>(a, w, coef + o2.coef, false);
-  w = qft_w<R>(o1, gglobal, w);
-  op_qft<1>(a, w, coef + o1.coef, false);
-  w = qft_w<R>(o0, gglobal, w);
-  op_qft<0>(a, w, coef + o0.coef, false);
+__device__ __forceinline__ void round_qft4(cplx<R>* a, cptr<TileOp> ops, cptr<cplx<R>> coef, uint32_t gglobal) {
+  cplx<R> w = qft_w<R>(ops + 0, gglobal, cplx<R>{R(1), R(0)});
+  op_qft<3, R, false>(a, w, coef + ops[0].coef);
+  w = qft_w<R>(ops + 1, gglobal, w);
+  op_qft<2, R, false>(a, w, coef + ops[1].coef);
+  w = qft_w<R>(ops + 2, gglobal, w);
+  op_qft<1, R, false>(a, w, coef + ops[2].coef);
+  w = qft_w<R>(ops + 3, gglobal, w);
+  op_qft<0, R, false>(a, w, coef + ops[3].coef);
 }
 
 template <class R>
@@ -125,14 +126,14 @@ __device__ __forceinline__ void round_h4(cplx<R>* a) {
 }
 
 template <class R>
-__device__ __forceinline__ void round_mat4(cplx<R>* a, const cplx<R>* __restrict__ c) {
+__device__ __forceinline__ void round_mat4(cplx<R>* a, cptr<cplx<R>> c) {
   op_mat<0>(a, c);
   op_mat<1>(a, c + 4);
   op_mat<2>(a, c + 8);
   op_mat<3>(a, c + 12);
 }
 
-// [[x, -i y], [-i y, x]] with real (x, y) = c[S]: 2 real multiply-adds per output component.
+// [[x, -i y], [-i y, x]] with real (x, y) = c: 2 real multiply-adds per output component.
 template <int S, class R>
 __device__ __forceinline__ void op_rx(cplx<R>* a, cplx<R> c) {
 #pragma unroll
@@ -143,7 +144,7 @@ __device__ __forceinline__ void op_rx(cplx<R>* a, cplx<R> c) {
     a[j | (1 << S)] = {c.re * y.re + c.im * x.im, c.re * y.im - c.im * x.re};
   }
 }
-// [[x, -y], [y, x]] with real (x, y) = c[S].
+// [[x, -y], [y, x]] with real (x, y) = c.
 template <int S, class R>
 __device__ __forceinline__ void op_ry(cplx<R>* a, cplx<R> c) {
 #pragma unroll
@@ -155,13 +156,135 @@ __device__ __forceinline__ void op_ry(cplx<R>* a, cplx<R> c) {
   }
 }
 
+// ---- round patterns as functors: f(a, g) transforms the 16 registers of the
+// group whose smallest index is g (index bits outside the round).
+template <class R, bool kThenH4>
+struct FQft4 {
+  cptr<TileOp> ops;
+  cptr<cplx<R>> coef;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const {
+    round_qft4<R>(a, ops, coef, g);
+    if (kThenH4) round_h4<R>(a);
+  }
+};
 template <class R>
-__global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
+struct FH4 {
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const { round_h4<R>(a); }
+};
+template <class R>
+struct FMat4 {
+  cptr<cplx<R>> c;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const { round_mat4<R>(a, c); }
+};
+template <class R>
+struct FRx4 {
+  cptr<cplx<R>> c;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const {
+    op_rx<0>(a, ldc(c, 0));
+    op_rx<1>(a, ldc(c, 1));
+    op_rx<2>(a, ldc(c, 2));
+    op_rx<3>(a, ldc(c, 3));
+  }
+};
+template <class R>
+struct FRy4 {
+  cptr<cplx<R>> c;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const {
+    op_ry<0>(a, ldc(c, 0));
+    op_ry<1>(a, ldc(c, 1));
+    op_ry<2>(a, ldc(c, 2));
+    op_ry<3>(a, ldc(c, 3));
+  }
+};
+template <int S, class R>
+struct FH1 {
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const { op_h<S>(a); }
+};
+template <int S, class R>
+struct FDiag1 {
+  cptr<cplx<R>> c;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const { op_diag<S>(a, c); }
+};
+template <int S, class R>
+struct FMat1 {
+  cptr<cplx<R>> c;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const { op_mat<S>(a, c); }
+};
+// One QFT stage (stage bit p) on register bit S, optionally followed by the
+// Hadamard of the same bit.  A lone stage always evaluates its twiddle.
+template <int S, class R, bool kThenH, bool kInv>
+struct FQft1 {
+  cptr<cplx<R>> E;
+  int p;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const {
+    const cplx<R> w = cispi<R>(p == 0 ? 0u : (g & ((1u << p) - 1u)), p);
+    op_qft<S, R, kInv>(a, w, E);
+    if (kThenH) op_h<S>(a);
+  }
+};
+
+// Diagonal slot d of a pass (uniform): its descriptor read with scalar loads.
+__device__ __forceinline__ DiagDev diag_slot(const DiagDev* slots, int d) {
+  const cptr<DiagDev> S = to_const(slots) + d;
+  DiagDev D;
+  D.terms = S->terms;
+  D.groups = S->groups;
+  D.lut = S->lut;
+  D.n_groups = S->n_groups;
+  D.conj = S->conj;
+  return D;
+}
+
+template <class R, bool kDiag>
+struct RoundLoop {
+  const TileKArgs<R>& A;
+  const Ctx& C;
+  cptr<TileRound> R_;
+  cplx<R>* T;
+  uint32_t ngroups, nthr;
+
+  template <class F>
+  __device__ __forceinline__ void operator()(const F& f) const {
+    const int t0 = R_->tbit[0], t1 = R_->tbit[1], t2 = R_->tbit[2], t3 = R_->tbit[3];
+    uint32_t loff[RN];
+#pragma unroll
+    for (int j = 0; j < RN; ++j) loff[j] = R_->loff[j];
+    for (uint32_t g = threadIdx.x; g < ngroups; g += nthr) {
+      uint32_t gpos = g;
+      gpos = insert0(gpos, t0);
+      gpos = insert0(gpos, t1);
+      gpos = insert0(gpos, t2);
+      gpos = insert0(gpos, t3);
+      cplx<R>* Tg = T + lds_off(gpos);
+      cplx<R> a[RN];
+#pragma unroll
+      for (int j = 0; j < RN; ++j) a[j] = Tg[loff[j]];
+      const uint32_t gglobal = C.base | C.dep(gpos);
+      if (kDiag && R_->diag >= 0) {
+        // register j holds index gglobal | dep(round bits of j)
+        const uint32_t b0 = C.dep(1u << t0), b1 = C.dep(1u << t1), b2 = C.dep(1u << t2), b3 = C.dep(1u << t3);
+        uint32_t off[RN];
+#pragma unroll
+        for (int j = 0; j < RN; ++j)
+          off[j] = ((j & 1) ? b0 : 0u) | ((j & 2) ? b1 : 0u) | ((j & 4) ? b2 : 0u) | ((j & 8) ? b3 : 0u);
+        diag_apply<R, RN>(a, gglobal, off, diag_slot(A.diag, R_->diag));
+      }
+      f(a, gglobal);
+#pragma unroll
+      for (int j = 0; j < RN; ++j) Tg[loff[j]] = a[j];
+    }
+  }
+};
+
+// kDiag: the pass carries diagonal layers.  Passes without them use an
+// instantiation that has no phase-evaluation code at all, which keeps the
+// butterfly rounds' register allocation and schedule tight.
+template <class R, bool kDiag>
+__device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t coset) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
   const uint32_t M = 1u << A.m;
   const uint32_t nthr = blockDim.x;
-  const uint32_t coset = blockIdx.x;
   Ctx C;
   C.L = A.L;
   C.a = A.a;
@@ -189,120 +312,83 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
   }
   __syncthreads();
 
-  // ---- rounds
+  // ---- rounds: the pattern is uniform per round, so the dispatch sits
+  // outside the per-thread group loop and every pattern runs its own loop
+  // (registers loaded, transformed and stored with no value crossing a join)
   const uint32_t ngroups = M >> RB;
+  const cptr<TileRound> rounds = to_const(A.rounds);
+  const cptr<TileOp> ops = to_const(A.ops);
+  const cptr<cplx<R>> coef = to_const(A.coef);
   for (uint32_t r = 0; r < A.n_rounds; ++r) {
-    const TileRound& R_ = A.rounds[r];
-    const int t0 = R_.tbit[0], t1 = R_.tbit[1], t2 = R_.tbit[2], t3 = R_.tbit[3];
-    for (uint32_t g = threadIdx.x; g < ngroups; g += nthr) {
-      uint32_t gpos = g;
-      gpos = insert0(gpos, t0);
-      gpos = insert0(gpos, t1);
-      gpos = insert0(gpos, t2);
-      gpos = insert0(gpos, t3);
-      cplx<R>* Tg = T + lds_off(gpos);
-      cplx<R> a[RN];
-#pragma unroll
-      for (int j = 0; j < RN; ++j) a[j] = Tg[R_.loff[j]];
-      if (R_.diag >= 0) {
-        const DiagDev& D = A.diag[R_.diag];
-        const uint32_t b0 = 1u << t0, b1 = 1u << t1, b2 = 1u << t2, b3 = 1u << t3;
-#pragma unroll
-        for (int j = 0; j < RN; ++j) {
-          const uint32_t off = ((j & 1) ? b0 : 0u) | ((j & 2) ? b1 : 0u) | ((j & 4) ? b2 : 0u) | ((j & 8) ? b3 : 0u);
-          a[j] = cmul(a[j], diag_phase<R>(C.base | C.dep(gpos | off), D));
+    const cptr<TileRound> R_ = rounds + r;
+    const RoundLoop<R, kDiag> L{A, C, R_, T, ngroups, nthr};
+    switch (R_->type) {
+      case RT_QFT4:
+        L(FQft4<R, false>{ops + R_->op_begin, coef});
+        break;
+      case RT_QFT4_H4:
+        L(FQft4<R, true>{ops + R_->op_begin, coef});
+        break;
+      case RT_H4:
+        L(FH4<R>{});
+        break;
+      case RT_MAT4:
+        L(FMat4<R>{coef + R_->coef4});
+        break;
+      case RT_MAT4_RX:
+        L(FRx4<R>{coef + R_->coef4});
+        break;
+      case RT_MAT4_RY:
+        L(FRy4<R>{coef + R_->coef4});
+        break;
+      case RT_OP1: {
+        const cptr<TileOp> op = ops + R_->op_begin;
+        const cptr<cplx<R>> c = coef + op->coef;
+        const int kind = op->kind == OP_H ? 0 : (op->kind == OP_DIAG ? 1 : 2);
+        switch (kind * 4 + (op->rbit & 3)) {
+          case 0: L(FH1<0, R>{}); break;
+          case 1: L(FH1<1, R>{}); break;
+          case 2: L(FH1<2, R>{}); break;
+          case 3: L(FH1<3, R>{}); break;
+          case 4: L(FDiag1<0, R>{c}); break;
+          case 5: L(FDiag1<1, R>{c}); break;
+          case 6: L(FDiag1<2, R>{c}); break;
+          case 7: L(FDiag1<3, R>{c}); break;
+          case 8: L(FMat1<0, R>{c}); break;
+          case 9: L(FMat1<1, R>{c}); break;
+          case 10: L(FMat1<2, R>{c}); break;
+          default: L(FMat1<3, R>{c}); break;
         }
+        break;
       }
-      const uint32_t gglobal = C.base | C.dep(gpos);
-      // every case writes its registers back itself, so nothing is live
-      // across the join of the switch
-      switch (R_.type) {
-        case RT_QFT4:
-          round_qft4<R>(a, A.ops + R_.op_begin, A.coef, gglobal);
-          break;
-        case RT_QFT4_H4:
-          round_qft4<R>(a, A.ops + R_.op_begin, A.coef, gglobal);
-          round_h4<R>(a);
-          break;
-        case RT_H4:
-          round_h4<R>(a);
-          break;
-        case RT_MAT4:
-          round_mat4<R>(a, A.coef + R_.coef4);
-          break;
-        case RT_MAT4_RX: {
-          const cplx<R>* c = A.coef + R_.coef4;
-          op_rx<0>(a, c[0]);
-          op_rx<1>(a, c[1]);
-          op_rx<2>(a, c[2]);
-          op_rx<3>(a, c[3]);
-          break;
+      case RT_QH1: {
+        const cptr<TileOp> op = ops + R_->op_begin;
+        const cptr<cplx<R>> E = coef + op->coef;
+        const int p = op->sbit;
+        switch (op->rbit & 3) {
+          case 0: L(FQft1<0, R, true, false>{E, p}); break;
+          case 1: L(FQft1<1, R, true, false>{E, p}); break;
+          case 2: L(FQft1<2, R, true, false>{E, p}); break;
+          default: L(FQft1<3, R, true, false>{E, p}); break;
         }
-        case RT_MAT4_RY: {
-          const cplx<R>* c = A.coef + R_.coef4;
-          op_ry<0>(a, c[0]);
-          op_ry<1>(a, c[1]);
-          op_ry<2>(a, c[2]);
-          op_ry<3>(a, c[3]);
-          break;
-        }
-        case RT_OP1: {
-          const TileOp op = A.ops[R_.op_begin];
-          const cplx<R>* c = A.coef + op.coef;
-          if (op.kind == OP_H) {
-            switch (op.rbit) {
-              case 0: op_h<0>(a); break;
-              case 1: op_h<1>(a); break;
-              case 2: op_h<2>(a); break;
-              default: op_h<3>(a); break;
-            }
-          } else if (op.kind == OP_DIAG) {
-            switch (op.rbit) {
-              case 0: op_diag<0>(a, c); break;
-              case 1: op_diag<1>(a, c); break;
-              case 2: op_diag<2>(a, c); break;
-              default: op_diag<3>(a, c); break;
-            }
-          } else {
-            switch (op.rbit) {
-              case 0: op_mat<0>(a, c); break;
-              case 1: op_mat<1>(a, c); break;
-              case 2: op_mat<2>(a, c); break;
-              default: op_mat<3>(a, c); break;
-            }
-          }
-          break;
-        }
-        case RT_QH1: {
-          const TileOp op = A.ops[R_.op_begin];
-          const int p = op.sbit;
-          const cplx<R> w = cispi<R>(p == 0 ? 0u : (gglobal & ((1u << p) - 1u)), p);
-          const cplx<R>* E = A.coef + op.coef;
-          switch (op.rbit) {
-            case 0: op_qft<0>(a, w, E, false); op_h<0>(a); break;
-            case 1: op_qft<1>(a, w, E, false); op_h<1>(a); break;
-            case 2: op_qft<2>(a, w, E, false); op_h<2>(a); break;
-            default: op_qft<3>(a, w, E, false); op_h<3>(a); break;
-          }
-          break;
-        }
-        default: {  // RT_QFT1
-          const TileOp op = A.ops[R_.op_begin];
-          const int p = op.sbit;  // a lone stage always evaluates its twiddle
-          const cplx<R> w = cispi<R>(p == 0 ? 0u : (gglobal & ((1u << p) - 1u)), p);
-          const bool inv = op.kind == OP_QFT_INV;
-          const cplx<R>* E = A.coef + op.coef;
-          switch (op.rbit) {
-            case 0: op_qft<0>(a, w, E, inv); break;
-            case 1: op_qft<1>(a, w, E, inv); break;
-            case 2: op_qft<2>(a, w, E, inv); break;
-            default: op_qft<3>(a, w, E, inv); break;
-          }
-          break;
-        }
+        break;
       }
-#pragma unroll
-      for (int j = 0; j < RN; ++j) Tg[R_.loff[j]] = a[j];
+      default: {  // RT_QFT1
+        const cptr<TileOp> op = ops + R_->op_begin;
+        const cptr<cplx<R>> E = coef + op->coef;
+        const int p = op->sbit;
+        switch ((op->kind == OP_QFT_INV ? 4 : 0) + (op->rbit & 3)) {
+          case 0: L(FQft1<0, R, false, false>{E, p}); break;
+          case 1: L(FQft1<1, R, false, false>{E, p}); break;
+          case 2: L(FQft1<2, R, false, false>{E, p}); break;
+          case 3: L(FQft1<3, R, false, false>{E, p}); break;
+          case 4: L(FQft1<0, R, false, true>{E, p}); break;
+          case 5: L(FQft1<1, R, false, true>{E, p}); break;
+          case 6: L(FQft1<2, R, false, true>{E, p}); break;
+          default: L(FQft1<3, R, false, true>{E, p}); break;
+        }
+        break;
+      }
     }
     __syncthreads();
   }
@@ -338,25 +424,109 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
   }
 }
 
+template <class R, bool kDiag>
+__global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
+  tile_body<R, kDiag>(A, blockIdx.x);
+}
+
+// complex64 passes without diagonal layers: registers capped at 128 so that
+// four waves fit per SIMD (two 512-thread workgroups of 2^13-amplitude tiles,
+// or four of 2^12, share a CU's LDS).
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
+tile_kernel_c64(TileKArgs<float> A) {
+  tile_body<float, false>(A, blockIdx.x);
+}
+
+// Many instances of one tile geometry in one grid: block b runs coset
+// (b & (2^shift - 1)) of instance (b >> shift).
+template <class R, bool kDiag>
+__global__ void __launch_bounds__(kMaxThreads) tile_kernel_batched(const TileKArgs<R>* __restrict__ descs,
+                                                                    uint32_t shift) {
+  // the instance's argument block, read field by field with scalar loads
+  const cptr<TileKArgs<R>> P = to_const(descs) + (blockIdx.x >> shift);
+  TileKArgs<R> A;
+  A.psi = P->psi;
+  A.rounds = P->rounds;
+  A.ops = P->ops;
+  A.coef = P->coef;
+  A.diag = P->diag;
+  A.L = P->L;
+  A.a = P->a;
+  A.h = P->h;
+  A.m = P->m;
+  A.n_rounds = P->n_rounds;
+  A.n = P->n;
+  A.scale = P->scale;
+  tile_body<R, kDiag>(A, blockIdx.x & ((1u << shift) - 1u));
+}
+
+inline uint32_t tile_threads(uint32_t m) {
+  uint32_t threads = (1u << m) >> RB;
+  return threads < 64 ? 64 : (threads > (uint32_t)kMaxThreads ? (uint32_t)kMaxThreads : threads);
+}
+
+inline size_t tile_lds(uint32_t m, size_t elem) {
+  const uint32_t M = 1u << m;
+  return elem * (M + ((M >> 5) << 1));
+}
+
 }  // namespace
 
-template <class R>
-void launch_tile(const TileKArgs<R>& A, hipStream_t s) {
+template <class R, bool kDiag>
+void launch_tile_batched_k(const TileKArgs<R>* descs_dev, uint32_t count, uint32_t n, uint32_t m, hipStream_t s) {
   static bool attr_set = false;
-  const uint32_t M = 1u << A.m;
-  const size_t lds = sizeof(cplx<R>) * (M + ((M >> 5) << 1));
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)tile_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute((const void*)tile_kernel_batched<R, kDiag>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        160 * 1024);
+    attr_set = true;
+  }
+  const uint32_t shift = n - m;
+  QS_LAUNCH("tile_pass_batched", s, (tile_kernel_batched<R, kDiag>), dim3(count << shift), dim3(tile_threads(m)),
+            tile_lds(m, sizeof(cplx<R>)), s, descs_dev, shift);
+}
+
+template <class R>
+void launch_tile_batched(const TileKArgs<R>* descs_dev, uint32_t count, uint32_t n, uint32_t m, bool has_diag,
+                         hipStream_t s) {
+  if (has_diag)
+    launch_tile_batched_k<R, true>(descs_dev, count, n, m, s);
+  else
+    launch_tile_batched_k<R, false>(descs_dev, count, n, m, s);
+}
+
+template <class R, bool kDiag>
+void launch_tile_k(const TileKArgs<R>& A, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)tile_kernel<R, kDiag>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   // one thread per register group of a round, between 64 and 512 threads
-  uint32_t threads = M >> RB;
-  threads = threads < 64 ? 64 : (threads > (uint32_t)kMaxThreads ? (uint32_t)kMaxThreads : threads);
   const uint32_t n_cosets = 1u << (A.n - A.m);
-  QS_LAUNCH("tile_pass", s, tile_kernel<R>, dim3(n_cosets), dim3(threads), lds, s, A);
+  QS_LAUNCH("tile_pass", s, (tile_kernel<R, kDiag>), dim3(n_cosets), dim3(tile_threads(A.m)),
+            tile_lds(A.m, sizeof(cplx<R>)), s, A);
+}
+
+template <class R>
+void launch_tile(const TileKArgs<R>& A, hipStream_t s) {
+  if (A.diag != nullptr) {
+    launch_tile_k<R, true>(A, s);
+  } else if constexpr (sizeof(R) == 4) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      hipFuncSetAttribute((const void*)tile_kernel_c64, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      attr_set = true;
+    }
+    QS_LAUNCH("tile_pass", s, tile_kernel_c64, dim3(1u << (A.n - A.m)), dim3(tile_threads(A.m)),
+              tile_lds(A.m, sizeof(cplx<R>)), s, A);
+  } else {
+    launch_tile_k<R, false>(A, s);
+  }
 }
 
 template void launch_tile<float>(const TileKArgs<float>&, hipStream_t);
 template void launch_tile<double>(const TileKArgs<double>&, hipStream_t);
+template void launch_tile_batched<float>(const TileKArgs<float>*, uint32_t, uint32_t, uint32_t, bool, hipStream_t);
+template void launch_tile_batched<double>(const TileKArgs<double>*, uint32_t, uint32_t, uint32_t, bool, hipStream_t);
 
 }  // namespace qs

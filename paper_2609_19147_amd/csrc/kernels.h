@@ -52,13 +52,35 @@ struct TileKArgs {
   const TileRound* rounds;
   const TileOp* ops;
   const cplx<R>* coef;
-  DiagDev diag[kMaxDiagSlots];
+  const DiagDev* diag;  // the pass's diagonal slots (device memory), or null
   uint32_t L, a, h, m;
   uint32_t n_rounds;
   uint32_t n;
   double scale;  // 2^(-k/2) for the pass's k unscaled butterflies
 };
 template <class R> void launch_tile(const TileKArgs<R>& A, hipStream_t s);
+// count instances of one geometry (n qubits, m tile bits), descriptors in device
+// memory; has_diag: some descriptor has a diagonal slot.
+template <class R>
+void launch_tile_batched(const TileKArgs<R>* descs_dev, uint32_t count, uint32_t n, uint32_t m, bool has_diag,
+                         hipStream_t s);
+
+// Diagonal observable value(i) = c0 + sum_g w[g] count_g(i) (count terms as in
+// the phase layers), expectation sum_i |psi_i|^2 value(i), for count instances
+// of n qubits at once; out[k] receives instance k's expectation (device).
+struct ObsDev {
+  const void* psi;  // cplx<R>*
+  const DiagTerm* terms;
+  const DiagGroup* groups;
+  const double* w;
+  int32_t n_groups;
+  int32_t pad;
+  double c0;
+};
+template <class R>
+void launch_batch_observable(const ObsDev* obs_dev, uint32_t count, uint32_t n, double* partials, double* out,
+                             hipStream_t s);
+size_t batch_observable_partials(uint32_t count, uint32_t n);  // doubles needed for partials
 
 template <class R>
 void launch_diag(cplx<R>* psi, int n, const DiagDev& D, hipStream_t s);
@@ -68,7 +90,7 @@ void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s
 
 // ---- FP64 reductions (deterministic: fixed grid, fixed combination order) ----
 // Each writes NV (sum, compensation) pairs per block into partials and then
-// folds them into out[NV] (device) with a single-block kernel.
+// folds them into out[NV] (device), one workgroup per output.
 constexpr int kRedBlocks = 1024;
 constexpr int kMaxTermsPerLaunch = 8;
 template <class R> void launch_norm2(const cplx<R>* psi, uint64_t N, double* partials, double* out, hipStream_t s);
@@ -85,5 +107,21 @@ void launch_expect_z(const cplx<R>* psi, int n, const uint32_t* z, int nt, doubl
 template <class R>
 void launch_expect_x(const cplx<R>* psi, int n, uint32_t x, const uint32_t* z, const int* ny, int nt,
                      double* partials, double* out, hipStream_t s);
+
+// ---- adjoint support ----
+// out_i = sum_t c_t (-1)^{popcount((i ^ x_t) & z_t)} psi_{i ^ x_t}, terms sorted by x
+// (c_t complex: the Pauli coefficient times i^{#Y}); arrays in device memory.
+template <class R>
+void launch_pauli_apply(const cplx<R>* psi, cplx<R>* out, int n, const uint32_t* x_dev, const uint32_t* z_dev,
+                        const double* c_dev, int n_terms, hipStream_t s);
+// rho[r][c] = sum over pairs on bit b of conj(lam_r) phi_c (8 doubles: re/im of
+// rho00, rho01, rho10, rho11).
+template <class R>
+void launch_pair_rho(const cplx<R>* phi, const cplx<R>* lam, int n, int b, double* partials, double* out,
+                     hipStream_t s);
+// out[g] = sum_x count_g(x) Im(conj(lam_x) phi_x) for groups [g0, g0 + ng), ng <= 8.
+template <class R>
+void launch_diag_grad(const cplx<R>* phi, const cplx<R>* lam, int n, const DiagDev& D, int g0, int ng,
+                      double* partials, double* out, hipStream_t s);
 
 }  // namespace qs

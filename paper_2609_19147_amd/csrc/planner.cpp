@@ -307,6 +307,26 @@ static DiagIR build_diag(const std::vector<DiagTermIR>& raw, const Angle& global
   return d;
 }
 
+DiagIR diag_observable(int n, const qs_pauli* terms, size_t n_terms) {
+  // c (-1)^{parity(i & z)} = c - 2 c parity(i & z): count terms weighted -2c
+  std::vector<DiagTermIR> raw;
+  Angle gl;
+  for (size_t t = 0; t < n_terms; ++t) {
+    const qs_pauli& P = terms[t];
+    if (P.x_mask) fail(QS_EINVAL, "diagonal observable with an X or Y factor");
+    if (!std::isfinite(P.coeff)) fail(QS_EINVAL, "non-finite coefficient");
+    if (n < 64 && (P.z_mask >> n)) fail(QS_EINVAL, "Pauli mask out of range");
+    uint32_t z = 0;
+    for (int q = 0; q < n; ++q)
+      if ((P.z_mask >> q) & 1) z |= 1u << (n - 1 - q);
+    gl.c0 += P.coeff;
+    int pc = __builtin_popcount(z);
+    if (pc == 0) continue;
+    raw.push_back({pc == 1 ? 0 : pc == 2 ? 1 : 4, z, Angle{-2.0 * P.coeff, {}}});
+  }
+  return build_diag(raw, gl);
+}
+
 DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj) {
   DiagNumeric out;
   double gl = d.global.eval(params);
@@ -1121,6 +1141,10 @@ std::vector<cd> op_matrix(const PlanIR& P, const OpIR& op, const std::vector<dou
 
 std::vector<cd> pass_coefficients(const PlanIR& P, const TilePassIR& T, const std::vector<double>& params) {
   std::vector<cd> coef((size_t)T.n_coef);
+  auto opm = [&](int k) {
+    std::vector<cd> U = op_matrix(P, P.ops[T.op_src[k]], params);
+    return T.inverse ? dagger(U, 2) : U;
+  };
   for (const TileRound& r : T.rounds) {
     if (r.type != RT_MAT4) continue;
     for (int b = 0; b < 4; ++b) {
@@ -1131,7 +1155,7 @@ std::vector<cd> pass_coefficients(const PlanIR& P, const TilePassIR& T, const st
       const TileOp& op = T.ops[k];
       std::vector<cd> U;
       if (op.kind == OP_H) U = {1.0, 1.0, 1.0, -1.0};  // unscaled butterfly
-      else U = op_matrix(P, P.ops[T.op_src[k]], params);
+      else U = opm(k);
       if (op.kind == OP_DIAG) U = {U[0], 0.0, 0.0, U[3]};
       for (int e = 0; e < 4; ++e) coef[r.coef4 + 4 * op.rbit + e] = U[e];
     }
@@ -1139,15 +1163,14 @@ std::vector<cd> pass_coefficients(const PlanIR& P, const TilePassIR& T, const st
   for (size_t k = 0; k < T.ops.size(); ++k) {
     const TileOp& op = T.ops[k];
     if (T.op_src[k] < 0) continue;
-    const OpIR& o = P.ops[T.op_src[k]];
     if (op.kind == OP_MAT) {
-      auto U = op_matrix(P, o, params);
+      auto U = opm((int)k);
       for (int e = 0; e < 4; ++e) coef[op.coef + e] = U[e];
     } else if (op.kind == OP_DIAG) {
-      auto U = op_matrix(P, o, params);
+      auto U = opm((int)k);
       coef[op.coef] = U[0];
       coef[op.coef + 1] = U[3];
-    } else if (op.kind == OP_QFT) {
+    } else if (op.kind == OP_QFT || op.kind == OP_QFT_INV) {
       // intra-round twiddles: register bits below the op's bit
       const TileRound* R = nullptr;
       for (auto& r : T.rounds)
@@ -1201,6 +1224,221 @@ std::vector<cd> pass_coefficients_device(const PlanIR& P, const TilePassIR& T, c
     }
   }
   return coef;
+}
+
+// ---------------------------------------------------------------- adjoint support
+std::vector<cd> dagger(const std::vector<cd>& M, int d) {
+  std::vector<cd> R((size_t)d * d);
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) R[(size_t)r * d + c] = std::conj(M[(size_t)c * d + r]);
+  return R;
+}
+
+static TilePassIR invert_pass(const PlanIR& P, const TilePassIR& F) {
+  TilePassIR T;
+  T.L = F.L;
+  T.a = F.a;
+  T.h = F.h;
+  T.inverse = true;
+  T.diag_slots = F.diag_slots;
+  T.n_butterfly = F.n_butterfly;
+  T.scale = F.scale;
+  int carry_diag = -1;  // a forward round's diagonal, undone after its inverted ops
+  auto push_round = [&](const TileRound& src, std::vector<int> fwd_ops, int diag_before) {
+    TileRound r = src;
+    r.op_begin = (int32_t)T.ops.size();
+    for (auto it = fwd_ops.rbegin(); it != fwd_ops.rend(); ++it) {
+      TileOp op = F.ops[*it];
+      if (op.kind == OP_QFT) op.kind = OP_QFT_INV;
+      op.square = 0;
+      op.coef = T.n_coef;
+      if (op.kind == OP_MAT) T.n_coef += 4;
+      else if (op.kind == OP_DIAG) T.n_coef += 2;
+      else if (op.kind == OP_QFT_INV) T.n_coef += 1 << op.rbit;
+      T.ops.push_back(op);
+      T.op_src.push_back(F.op_src[*it]);
+    }
+    r.op_end = (int32_t)T.ops.size();
+    r.diag = diag_before;
+    r.diag_conj = 1;
+    r.type = classify_round(P, T, r);
+    r.coef4 = -1;
+    if (r.type == RT_GENERIC) {
+      // split, as in finalize_pass
+      int k = r.op_begin;
+      bool first = true;
+      while (k < r.op_end) {
+        TileRound q = r;
+        q.diag = first ? r.diag : -1;
+        first = false;
+        q.op_begin = k;
+        if (T.ops[k].kind == OP_QFT_INV) {
+          q.op_end = k + 1;
+          q.type = RT_QFT1;
+        } else {
+          uint32_t seen = 0;
+          int e = k;
+          while (e < r.op_end && T.ops[e].kind != OP_QFT_INV && !((seen >> T.ops[e].rbit) & 1)) {
+            seen |= 1u << T.ops[e].rbit;
+            ++e;
+          }
+          q.op_end = e;
+          if (e - k == 1) {
+            q.type = RT_OP1;
+          } else {
+            q.type = RT_MAT4;
+            q.coef4 = T.n_coef;
+            T.n_coef += 16;
+          }
+        }
+        k = q.op_end;
+        T.rounds.push_back(q);
+      }
+      return;
+    }
+    if (r.type == RT_MAT4) {
+      r.coef4 = T.n_coef;
+      T.n_coef += 16;
+    }
+    T.rounds.push_back(r);
+  };
+  for (auto it = F.rounds.rbegin(); it != F.rounds.rend(); ++it) {
+    std::vector<int> ops;
+    for (int k = it->op_begin; k < it->op_end; ++k) ops.push_back(k);
+    push_round(*it, ops, carry_diag);
+    carry_diag = it->diag;
+  }
+  if (carry_diag >= 0) push_round(F.rounds.front(), {}, carry_diag);
+  return T;
+}
+
+static Gf2IR invert_gf2(int n, const Gf2IR& G) {
+  // forward: out[y] = in[A y ^ c'];  inverse: out[x] = in[M x ^ M c'], M = A^{-1}
+  std::vector<uint32_t> aug(n);  // rows of [A | I]
+  std::vector<uint32_t> A = G.rows, inv(n);
+  for (int r = 0; r < n; ++r) inv[r] = 1u << r;
+  for (int c = 0; c < n; ++c) {
+    int piv = -1;
+    for (int r = c; r < n; ++r)
+      if ((A[r] >> c) & 1) { piv = r; break; }
+    if (piv < 0) fail(QS_EINVAL, "permutation block is not invertible");
+    std::swap(A[c], A[piv]);
+    std::swap(inv[c], inv[piv]);
+    for (int r = 0; r < n; ++r)
+      if (r != c && ((A[r] >> c) & 1)) { A[r] ^= A[c]; inv[r] ^= inv[c]; }
+  }
+  Gf2IR R;
+  R.rows = inv;
+  uint32_t c2 = 0;
+  for (int r = 0; r < n; ++r) c2 |= (uint32_t)(__builtin_popcount(inv[r] & G.cprime) & 1) << r;
+  R.cprime = c2;
+  R.gates = G.gates;
+  return R;
+}
+
+PlanIR invert_plan(const PlanIR& F) {
+  PlanIR P;
+  P.n = F.n;
+  P.n_params = F.n_params;
+  P.opt = F.opt;
+  P.gates = F.gates;
+  P.diags = F.diags;
+  P.ops = F.ops;
+  P.tile_bits = F.tile_bits;
+  P.low_bits = F.low_bits;
+  for (auto it = F.layers.rbegin(); it != F.layers.rend(); ++it) {
+    LayerIR L = *it;
+    if (L.kind == L_TILE) {
+      L.index = (int32_t)P.passes.size();
+      P.passes.push_back(invert_pass(F, F.passes[it->index]));
+    } else if (L.kind == L_GF2) {
+      L.index = (int32_t)P.gf2s.size();
+      P.gf2s.push_back(invert_gf2(F.n, F.gf2s[it->index]));
+    } else {
+      L.inverse = 1;
+    }
+    P.layers.push_back(L);
+  }
+  return P;
+}
+
+// u^dagger du/dangle for the rotation kinds (angle derivative, before `scale`)
+static std::vector<cd> gen_of(int kind) {
+  const cd mi(0, -0.5);
+  switch (kind) {
+    case QS_GATE_RX: return {0, mi, mi, 0};
+    case QS_GATE_RY: return {0, -0.5, 0.5, 0};  // -(i/2) Y
+    case QS_GATE_RZ: return {mi, 0, 0, -mi};
+    case QS_GATE_P: return {0, 0, 0, cd(0, 1)};
+    default: fail(QS_EUNSUPPORTED, "adjoint gradient for this parametrised gate kind");
+  }
+}
+
+std::vector<std::vector<GradEntry>> grad_entries(const PlanIR& P, const std::vector<double>& params) {
+  std::vector<std::vector<GradEntry>> out(P.layers.size());
+  for (size_t li = 0; li < P.layers.size(); ++li) {
+    const LayerIR& L = P.layers[li];
+    if (L.kind == L_PLAIN) {
+      if (!P.gates[L.index].angle.is_const()) fail(QS_EUNSUPPORTED, "parameter on a gate run by the plain path");
+      continue;
+    }
+    if (L.kind == L_GF2) continue;
+    if (L.kind == L_DIAG) {
+      const DiagIR& D = P.diags[L.index];
+      for (size_t g = 0; g < D.groups.size(); ++g)
+        for (auto& t : D.groups[g].angle.lin)
+          out[li].push_back({1, -1, t.first, t.second, {0, 0, 0, 0}, L.index, (int32_t)g});
+      continue;
+    }
+    const TilePassIR& T = P.passes[L.index];
+    // device op order of the pass, with the diagonal slots in between
+    std::vector<std::pair<int, int>> seq;  // (0, op) or (1, slot)
+    for (const TileRound& r : T.rounds) {
+      if (r.diag >= 0) seq.push_back({1, r.diag});
+      for (int k = r.op_begin; k < r.op_end; ++k) seq.push_back({0, k});
+    }
+    for (size_t pos = 0; pos < seq.size(); ++pos) {
+      if (seq[pos].first == 1) {
+        const DiagIR& D = P.diags[T.diag_slots[seq[pos].second]];
+        bool has = false;
+        for (auto& G : D.groups) has = has || !G.angle.is_const();
+        if (has) fail(QS_EUNSUPPORTED, "parametrised diagonal fused inside a tile pass");
+        continue;
+      }
+      const int k = seq[pos].second;
+      const TileOp& op = T.ops[k];
+      if (T.op_src[k] < 0) continue;
+      const OpIR& o = P.ops[T.op_src[k]];
+      bool param = false;
+      for (int gi : o.gates) param = param || !P.gates[gi].angle.is_const();
+      if (!param) continue;
+      // every earlier op of the pass must commute with an operator on this bit
+      for (size_t q = 0; q < pos; ++q) {
+        bool clash = false;
+        if (seq[q].first == 1) {
+          clash = (P.diags[T.diag_slots[seq[q].second]].support >> op.sbit) & 1;
+        } else {
+          const TileOp& e = T.ops[seq[q].second];
+          clash = e.sbit == op.sbit || ((e.kind == OP_QFT || e.kind == OP_QFT_INV) && e.sbit > op.sbit);
+        }
+        if (clash) fail(QS_EUNSUPPORTED, "parametrised window follows a non-commuting op in its pass");
+      }
+      std::vector<cd> V = {1, 0, 0, 1};  // product of the window's gates before gate m
+      for (size_t m = 0; m < o.gates.size(); ++m) {
+        const NGate& g = P.gates[o.gates[m]];
+        if (!g.angle.is_const()) {
+          std::vector<cd> G = gen_of(g.kind);
+          std::vector<cd> K = mul2(dagger(V, 2), mul2(G, V));
+          for (auto& t : g.angle.lin) {
+            GradEntry e{0, op.sbit, t.first, t.second, {K[0], K[1], K[2], K[3]}, -1, -1};
+            out[li].push_back(e);
+          }
+        }
+        V = mul2(gate_matrix(g, params), V);
+      }
+    }
+  }
+  return out;
 }
 
 // ---------------------------------------------------------------- describe
@@ -1259,7 +1497,7 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
     if (li) o << ",";
     const LayerIR& L = P.layers[li];
     if (L.kind == L_DIAG) {
-      o << "{\"kind\":\"diag\",\"diag\":";
+      o << "{\"kind\":\"diag\",\"inverse\":" << L.inverse << ",\"diag\":";
       describe_diag(o, P.diags[L.index], params, bound);
       o << "}";
     } else if (L.kind == L_GF2) {
@@ -1269,12 +1507,14 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
       o << "],\"cprime\":" << G.cprime << ",\"n_gates\":" << G.gates.size() << "}";
     } else if (L.kind == L_PLAIN) {
       const NGate& g = P.gates[L.index];
-      o << "{\"kind\":\"plain\",\"gate\":" << L.index << ",\"gate_kind\":" << g.kind << ",\"bits\":[";
+      o << "{\"kind\":\"plain\",\"inverse\":" << L.inverse << ",\"gate\":" << L.index
+        << ",\"gate_kind\":" << g.kind << ",\"bits\":[";
       for (size_t b = 0; b < g.bits.size(); ++b) { if (b) o << ","; o << g.bits[b]; }
       o << "]}";
     } else {
       const TilePassIR& T = P.passes[L.index];
-      o << "{\"kind\":\"tile\",\"L\":" << T.L << ",\"a\":" << T.a << ",\"h\":" << T.h << ",\"rounds\":[";
+      o << "{\"kind\":\"tile\",\"inverse\":" << (T.inverse ? 1 : 0) << ",\"L\":" << T.L << ",\"a\":" << T.a
+        << ",\"h\":" << T.h << ",\"rounds\":[";
       for (size_t r = 0; r < T.rounds.size(); ++r) {
         auto& R = T.rounds[r];
         if (r) o << ",";
@@ -1291,7 +1531,8 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
         o << "{\"kind\":" << op.kind << ",\"bit\":" << op.sbit << ",\"rbit\":" << op.rbit
           << ",\"square\":" << op.square;
         if (bound) {
-          int nc = op.kind == OP_MAT ? 4 : op.kind == OP_DIAG ? 2 : op.kind == OP_QFT ? (1 << op.rbit) : 0;
+          int nc = op.kind == OP_MAT ? 4 : op.kind == OP_DIAG ? 2
+                   : (op.kind == OP_QFT || op.kind == OP_QFT_INV) ? (1 << op.rbit) : 0;
           o << ",\"coef\":[";
           for (int e = 0; e < nc; ++e) { if (e) o << ","; jc(o, coef[op.coef + e]); }
           o << "]";

@@ -98,6 +98,7 @@ struct TilePassIR {
   int32_t n_coef = 0;
   int32_t n_butterfly = 0;  // unscaled H / QFT butterflies in the pass
   double scale = 1.0;       // 2^(-n_butterfly/2), applied at the store
+  bool inverse = false;     // ops are inverses of their sources (U^dagger, QFT^-1, conj diagonals)
 };
 
 struct Gf2IR {
@@ -111,6 +112,7 @@ enum LayerKind : int32_t { L_DIAG = 0, L_TILE = 1, L_GF2 = 2, L_PLAIN = 3 };
 struct LayerIR {
   int32_t kind;
   int32_t index;  // into diags / passes / gf2s / plain gate index (into Plan::gates)
+  int32_t inverse = 0;  // L_DIAG / L_PLAIN: apply the inverse (conjugate / dagger)
 };
 
 struct PlanOptions {
@@ -146,6 +148,9 @@ struct DiagNumeric {
   std::vector<cd> lut;
 };
 DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj = false);
+// Diagonal observable sum_t c_t Z-string_t as value(i) = global + sum_g angle_g
+// count_g(i) (the groups' "angles" are the real weights -2 c).
+DiagIR diag_observable(int n, const qs_pauli* terms, size_t n_terms);
 std::vector<cd> pass_coefficients(const PlanIR& p, const TilePassIR& t, const std::vector<double>& params);
 // Device form of a pass's rounds and coefficients (RX / RY refinements applied).
 std::vector<cd> pass_coefficients_device(const PlanIR& p, const TilePassIR& t, const std::vector<double>& params,
@@ -155,5 +160,27 @@ std::vector<cd> op_matrix(const PlanIR& p, const OpIR& op, const std::vector<dou
 Gf2Args gf2_args(int n, const Gf2IR& g, int c_bits);
 
 std::string describe_json(const PlanIR& p, const std::vector<double>& params, bool bound);
+
+// ---- adjoint support ------------------------------------------------------------
+// The inverse plan: layers in reverse order, each replaced by its inverse.
+PlanIR invert_plan(const PlanIR& p);
+// Dagger of a gate's matrix.
+std::vector<cd> dagger(const std::vector<cd>& M, int d);
+
+// One parameter occurrence of a forward layer: dE/dparam += coef * 2 Re <lambda|K|phi>
+// evaluated on the states before the layer.  kind 0: K is a 2x2 matrix on state
+// bit `bit`; kind 1: K = i * count_g (diagonal group g of diag layer `diag`).
+struct GradEntry {
+  int32_t kind;
+  int32_t bit;
+  int32_t param;
+  double coef;
+  cd K[4];
+  int32_t diag;
+  int32_t group;
+};
+// Entries of every forward layer (index = forward layer).  Fails with
+// QS_EUNSUPPORTED for parameters the adjoint sweep cannot isolate.
+std::vector<std::vector<GradEntry>> grad_entries(const PlanIR& p, const std::vector<double>& params);
 
 }  // namespace qs

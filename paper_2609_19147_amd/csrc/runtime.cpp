@@ -45,6 +45,7 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
   d.pass_rounds.assign(P.passes.size(), 0);
   d.pass_ops.assign(P.passes.size(), 0);
   d.pass_coef.assign(P.passes.size(), 0);
+  d.pass_diag.assign(P.passes.size(), 0);
   for (size_t i = 0; i < P.passes.size(); ++i) {
     const TilePassIR& T = P.passes[i];
     std::vector<TileRound> rounds;
@@ -52,8 +53,31 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
     d.pass_rounds[i] = b.put(rounds);
     d.pass_ops[i] = b.put(T.ops);
     d.pass_coef[i] = b.put(cast<R>(coef));
+    // slot descriptors hold device addresses: filled in once the blob has one
+    if (!T.diag_slots.empty()) d.pass_diag[i] = b.put(std::vector<DiagDev>(T.diag_slots.size()));
   }
   b.put(std::vector<double>(2, 0.0));  // never zero bytes
+}
+
+DiagDev diag_dev(const PlanDev& d, const char* base, int i, bool conj) {
+  DiagDev D;
+  D.terms = (const DiagTerm*)(base + d.diag_terms[i]);
+  D.groups = (const DiagGroup*)(base + d.diag_groups[i]);
+  D.lut = base + d.diag_lut[i];
+  D.n_groups = d.diag_ngroups[i];
+  D.conj = conj ? 1 : 0;
+  return D;
+}
+
+// The per-pass diagonal slot arrays, pointing into the blob at device address base.
+void fill_slots(const PlanIR& P, const PlanDev& d, const char* base, Blob& b) {
+  for (size_t i = 0; i < P.passes.size(); ++i) {
+    const TilePassIR& T = P.passes[i];
+    for (size_t k = 0; k < T.diag_slots.size(); ++k) {
+      const DiagDev D = diag_dev(d, base, T.diag_slots[k], T.inverse != 0);
+      std::memcpy(b.bytes.data() + d.pass_diag[i] + k * sizeof(DiagDev), &D, sizeof D);
+    }
+  }
 }
 
 }  // namespace
@@ -78,9 +102,25 @@ const PlanDev& qs_plan::device_for(qs_dtype dt) {
   }
   if (!d.blob) check_hip(hipMalloc(&d.blob, b.bytes.size()), "hipMalloc(plan tables)");
   d.bytes = b.bytes.size();
+  fill_slots(ir, d, (const char*)d.blob, b);
   check_hip(hipMemcpy(d.blob, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice), "hipMemcpy(plan tables)");
   d.valid = true;
   return d;
+}
+
+qs_plan& qs_plan::inverse() {
+  if (!inv) {
+    inv = new qs_plan();
+    inv->ir = invert_plan(ir);
+    inv_version = version + 1;  // force a parameter copy below
+  }
+  if (inv_version != version) {
+    inv->params = params;
+    inv->bound = bound;
+    inv->refresh_device();
+    inv_version = version;
+  }
+  return *inv;
 }
 
 void qs_plan::refresh_device() {
@@ -99,16 +139,6 @@ namespace qs {
 
 namespace {
 
-DiagDev diag_dev(const PlanDev& d, const char* base, int i, bool conj) {
-  DiagDev D;
-  D.terms = (const DiagTerm*)(base + d.diag_terms[i]);
-  D.groups = (const DiagGroup*)(base + d.diag_groups[i]);
-  D.lut = base + d.diag_lut[i];
-  D.n_groups = d.diag_ngroups[i];
-  D.conj = conj ? 1 : 0;
-  return D;
-}
-
 template <class R>
 void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
   const PlanDev& d = p.device_for(s.dtype);
@@ -119,7 +149,7 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
     const LayerIR& L = P.layers[li];
     switch (L.kind) {
       case L_DIAG:
-        launch_diag<R>((cplx<R>*)s.cur_ptr(), s.n, diag_dev(d, base, L.index, false), s.stream);
+        launch_diag<R>((cplx<R>*)s.cur_ptr(), s.n, diag_dev(d, base, L.index, L.inverse != 0), s.stream);
         break;
       case L_TILE: {
         const TilePassIR& T = P.passes[L.index];
@@ -130,7 +160,7 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
         A.rounds = (const TileRound*)(base + d.pass_rounds[L.index]);
         A.ops = (const TileOp*)(base + d.pass_ops[L.index]);
         A.coef = (const cplx<R>*)(base + d.pass_coef[L.index]);
-        for (size_t k = 0; k < T.diag_slots.size(); ++k) A.diag[k] = diag_dev(d, base, T.diag_slots[k], false);
+        A.diag = d.pass_diag[L.index] ? (const DiagDev*)(base + d.pass_diag[L.index]) : nullptr;
         A.L = T.L;
         A.a = T.a;
         A.h = T.h;
@@ -148,7 +178,7 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
         break;
       }
       case L_PLAIN:
-        apply_plain_gate(s, P.gates[L.index], p.params);
+        apply_plain_gate(s, P.gates[L.index], p.params, L.inverse != 0);
         break;
       default:
         fail(QS_EINVAL, "internal: unknown layer kind");
@@ -157,10 +187,11 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
 }
 
 template <class R>
-void plain_t(qs_state& s, const NGate& g, const std::vector<double>& params) {
+void plain_t(qs_state& s, const NGate& g, const std::vector<double>& params, bool inverse) {
   cplx<R>* psi = (cplx<R>*)s.cur_ptr();
   const int n = s.n;
   std::vector<cd> M = gate_matrix(g, params);
+  if (inverse) M = dagger(M, 1 << (int)g.bits.size());
   std::vector<cplx<R>> m = cast<R>(M);
   const auto& b = g.bits;
   switch (g.kind) {
@@ -240,9 +271,9 @@ void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last) {
   else apply_layers_t<double>(s, p, first, last);
 }
 
-void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params) {
-  if (s.dtype == QS_C64) plain_t<float>(s, g, params);
-  else plain_t<double>(s, g, params);
+void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params, bool inverse) {
+  if (s.dtype == QS_C64) plain_t<float>(s, g, params, inverse);
+  else plain_t<double>(s, g, params, inverse);
 }
 
 double state_norm2(qs_state& s) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <complex>
+#include <string>
 #include <vector>
 
 #include "kernels.h"
@@ -42,10 +43,12 @@ struct PlanDev {
   std::vector<size_t> diag_terms, diag_groups, diag_lut;
   std::vector<int> diag_ngroups;
   std::vector<size_t> pass_rounds, pass_ops, pass_coef;
+  std::vector<size_t> pass_diag;  // per pass: its diagonal slots as DiagDev[] (0: none)
   std::vector<size_t> plain_mat;  // per layer (only dense plain gates), else 0
 };
 
 void check_hip(hipError_t e, const char* what);
+extern thread_local std::string g_last_error;
 
 }  // namespace qs
 
@@ -55,16 +58,20 @@ struct qs_plan {
   bool bound = false;
   qs::PlanDev dev[2];
   std::vector<qs::Gf2Args> gf2;  // host-side kernel arguments per GF(2) layer
+  uint64_t version = 0;          // bumped whenever the parameters change
+  qs_plan* inv = nullptr;        // inverse plan (adjoint sweeps), built on demand
+  uint64_t inv_version = 0;
 
   void refresh_device();  // rebuild the tables of every precision already on the device
   const qs::PlanDev& device_for(qs_dtype dt);
+  qs_plan& inverse();     // the inverse plan with the current parameters
   ~qs_plan();
 };
 
 namespace qs {
 
 void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last);
-void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params);
+void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params, bool inverse = false);
 double state_norm2(qs_state& s);
 std::complex<double> state_overlap(qs_state& a, qs_state& b);
 double state_infidelity(qs_state& a, qs_state& b);

@@ -56,7 +56,8 @@ def apply_bit_2x2(psi, n, b, U):
 def apply_layer(psi, n, L, stream, params):
     k = L["kind"]
     if k == "diag":
-        return psi * diag_phase(L["diag"], n)
+        ph = diag_phase(L["diag"], n)
+        return psi * (np.conj(ph) if L.get("inverse") else ph)
     if k == "gf2":
         rows = [np.uint64(r) for r in L["rows"]]
         y = np.arange(1 << n, dtype=np.uint64)
@@ -66,13 +67,20 @@ def apply_layer(psi, n, L, stream, params):
         src ^= np.uint64(L["cprime"])
         return psi[src.astype(np.int64)]
     if k == "plain":
-        return sv.apply_gate(psi, n, stream[L["gate"]], params)
+        g = stream[L["gate"]]
+        if L.get("inverse"):
+            from oracle import gates as og
+            U = og.matrix(g, params).conj().T
+            from workloads import G
+            g = G("U" if len(g.wires) == 1 else "UNITARY", *g.wires, mat=U)
+        return sv.apply_gate(psi, n, g, params)
     assert k == "tile"
     psi = psi.copy()
     r2 = 1 / math.sqrt(2)
     for R in L["rounds"]:
         if R["diag"] >= 0:
-            psi *= diag_phase(L["diags"][R["diag"]], n)
+            ph = diag_phase(L["diags"][R["diag"]], n)
+            psi *= np.conj(ph) if L.get("inverse") else ph
         for op in L["ops"][R["ops"][0]:R["ops"][1]]:
             b = op["bit"]
             c = [complex(a, bb) for a, bb in op.get("coef", [])]
@@ -89,6 +97,13 @@ def apply_layer(psi, n, L, stream, params):
                 tw = np.exp(1j * math.pi * low / (1 << b))
                 sel = ((i >> b) & 1) == 1
                 psi[sel] *= tw[sel]
+            elif op["kind"] == 4:  # inverse QFT stage: undo the twiddle, then the butterfly
+                i = np.arange(1 << n, dtype=np.int64)
+                low = i & ((1 << b) - 1)
+                tw = np.exp(-1j * math.pi * low / (1 << b))
+                sel = ((i >> b) & 1) == 1
+                psi[sel] *= tw[sel]
+                apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
             else:
                 raise AssertionError(f"unexpected op kind {op['kind']}")
     return psi

@@ -1,0 +1,96 @@
+"""Batched ragged execution (one recorded HIP graph) against the oracle and
+against the per-instance paths."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import metrics, statevec as sv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qs():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2609_19147_amd as q
+    return q
+
+
+def qaoa_batch(qs, count, seed, depth, n_choices, dtype="c64"):
+    insts = W.qaoa_instances(count, seed, depth=depth, n_choices=n_choices)
+    plans = []
+    for inst in insts:
+        p = qs.Plan(inst.n, W.qaoa_stream(inst, param_offset=0, h_layer=False), n_params=2 * depth,
+                    max_tile_bits=min(13, max(6, (inst.n + 4) // 2)))
+        params = np.empty(2 * depth)
+        params[0::2] = inst.gammas
+        params[1::2] = inst.betas
+        p.set_params(params)
+        plans.append(p)
+    return insts, plans, qs.Batch(plans, init="plus", dtype=dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batched_qaoa_matches_oracle(qs, dtype):
+    insts, plans, B = qaoa_batch(qs, 12, 7, 2, (8, 10, 12), dtype)
+    B.run()
+    got = B.expect_diag([W.maxcut_terms(i.edges) for i in insts])
+    bar = 1e-10 if dtype == "c64" else 1e-24
+    for k, inst in enumerate(insts):
+        params = np.empty(4)
+        params[0::2] = inst.gammas
+        params[1::2] = inst.betas
+        ref = sv.run(sv.basis(inst.n, 0), inst.n, W.qaoa_stream(inst, param_offset=0), params)
+        c_ref = sv.expect(ref, inst.n, W.maxcut_terms(inst.edges))
+        assert abs(got[k] - c_ref) < (1e-5 if dtype == "c64" else 1e-11), (k, got[k], c_ref)
+        assert metrics.infidelity(B.state(k).download(), ref) <= bar
+
+
+def test_batch_equals_per_instance_paths_and_replays(qs):
+    insts, plans, B = qaoa_batch(qs, 9, 3, 3, (10, 12, 14))
+    obs = [W.maxcut_terms(i.edges) for i in insts]
+    B.run()
+    first = B.expect_diag(obs)
+    for k, inst in enumerate(insts):
+        st = qs.State(inst.n, "c64", init="plus")
+        qs.apply(st, plans[k])
+        assert abs(qs.expect(st, obs[k]) - first[k]) < 1e-12 * max(1, abs(first[k])) + 1e-9
+    # replays of the recorded graph give the same numbers, bit for bit
+    for _ in range(3):
+        B.run()
+        assert np.array_equal(B.expect_diag(obs), first)
+    # re-bound parameters are picked up by the same graph after refresh
+    params = np.linspace(0.1, 0.8, 6)
+    for p in plans:
+        p.set_params(params)
+    B.refresh()
+    B.run()
+    again = B.expect_diag(obs)
+    for k, inst in enumerate(insts):
+        ref = sv.run(sv.basis(inst.n, 0), inst.n, W.qaoa_stream(inst, param_offset=0), params)
+        assert abs(again[k] - sv.expect(ref, inst.n, obs[k])) < 1e-5
+
+
+def test_p1_closed_form_whole_batch(qs):
+    # p = 1 on 3-regular graphs: the Wang-Hadfield-Jiang-Rieffel closed form
+    from tests.test_oracle_pins import qaoa_p1_edge
+    insts, plans, B = qaoa_batch(qs, 24, 11, 1, (16, 18, 20))
+    B.run()
+    got = B.expect_diag([W.maxcut_terms(i.edges) for i in insts])
+    for k, inst in enumerate(insts):
+        adj = {q: set() for q in range(inst.n)}
+        for u, v in inst.edges:
+            adj[u].add(v)
+            adj[v].add(u)
+        ref = sum(qaoa_p1_edge(adj, u, v, inst.gammas[0], inst.betas[0]) for u, v in inst.edges)
+        assert abs(got[k] - ref) < 2e-5, (k, got[k], ref)
+
+
+def test_batch_rejects_permutation_layers(qs):
+    p = qs.Plan(6, W.ghz_stream(6))
+    with pytest.raises(qs.QsError) as e:
+        qs.Batch([p])
+    assert e.value.code == -4

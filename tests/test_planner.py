@@ -211,3 +211,33 @@ def test_twiddle_squaring_stays_inside_a_round(tile_bits):
                     prev = [o for o in ops[:k] if o["kind"] == 2]
                     assert R["type"] in (1, 2), R
                     assert prev and prev[-1]["bit"] == op["bit"] + 1 and not prev[-1]["square"]
+
+
+@pytest.mark.parametrize("case", ["qft", "mixed", "tfim", "hea", "perm", "xxyy"])
+def test_inverse_plan_undoes_the_plan(case):
+    n = 9
+    params = None
+    n_params = 0
+    if case == "qft":
+        st = W.qft_stream(n) + W.wht_stream(n)
+    elif case == "mixed":
+        st = W.random_stream(n, 150, 21)
+    elif case == "tfim":
+        st = W.tfim_strang_stream(n, 1, 0.8, 0.1, 3)
+    elif case == "hea":
+        st = W.hea_stream(n, 3)
+        params = W.hea_params(n, 3, 2)
+        n_params = len(params)
+    elif case == "perm":
+        st = W.random_perm_block(n, 50, 4) + W.wht_stream(n)
+    else:
+        st = ([W.G("RXX", q, q + 1, theta=0.3) for q in range(n - 1)]
+              + [W.G("RYY", q, q + 2, theta=0.2) for q in range(n - 2)] + W.random_stream(n, 20, 3))
+    for tb in (5, 13):
+        p = plan_of(n, st, n_params, params, max_tile_bits=tb)
+        inv = p.inverse()
+        psi0 = W.gaussian_state(n, 5)
+        fwd = run_plan(p.describe(), psi0, st, params)
+        np.testing.assert_allclose(fwd, sv.run(psi0, n, st, params), atol=1e-12)
+        back = run_plan(inv.describe(), fwd, st, params)
+        assert np.max(np.abs(back - psi0)) < 1e-12

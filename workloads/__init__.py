@@ -243,14 +243,16 @@ def qaoa_instances(count: int, seed: int, depth: int = 4,
     return out
 
 
-def qaoa_stream(inst: QaoaInstance, param_offset: int = -1) -> List[Gate]:
-    """|+>^n, then per layer exp(-i gamma C) (as RZZ(-gamma) per edge, equal to
-    the cost unitary up to a global phase) and exp(-i beta sum X) = RX(2 beta).
+def qaoa_stream(inst: QaoaInstance, param_offset: int = -1, h_layer: bool = True) -> List[Gate]:
+    """|+>^n (an H layer on |0...0>, omitted with ``h_layer=False`` for runs
+    that start from |+>^n directly), then per layer exp(-i gamma C) (as
+    RZZ(-gamma) per edge, equal to the cost unitary up to a global phase) and
+    exp(-i beta sum X) = RX(2 beta).
 
     With ``param_offset >= 0`` the angles are parameters: gamma_l at index
     offset + 2l (RZZ scale -1), beta_l at offset + 2l + 1 (RX scale 2).
     """
-    out = wht_stream(inst.n)
+    out = wht_stream(inst.n) if h_layer else []
     for l in range(len(inst.gammas)):
         if param_offset >= 0:
             out += [G("RZZ", u, v, param=param_offset + 2 * l, scale=-1.0) for u, v in inst.edges]
