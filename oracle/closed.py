@@ -8,6 +8,10 @@ layers have plain per-output definitions that cost O(k) for a k-sparse input:
   amplitude of k appears at index rev_n(k).
 * Walsh layer H^{(x)n} (Appendix A, the H^{(x)4} closed form extended to n
   qubits): <y|H^n|j> = N^{-1/2} (-1)^{popcount(j AND y)}.
+* QFT followed by the Walsh layer (the composed circuit of the state-vector
+  benchmark): with u = rev_n(y), <y|H^n QFT|j> = N^{-1} sum_k
+  (-1)^{popcount(u AND k)} e^{2 pi i j k / N}, and the sum over the bits of k
+  factorises into prod_b (1 + (-1)^{u_b} e^{2 pi i j 2^b / N}).
 * X/CNOT/SWAP blocks (Section "Kernel Taxonomy", GF(2) affine gathers): the
   output amplitude at y is the input amplitude at the index obtained by
   pushing y back through the gates in reverse order (each is an
@@ -59,6 +63,24 @@ def wht_sparse(n: int, idx: np.ndarray, coeffs: np.ndarray, ys: np.ndarray) -> n
         sign = 1.0 - 2.0 * popcount_parity(ys & np.uint64(j)).astype(np.float64)
         out += c * sign
     return out / math.sqrt(1 << n)
+
+
+def qft_wht_sparse(n: int, idx: np.ndarray, coeffs: np.ndarray, ys: np.ndarray) -> np.ndarray:
+    """Output amplitudes at ``ys`` of the QFT stream followed by the Walsh
+    layer, applied to sum_k coeffs[k] |idx[k]> (product form above)."""
+    N = 1 << n
+    u = bit_reverse(ys, n)
+    out = np.zeros(len(ys), dtype=np.complex128)
+    for j, c in zip(np.asarray(idx, dtype=np.uint64), coeffs):
+        prod = np.ones(len(ys), dtype=np.complex128)
+        for b in range(n):
+            # (j * 2^b) mod N exactly in integers
+            m = (int(j) << b) & (N - 1)
+            e = np.exp(2j * math.pi * m / N)
+            sign = 1.0 - 2.0 * ((u >> np.uint64(b)) & np.uint64(1)).astype(np.float64)
+            prod *= 1.0 + sign * e
+        out += c * prod
+    return out / N
 
 
 def perm_source(n: int, stream: Sequence, ys: np.ndarray) -> np.ndarray:

@@ -172,6 +172,30 @@ def test_wht_sparse_closed_and_involution():
     assert np.max(np.abs(back - psi0)) < 1e-14
 
 
+@pytest.mark.parametrize("n", [1, 5, 9])
+def test_qft_then_wht_product_form_matches_composition(n):
+    # brute force: the two streams applied one gate at a time
+    idx, c = W.sparse_state(n, 30 + n, k=min(5, 1 << n))
+    psi0 = np.zeros(1 << n, np.complex128)
+    psi0[idx.astype(np.int64)] = c
+    full = sv.run(psi0, n, W.qft_stream(n) + W.wht_stream(n))
+    ys = np.arange(1 << n, dtype=np.uint64)
+    assert np.max(np.abs(closed.qft_wht_sparse(n, idx, c, ys) - full)) < 1e-13
+
+
+def test_qft_then_wht_special_cases():
+    n = 12
+    ys = np.arange(1 << n, dtype=np.uint64)
+    # |0>: the QFT gives the uniform state and the Walsh layer maps it back to |0>
+    out = closed.qft_wht_sparse(n, np.array([0], np.uint64), np.array([1.0 + 0j]), ys)
+    assert abs(out[0] - 1) < 1e-14 and np.max(np.abs(out[1:])) < 1e-14
+    # |N/2>: QFT gives (-1)^k on amplitude k, stored at index rev(k), so the sign
+    # follows bit 0 of k = the top bit of the index; its Walsh image is |N/2>
+    top = 1 << (n - 1)
+    out = closed.qft_wht_sparse(n, np.array([top], np.uint64), np.array([1.0 + 0j]), ys)
+    assert abs(out[top] - 1) < 1e-13 and np.max(np.abs(np.delete(out, top))) < 1e-13
+
+
 # ---------------------------------------------------------------- permutations
 def int_replay_forward(n, stream, x):
     """Forward image g(x) of one basis index through the gates (python ints)."""
