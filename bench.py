@@ -44,8 +44,8 @@ def circuit(n):
 
 
 def kernel_source_hash(kernel: str) -> str:
-    files = {"tile_pass": ["k_tile.hip", "dev.h", "layout.h"],
-             "gf2_gather": ["k_stream.hip", "dev.h", "layout.h"]}[kernel]
+    files = {"tile_pass": ["k_tile.hip", "dev.h", "layout.h", "kernels.h"],
+             "gf2_gather": ["k_stream.hip", "dev.h", "layout.h", "kernels.h"]}[kernel]
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_2609_19147_amd", "csrc", f), "rb") as fh:
