@@ -253,6 +253,93 @@ def bench_tfim(qs, torch, n=25, steps=40):
             "max_abs_Z": float(np.max(np.abs(z)))}
 
 
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def layer_streams(n):
+    """One structured layer of each kind at n qubits (fixed angles, seeded graph)."""
+    rng = np.random.default_rng(7)
+    graph = W.random_regular3_graph(n, rng)
+    return {
+        "diag_zz_chain": [W.G("RZZ", q, q + 1, theta=-0.1) for q in range(n - 1)],
+        "diag_qaoa_cut": [W.G("RZZ", u, v, theta=-0.7) for u, v in graph],
+        "gf2_block": W.random_perm_block(n, 200, BLOCK_SEED),
+        "rx_layer": [W.G("RX", q, theta=0.1 + 0.01 * q) for q in range(n)],
+        "qft": W.qft_stream(n),
+        "walsh": W.wht_stream(n),
+        "xx_layer": [W.G("RXX", q, q + 1, theta=0.3) for q in range(n - 1)],
+    }
+
+
+def bench_layers(qs, torch, n=30, reps=3):
+    """Each structured layer alone on the resident 30-qubit state: its plan's
+    layers, time per application and the per-pass effective bandwidth
+    (passes x 2 S / t), plus every kernel's average from the library's HIP
+    events."""
+    S = 8 * (1 << n)
+    st = qs.State(n, "c64", init=None)
+    W.gaussian_state_torch(n, STATE_SEED, "c64", out=st.tensor())
+    out = {}
+    for name, stream in layer_streams(n).items():
+        plan = qs.Plan(n, stream)
+        kinds = [L["kind"] for L in plan.describe()["layers"]]
+        qs.apply(st, plan)
+        torch.cuda.synchronize()
+        with qs.profile() as prof:
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                qs.apply(st, plan)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+        kern = {r["kernel"]: {"launches": r["launches"] // reps,
+                              "GBs": round(2 * S * r["launches"] / r["total_ms"] / 1e6, 1)} for r in prof.report}
+        out[name] = {"gates": len(stream), "layers": kinds, "ms": round(1e3 * t, 3),
+                     "GBs_per_pass": round(len(kinds) * 2 * S / t / 1e9, 1),
+                     "frac_per_pass": round(len(kinds) * 2 * S / t / 1e9 / HBM_PEAK_GBS, 4), "kernels": kern}
+    del st
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_dense(qs, torch, n=30, blocks=20, seed=6, reps=2):
+    """Dense k-qubit blocks on the matrix cores at 30 qubits (complex64): 20
+    UNITARY gates on seeded random wire sets per k = 4, 5, 6, each one dense
+    layer.  Reports the per-block kernel time, achieved HBM GB/s (2 S per
+    block) and TFLOP/s (8 2^k flop per amplitude), and one block on the plain
+    per-gate k-qubit kernel for comparison."""
+    S = 8 * (1 << n)
+    st = qs.State(n, "c64", init=None, lazy_scratch=True)
+    W.gaussian_state_torch(n, STATE_SEED, "c64", out=st.tensor())
+    out = {}
+    for k in (4, 5, 6):
+        stream = W.dense_block_stream(n, blocks, k, seed + k)
+        plan = qs.Plan(n, stream)
+        qs.apply(st, plan)
+        torch.cuda.synchronize()
+        with qs.profile() as prof:
+            for _ in range(reps):
+                qs.apply(st, plan)
+            torch.cuda.synchronize()
+        kern = {r["kernel"]: r for r in prof.report}[f"dense_k{k}"]
+        avg = kern["total_ms"] / kern["launches"] * 1e-3
+        flop = 8 * (1 << k) * (1 << n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qs.apply_gates(st, stream[:1])
+        st.sync()
+        t_plain = time.perf_counter() - t0
+        out[f"k{k}"] = {"ms_per_block": round(1e3 * avg, 4), "GBs": round(2 * S / avg / 1e9, 1),
+                        "hbm_frac": round(2 * S / avg / 1e9 / HBM_PEAK_GBS, 4),
+                        "TFLOPs": round(flop / avg / 1e12, 2),
+                        "mfma_frac": round(flop / avg / 1e12 / MFMA_F32_PEAK_TFLOPS, 4),
+                        "plain_ms_per_block": round(1e3 * t_plain, 2),
+                        "speedup_vs_plain": round(t_plain / avg, 1)}
+    out["norm_after"] = qs.norm2(st)
+    del st
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,6 +450,10 @@ def main():
         out["adjoint"] = bench_adjoint(qs, torch)
         log("TFIM: 25 qubits, 40 Strang steps")
         out["tfim25"] = bench_tfim(qs, torch)
+        log("dense k-qubit blocks: 30 qubits, k = 4, 5, 6")
+        out["dense_blocks"] = bench_dense(qs, torch)
+        log("single layers: 30 qubits")
+        out["layers_30q"] = bench_layers(qs, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

@@ -276,6 +276,7 @@ extern "C" qs_status qs_plan_create(int n, const qs_gate* gates, size_t n_gates,
       if (opts->mode != QS_PLAIN && opts->mode != QS_FUSED) fail(QS_EINVAL, "unknown plan mode");
       o.mode = opts->mode;
       o.max_tile_bits = opts->max_tile_bits;
+      if (opts->dense_k_max) o.dense_k_max = opts->dense_k_max;
     }
     int tb = o.max_tile_bits ? o.max_tile_bits : 13;
     if (tb < kRoundBits + 1 || tb > kMaxTileBits) fail(QS_EINVAL, "max_tile_bits out of range");

@@ -1,0 +1,224 @@
+// Dense k-qubit blocks (k = 4, 5, 6) on the matrix cores.
+//
+// A block applies a 2^k x 2^k complex matrix U to the k target bits of every
+// basis index: for each assignment of the other bits (a column), the 2^k
+// amplitudes along the targets are multiplied by U.  That is a complex matrix
+// product Y = U X with X of shape 2^k x (number of columns); the paper names
+// generic matrix fusion of such windows as its next extension (Section
+// "Limitations and Future Work"), and it is the one layer here whose
+// arithmetic intensity (8 2^k flop per amplitude, 2^(k-1) flop per byte in
+// complex64) reaches the matrix cores' ridge.
+//
+// Tiles: the target bits plus the c lowest non-target bits (the columns).
+// Every tile bit below the c-th non-target bit is in the tile, so the tile's
+// low L >= c bits are the state's low bits and loads/stores move runs of
+// 2^L >= 16 consecutive amplitudes; the remaining tile bits are targets, whose
+// global offsets come from a small LDS table.  A workgroup (4 waves) stages a
+// tile in LDS; wave w takes 16-column blocks w, w + 4, ...; each block's product
+// is 4 real MFMA 16x16x4 chains per 16-row tile of U:
+//   Yr += Ur Xr + Ui (-Xi),   Yi += Ur Xi + Ui Xr,
+// with U's fragments held in registers for the whole kernel and X's read from
+// LDS.  Results go back to the same LDS columns (each column block is read and
+// written by one wave only), then the tile is stored.
+//
+// Operand layouts of V_MFMA_{F32,F64}_16X16X4 (wave64): A[i][kk] in lane
+// i + 16 kk, B[kk][j] in lane j + 16 kk; D[i][j] in lane j + 16 (i / 4),
+// register i % 4 for F32, and in lane j + 16 (i % 4), register i / 4 for F64
+// (checked by a one-hot probe of both builtins).
+#include "kernels.h"
+
+namespace qs {
+
+namespace {
+
+constexpr int kDenseThreads = 256;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class R>
+struct Acc4;
+template <>
+struct Acc4<float> {
+  typedef f32x4 T;
+};
+template <>
+struct Acc4<double> {
+  typedef f64x4 T;
+};
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// LDS element of tile position pos (two pad elements every 32).
+__device__ __forceinline__ uint32_t dense_lds_off(uint32_t pos) { return pos + ((pos >> 5) << 1); }
+
+// Deposit the low bits of v into the set bits of mask, in increasing order.
+__device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
+  uint32_t r = 0;
+  while (mask) {
+    const uint32_t low = mask & (0u - mask);
+    if (v & 1u) r |= low;
+    v >>= 1;
+    mask &= mask - 1u;
+  }
+  return r;
+}
+
+template <class R, int K>
+__global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restrict__ psi, const cplx<R>* U_,
+                                                              DenseGeom G) {
+  constexpr int RT = K / 16;  // 16-row tiles of U
+  constexpr int KS = K / 4;   // 4-deep steps of the contraction
+  typedef typename Acc4<R>::T acc_t;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t M = 1u << G.m;
+  cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
+  uint32_t* hi_tab = reinterpret_cast<uint32_t*>(smem_raw + sizeof(cplx<R>) * dense_lds_off(M));
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t li = lane & 15u, lk = lane >> 4;
+
+  // global offsets of the high tile bits (all of them targets)
+  for (uint32_t h = threadIdx.x; h < (1u << G.n_hi); h += kDenseThreads) {
+    uint32_t off = 0;
+    for (uint32_t j = 0; j < G.n_hi; ++j)
+      if ((h >> j) & 1u) off |= 1u << G.hi_bit[j];
+    hi_tab[h] = off;
+  }
+
+  // U fragments: A[i][kk] = U[16 rt + i][4 ks + kk]
+  const cptr<cplx<R>> U = to_const(U_);
+  R ur[RT][KS], ui[RT][KS];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const uint32_t e = (16u * rt + li) * K + 4u * ks + lk;
+      ur[rt][ks] = U[e].re;
+      ui[rt][ks] = U[e].im;
+    }
+  // tile positions of the rows this lane reads (B operand) and writes (D)
+  const uint32_t colmask = (M - 1u) & ~G.rowmask;
+  uint32_t brow[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) brow[ks] = deposit(4u * ks + lk, G.rowmask);
+  uint32_t drow[RT][4];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      drow[rt][v] = deposit(16u * rt + (sizeof(R) == 4 ? 4u * lk + v : lk + 4u * v), G.rowmask);
+  const uint32_t ncb = (1u << G.c) >> 4;
+  const uint32_t Lmask = (1u << G.L) - 1u;
+  __syncthreads();
+
+  for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
+    // coset bits of tile t (the state bits outside the tile)
+    uint32_t base = 0;
+    for (uint32_t j = 0; j < G.n_free; ++j)
+      if ((t >> j) & 1u) base |= 1u << G.free_bit[j];
+    // load: tile bit 0 is state bit 0, so pairs (p, p + 1) are adjacent
+    for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
+      const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
+      *reinterpret_cast<cplx2<R>*>(T + dense_lds_off(p)) = ld_nt(reinterpret_cast<const cplx2<R>*>(psi + g));
+    }
+    __syncthreads();
+
+    for (uint32_t cb = wave; cb < ncb; cb += kDenseThreads / 64) {
+      const uint32_t colp = deposit(16u * cb + li, colmask);
+      acc_t yr[RT], yi[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        yr[rt] = acc_t{0, 0, 0, 0};
+        yi[rt] = acc_t{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const cplx<R> x = T[dense_lds_off(brow[ks] | colp)];
+        const R nxi = -x.im;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          yr[rt] = mfma16(ur[rt][ks], x.re, yr[rt]);
+          yr[rt] = mfma16(ui[rt][ks], nxi, yr[rt]);
+          yi[rt] = mfma16(ur[rt][ks], x.im, yi[rt]);
+          yi[rt] = mfma16(ui[rt][ks], x.re, yi[rt]);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[dense_lds_off(drow[rt][v] | colp)] = cplx<R>{yr[rt][v], yi[rt][v]};
+    }
+    __syncthreads();
+    for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
+      const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
+      st_nt(reinterpret_cast<cplx2<R>*>(psi + g), *reinterpret_cast<const cplx2<R>*>(T + dense_lds_off(p)));
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+bool dense_supported(int n, int k, bool complex128) {
+  if (k < 4 || k > 6 || n - k < 4 || n > 32) return false;
+  return !(complex128 && k == 6);  // 128 double-precision U fragments exceed the register file
+}
+
+DenseGeom dense_geometry(int n, int k, const int* bits_sorted) {
+  DenseGeom G{};
+  uint32_t tmask = 0;
+  for (int j = 0; j < k; ++j) tmask |= 1u << bits_sorted[j];
+  const int c = n - k < 6 ? n - k : 6;
+  // tile bits: the targets plus the c lowest other bits
+  uint32_t bmask = tmask;
+  for (int b = 0, got = 0; b < n && got < c; ++b)
+    if (!((tmask >> b) & 1u)) {
+      bmask |= 1u << b;
+      ++got;
+    }
+  int L = 0;
+  while (L < n && ((bmask >> L) & 1u)) ++L;
+  G.m = (uint32_t)(k + c);
+  G.c = (uint32_t)c;
+  G.L = (uint32_t)L;
+  // tile position of every tile bit = its rank in bmask
+  uint32_t rowmask = 0, pos = 0;
+  for (int b = 0; b < n; ++b)
+    if ((bmask >> b) & 1u) {
+      if ((tmask >> b) & 1u) rowmask |= 1u << pos;
+      if ((int)pos >= L) G.hi_bit[G.n_hi++] = (uint32_t)b;
+      ++pos;
+    }
+  G.rowmask = rowmask;
+  for (int b = 0; b < n; ++b)
+    if (!((bmask >> b) & 1u)) G.free_bit[G.n_free++] = (uint32_t)b;
+  G.n_tiles = 1u << G.n_free;
+  return G;
+}
+
+template <class R>
+bool launch_dense(cplx<R>* psi, int n, int k, const int* bits_sorted, const cplx<R>* U_dev, hipStream_t s) {
+  if (!dense_supported(n, k, sizeof(R) == 8)) return false;
+  const DenseGeom G = dense_geometry(n, k, bits_sorted);
+  const uint32_t M = 1u << G.m;
+  const size_t lds = sizeof(cplx<R>) * (M + ((M >> 5) << 1)) + 64 * sizeof(uint32_t);
+  const uint32_t grid = G.n_tiles < 2048u ? G.n_tiles : 2048u;
+  if (k == 4) {
+    QS_LAUNCH("dense_k4", s, (dense_kernel<R, 16>), dim3(grid), dim3(kDenseThreads), lds, s, psi, U_dev, G);
+  } else if (k == 5) {
+    QS_LAUNCH("dense_k5", s, (dense_kernel<R, 32>), dim3(grid), dim3(kDenseThreads), lds, s, psi, U_dev, G);
+  } else if constexpr (sizeof(R) == 4) {
+    QS_LAUNCH("dense_k6", s, (dense_kernel<R, 64>), dim3(grid), dim3(kDenseThreads), lds, s, psi, U_dev, G);
+  }
+  return true;
+}
+
+template bool launch_dense<float>(cplx<float>*, int, int, const int*, const cplx<float>*, hipStream_t);
+template bool launch_dense<double>(cplx<double>*, int, int, const int*, const cplx<double>*, hipStream_t);
+
+}  // namespace qs

@@ -85,6 +85,24 @@ size_t batch_observable_partials(uint32_t count, uint32_t n);  // doubles needed
 template <class R>
 void launch_diag(cplx<R>* psi, int n, const DiagDev& D, hipStream_t s);
 
+// Dense k-qubit block (matrix cores): psi <- U on the k bits bits_sorted
+// (ascending); U_dev is 2^k x 2^k row-major in device memory with index bit u
+// of rows and columns on bits_sorted[u].  Supported for k = 4..6 with n >= k + 4
+// (complex128: k <= 5); returns false, launching nothing, otherwise.
+struct DenseGeom {
+  uint32_t m, c, L;        // tile bits, column bits, low tile bits equal to state bits [0, L)
+  uint32_t rowmask;        // tile positions of the targets
+  uint32_t n_hi;           // tile bits at positions >= L (all targets) ...
+  uint32_t hi_bit[6];      // ... and their state bits
+  uint32_t n_free;         // state bits outside the tile (ascending) ...
+  uint32_t free_bit[32];
+  uint32_t n_tiles;        // 2^n_free
+};
+bool dense_supported(int n, int k, bool complex128);
+DenseGeom dense_geometry(int n, int k, const int* bits_sorted);
+template <class R>
+bool launch_dense(cplx<R>* psi, int n, int k, const int* bits_sorted, const cplx<R>* U_dev, hipStream_t s);
+
 template <class R>
 void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s);
 

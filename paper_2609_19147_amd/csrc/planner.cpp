@@ -4,6 +4,7 @@
 #include "planner.h"
 
 #include <algorithm>
+#include <iomanip>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -604,6 +605,36 @@ Sched make_groups(int n, int tile_bits, int low_bits) {
   return s;
 }
 
+// The gate's matrix (first listed wire = most significant index bit) re-indexed
+// so that index bit u sits on the u-th smallest target bit.
+DenseIR make_dense(const NGate& g, int32_t gi) {
+  DenseIR D;
+  D.gate = gi;
+  const int k = (int)g.bits.size();
+  D.bits = g.bits;
+  std::sort(D.bits.begin(), D.bits.end());
+  std::vector<int> gate_bit(k);  // index bit of the gate's matrix holding D.bits[u]
+  for (int u = 0; u < k; ++u)
+    for (int j = 0; j < k; ++j)
+      if (g.bits[j] == D.bits[u]) gate_bit[u] = k - 1 - j;
+  const int K = 1 << k;
+  std::vector<int> perm(K);
+  for (int r = 0; r < K; ++r) {
+    int q = 0;
+    for (int u = 0; u < k; ++u)
+      if ((r >> u) & 1) q |= 1 << gate_bit[u];
+    perm[r] = q;
+  }
+  D.mat.resize((size_t)K * K);
+  D.mat_dagger.resize((size_t)K * K);
+  for (int r = 0; r < K; ++r)
+    for (int c = 0; c < K; ++c) {
+      D.mat[(size_t)r * K + c] = g.mat[(size_t)perm[r] * K + perm[c]];
+      D.mat_dagger[(size_t)c * K + r] = std::conj(D.mat[(size_t)r * K + c]);
+    }
+  return D;
+}
+
 struct Item {
   ItemIR ir;
   uint32_t W = 0, R = 0;
@@ -651,6 +682,11 @@ class Builder {
       } else if (k == QS_GATE_RYY) {
         open_block(YY);
         pp.push_back((int)i);
+      } else if (k == QS_GATE_UNITARY && (int)g.bits.size() >= 4 && (int)g.bits.size() <= P.opt.dense_k_max &&
+                 n - (int)g.bits.size() >= 4) {
+        close_open();
+        barrier({L_DENSE, (int32_t)P.denses.size()});
+        P.denses.push_back(make_dense(g, (int32_t)i));
       } else {
         close_open();
         barrier({L_PLAIN, (int32_t)i});
@@ -1343,6 +1379,7 @@ PlanIR invert_plan(const PlanIR& F) {
   P.opt = F.opt;
   P.gates = F.gates;
   P.diags = F.diags;
+  P.denses = F.denses;
   P.ops = F.ops;
   P.tile_bits = F.tile_bits;
   P.low_bits = F.low_bits;
@@ -1382,7 +1419,7 @@ std::vector<std::vector<GradEntry>> grad_entries(const PlanIR& P, const std::vec
       if (!P.gates[L.index].angle.is_const()) fail(QS_EUNSUPPORTED, "parameter on a gate run by the plain path");
       continue;
     }
-    if (L.kind == L_GF2) continue;
+    if (L.kind == L_GF2 || L.kind == L_DENSE) continue;
     if (L.kind == L_DIAG) {
       const DiagIR& D = P.diags[L.index];
       for (size_t g = 0; g < D.groups.size(); ++g)
@@ -1505,6 +1542,18 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
       o << "{\"kind\":\"gf2\",\"rows\":[";
       for (size_t r = 0; r < G.rows.size(); ++r) { if (r) o << ","; o << G.rows[r]; }
       o << "],\"cprime\":" << G.cprime << ",\"n_gates\":" << G.gates.size() << "}";
+    } else if (L.kind == L_DENSE) {
+      const DenseIR& D = P.denses[L.index];
+      o << "{\"kind\":\"dense\",\"inverse\":" << L.inverse << ",\"gate\":" << D.gate << ",\"bits\":[";
+      for (size_t b = 0; b < D.bits.size(); ++b) { if (b) o << ","; o << D.bits[b]; }
+      o << "],\"mat\":[";
+      const std::vector<cd>& M = L.inverse ? D.mat_dagger : D.mat;
+      o << std::setprecision(17);
+      for (size_t e = 0; e < M.size(); ++e) {
+        if (e) o << ",";
+        o << "[" << M[e].real() << "," << M[e].imag() << "]";
+      }
+      o << "]}";
     } else if (L.kind == L_PLAIN) {
       const NGate& g = P.gates[L.index];
       o << "{\"kind\":\"plain\",\"inverse\":" << L.inverse << ",\"gate\":" << L.index

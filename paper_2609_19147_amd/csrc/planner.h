@@ -107,7 +107,16 @@ struct Gf2IR {
   std::vector<int32_t> gates;  // source gates (for describe)
 };
 
-enum LayerKind : int32_t { L_DIAG = 0, L_TILE = 1, L_GF2 = 2, L_PLAIN = 3 };
+enum LayerKind : int32_t { L_DIAG = 0, L_TILE = 1, L_GF2 = 2, L_PLAIN = 3, L_DENSE = 4 };
+
+// A dense k-qubit block (k = 4..6) for the matrix cores: the gate's matrix with
+// row / column index bit u on the state bit bits[u] (ascending), and its
+// conjugate transpose for the inverse plan.
+struct DenseIR {
+  int32_t gate = 0;          // index into Plan::gates
+  std::vector<int> bits;     // ascending
+  std::vector<cd> mat, mat_dagger;
+};
 
 struct LayerIR {
   int32_t kind;
@@ -118,6 +127,7 @@ struct LayerIR {
 struct PlanOptions {
   int mode = QS_FUSED;
   int max_tile_bits = 0;  // 0 = default by dtype at apply time
+  int dense_k_max = 6;    // largest UNITARY gate run as a dense block (< 4: none)
 };
 
 struct PlanIR {
@@ -129,6 +139,7 @@ struct PlanIR {
   std::vector<OpIR> ops;
   std::vector<TilePassIR> passes;
   std::vector<Gf2IR> gf2s;
+  std::vector<DenseIR> denses;
   std::vector<LayerIR> layers;
   int tile_bits = 13;  // tile size used to build the passes
   int low_bits = 4;    // L of high tiles

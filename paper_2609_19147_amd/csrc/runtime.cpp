@@ -56,6 +56,12 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
     // slot descriptors hold device addresses: filled in once the blob has one
     if (!T.diag_slots.empty()) d.pass_diag[i] = b.put(std::vector<DiagDev>(T.diag_slots.size()));
   }
+  d.dense_mat.assign(P.denses.size(), 0);
+  d.dense_mat_dagger.assign(P.denses.size(), 0);
+  for (size_t i = 0; i < P.denses.size(); ++i) {
+    d.dense_mat[i] = b.put(cast<R>(P.denses[i].mat));
+    d.dense_mat_dagger[i] = b.put(cast<R>(P.denses[i].mat_dagger));
+  }
   b.put(std::vector<double>(2, 0.0));  // never zero bytes
 }
 
@@ -175,6 +181,16 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
         s.ensure_other();
         launch_gf2<R>((const cplx<R>*)s.buf[s.cur], (cplx<R>*)s.buf[1 - s.cur], p.gf2[L.index], s.stream);
         s.cur = 1 - s.cur;
+        break;
+      }
+      case L_DENSE: {
+        const DenseIR& D = P.denses[L.index];
+        const cplx<R>* U = (const cplx<R>*)(base + (L.inverse ? d.dense_mat_dagger[L.index] : d.dense_mat[L.index]));
+        if (!launch_dense<R>((cplx<R>*)s.cur_ptr(), s.n, (int)D.bits.size(), D.bits.data(), U, s.stream)) {
+          // the per-gate k-qubit kernel, with the first listed bit most significant
+          std::vector<int> desc(D.bits.rbegin(), D.bits.rend());
+          launch_matk<R>((cplx<R>*)s.cur_ptr(), s.n, (int)desc.size(), desc.data(), U, s.stream);
+        }
         break;
       }
       case L_PLAIN:

@@ -5,7 +5,8 @@ round, diagonal layers from their FP64 lookup tables, GF(2) gathers from
 their row masks -- so the planner's rewrite can be checked against the
 one-gate-at-a-time oracle on the CPU, without a GPU.  QFT stages use the
 plain stage definition (butterfly on bit p, then exp(i pi (i mod 2^p) / 2^p)
-on the bit-p = 1 half).  Plain layers call the oracle's gate application.
+on the bit-p = 1 half).  Dense layers apply the matrix the plan carries;
+plain layers call the oracle's gate application.
 """
 from __future__ import annotations
 
@@ -53,6 +54,17 @@ def apply_bit_2x2(psi, n, b, U):
     v[:, 1, :] = U[1][0] * x + U[1][1] * y
 
 
+def apply_dense(psi, n, bits, U):
+    idx = np.arange(1 << n, dtype=np.int64)
+    tmask = sum(1 << b for b in bits)
+    base = idx[(idx & tmask) == 0]
+    offs = np.array([sum(((r >> u) & 1) << b for u, b in enumerate(bits)) for r in range(len(U))], np.int64)
+    pos = base[None, :] + offs[:, None]
+    out = psi.copy()
+    out[pos] = U @ psi[pos]
+    return out
+
+
 def apply_layer(psi, n, L, stream, params):
     k = L["kind"]
     if k == "diag":
@@ -66,6 +78,11 @@ def apply_layer(psi, n, L, stream, params):
             src |= (_popc(y & row) & 1).astype(np.uint64) << np.uint64(r)
         src ^= np.uint64(L["cprime"])
         return psi[src.astype(np.int64)]
+    if k == "dense":
+        # the plan's own matrix: index bit u of rows and columns on bits[u]
+        U = np.array([complex(a, b) for a, b in L["mat"]])
+        K = int(round(math.sqrt(U.size)))
+        return apply_dense(psi, n, L["bits"], U.reshape(K, K))
     if k == "plain":
         g = stream[L["gate"]]
         if L.get("inverse"):

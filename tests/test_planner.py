@@ -160,6 +160,31 @@ def test_multi_controlled_and_dense_gates():
     check_plan(n, st, tol=1e-12)
 
 
+@pytest.mark.parametrize("k", [4, 5, 6])
+def test_unitary_blocks_become_dense_layers(k):
+    n = 11
+    st = W.dense_block_stream(n, 3, k, 40 + k) + W.random_stream(n, 30, k) + W.dense_block_stream(n, 2, k, 50 + k)
+    d = check_plan(n, st, tol=1e-12)
+    dense = [L for L in d["layers"] if L["kind"] == "dense"]
+    assert len(dense) == 5
+    for L in dense:
+        assert L["bits"] == sorted(L["bits"]) and len(L["bits"]) == k
+    # the plain path keeps them as per-gate layers, a small cap or a small state disables them
+    assert "dense" not in kinds(plan_of(n, st, mode="plain").describe())
+    assert "dense" not in kinds(plan_of(n, st, dense_k_max=k - 1).describe())
+    assert "dense" not in kinds(plan_of(k + 3, W.dense_block_stream(k + 3, 1, k, 1)).describe())
+
+
+def test_dense_inverse_plan():
+    n = 10
+    st = W.dense_block_stream(n, 4, 5, 8) + W.qft_stream(n)
+    p = plan_of(n, st)
+    psi0 = W.gaussian_state(n, 2)
+    fwd = run_plan(p.describe(), psi0, st)
+    back = run_plan(p.inverse().describe(), fwd, st)
+    assert np.max(np.abs(back - psi0)) < 1e-12
+
+
 def test_grover_plan():
     n = 8
     st = W.grover_stream(n, 0b10110011, 3)

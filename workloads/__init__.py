@@ -365,6 +365,17 @@ def random_unitary(dim: int, rng: np.random.Generator) -> np.ndarray:
     return q * (d / np.abs(d))
 
 
+def dense_block_stream(n: int, count: int, k: int, seed: int) -> List[Gate]:
+    """``count`` UNITARY gates on k distinct random wires each, with Haar-ish
+    2^k x 2^k matrices (the dense-block microbenchmark's input)."""
+    rng = np.random.default_rng(seed)
+    out: List[Gate] = []
+    for _ in range(count):
+        w = rng.choice(n, size=k, replace=False)
+        out.append(G("UNITARY", *[int(x) for x in w], mat=random_unitary(1 << k, rng)))
+    return out
+
+
 def gaussian_state_torch(n: int, seed: int, dtype: str = "c64", out=None):
     """Seeded i.i.d. complex Gaussian state generated on the GPU with torch's
     Philox generator, normalised in FP64 (for sizes where a host state would be
