@@ -104,48 +104,108 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
   }
   *energy = state_overlap(phi.s, lam.s).real();
 
-  // backward
+  // backward: every reduction writes its own slot of one device array, read
+  // back once after the sweep (no host round trip per layer)
   std::vector<double> g(p.ir.n_params, 0.0);
   phi.s.ensure_red();
   const PlanDev& d = p.device_for(psi.dtype);
+  // per forward layer: the cross densities of all of a tile layer's parameter
+  // bits in one read of phi and lambda (the layer's tile geometry), else one
+  // reduction per bit; diagonal-layer parameters one reduction per group
+  std::vector<RhoTileArgs> tile_rho(L);
+  std::vector<std::map<int, size_t>> rho_slot(L);   // bit -> offset of its 8 sums
+  std::vector<std::vector<int>> single_bits(L);     // bits reduced one at a time
+  std::vector<std::map<std::pair<int, int>, size_t>> diag_slot(L);  // (diag, group) -> offset
+  std::vector<size_t> tile_slot(L, 0);
+  size_t n_res = 0, rho_partials = 0;
+  for (size_t fl = 0; fl < L; ++fl) {
+    const LayerIR& FL = p.ir.layers[fl];
+    std::vector<int> bits;
+    for (const GradEntry& e : entries[fl]) {
+      if (e.kind == 0) {
+        if (std::find(bits.begin(), bits.end(), e.bit) == bits.end()) bits.push_back(e.bit);
+      } else if (!diag_slot[fl].count({e.diag, e.group})) {
+        diag_slot[fl][{e.diag, e.group}] = n_res++;
+      }
+    }
+    if (bits.empty()) continue;
+    bool tiled = false;
+    if (FL.kind == L_TILE && bits.size() <= 32) {
+      const TilePassIR& T = p.ir.passes[FL.index];
+      RhoTileArgs A{};
+      A.L = (uint32_t)T.L;
+      A.a = (uint32_t)T.a;
+      A.h = (uint32_t)T.h;
+      A.m = (uint32_t)(T.L + T.h);
+      tiled = T.L >= 1 && rho_tile_fits(A.m, sizeof(R));
+      for (int b : bits) {
+        const int pos = b < T.L ? b : (b >= T.a && b < T.a + T.h ? T.L + b - T.a : -1);
+        if (pos < 0) tiled = false;
+        else A.tbit[A.nbits++] = (uint32_t)pos;
+      }
+      if (tiled) {
+        tile_rho[fl] = A;
+        tile_slot[fl] = n_res;
+        for (size_t k = 0; k < bits.size(); ++k) rho_slot[fl][bits[k]] = n_res + 8 * k;
+        n_res += 8 * bits.size();
+        rho_partials = std::max(rho_partials, rho_tile_partials(n, A));
+      }
+    }
+    if (!tiled) {
+      for (int b : bits) {
+        rho_slot[fl][b] = n_res;
+        n_res += 8;
+      }
+      single_bits[fl] = bits;
+    }
+  }
+  void* buf = nullptr;
+  if (n_res) check_hip(hipMalloc(&buf, (rho_partials + n_res) * sizeof(double)), "hipMalloc");
+  struct BufGuard {
+    void* p;
+    ~BufGuard() {
+      if (p) hipFree(p);
+    }
+  } buf_guard{buf};
+  double* part = (double*)buf;
+  double* res = part + rho_partials;
   for (size_t j = 0; j < L; ++j) {
     const size_t fl = L - 1 - j;  // forward layer being undone
     apply_layers(phi.s, inv, j, j + 1);
     apply_layers(lam.s, inv, j, j + 1);
-    if (entries[fl].empty()) continue;
-    std::map<int, std::vector<double>> rho;  // per bit
-    for (const GradEntry& e : entries[fl]) {
-      if (e.kind == 0) {
-        auto it = rho.find(e.bit);
-        if (it == rho.end()) {
-          launch_pair_rho<R>((const cplx<R>*)phi.s.cur_ptr(), (const cplx<R>*)lam.s.cur_ptr(), n, e.bit,
-                             phi.s.red_partials, phi.s.red_out, psi.stream);
-          std::vector<double> r(8);
-          check_hip(hipMemcpyAsync(r.data(), phi.s.red_out, 64, hipMemcpyDeviceToHost, psi.stream), "hipMemcpyAsync");
-          psi.sync();
-          it = rho.emplace(e.bit, r).first;
-        }
-        const std::vector<double>& r = it->second;
-        cd acc = 0;
-        for (int k = 0; k < 4; ++k) acc += e.K[k] * cd(r[2 * k], r[2 * k + 1]);
-        g[e.param] += e.coef * 2.0 * acc.real();
-      } else {
-        const char* base = (const char*)d.blob;
-        DiagDev D;
-        D.terms = (const DiagTerm*)(base + d.diag_terms[e.diag]);
-        D.groups = (const DiagGroup*)(base + d.diag_groups[e.diag]);
-        D.lut = base + d.diag_lut[e.diag];
-        D.n_groups = d.diag_ngroups[e.diag];
-        D.conj = 0;
-        launch_diag_grad<R>((const cplx<R>*)phi.s.cur_ptr(), (const cplx<R>*)lam.s.cur_ptr(), n, D, e.group, 1,
-                            phi.s.red_partials, phi.s.red_out, psi.stream);
-        double v = 0;
-        check_hip(hipMemcpyAsync(&v, phi.s.red_out, 8, hipMemcpyDeviceToHost, psi.stream), "hipMemcpyAsync");
-        psi.sync();
-        g[e.param] += e.coef * (-2.0) * v;
-      }
+    const cplx<R>* ph = (const cplx<R>*)phi.s.cur_ptr();
+    const cplx<R>* la = (const cplx<R>*)lam.s.cur_ptr();
+    if (tile_rho[fl].nbits) launch_rho_tile<R>(ph, la, n, tile_rho[fl], part, res + tile_slot[fl], psi.stream);
+    for (int b : single_bits[fl])
+      launch_pair_rho<R>(ph, la, n, b, phi.s.red_partials, res + rho_slot[fl][b], psi.stream);
+    for (const auto& kv : diag_slot[fl]) {
+      const char* base = (const char*)d.blob;
+      const int di = kv.first.first;
+      DiagDev D;
+      D.terms = (const DiagTerm*)(base + d.diag_terms[di]);
+      D.groups = (const DiagGroup*)(base + d.diag_groups[di]);
+      D.lut = base + d.diag_lut[di];
+      D.n_groups = d.diag_ngroups[di];
+      D.conj = 0;
+      launch_diag_grad<R>(ph, la, n, D, kv.first.second, 1, phi.s.red_partials, res + kv.second, psi.stream);
     }
   }
+  std::vector<double> r(n_res);
+  if (n_res)
+    check_hip(hipMemcpyAsync(r.data(), res, n_res * sizeof(double), hipMemcpyDeviceToHost, psi.stream),
+              "hipMemcpyAsync");
+  psi.sync();
+  for (size_t fl = 0; fl < L; ++fl)
+    for (const GradEntry& e : entries[fl]) {
+      if (e.kind == 0) {
+        const double* q = r.data() + rho_slot[fl].at(e.bit);
+        cd acc = 0;
+        for (int k = 0; k < 4; ++k) acc += e.K[k] * cd(q[2 * k], q[2 * k + 1]);
+        g[e.param] += e.coef * 2.0 * acc.real();
+      } else {
+        g[e.param] += e.coef * (-2.0) * r[diag_slot[fl].at({e.diag, e.group})];
+      }
+    }
   std::copy(g.begin(), g.end(), grad);
 }
 

@@ -371,6 +371,123 @@ template void launch_diag_grad<float>(const cplx<float>*, const cplx<float>*, in
 template void launch_diag_grad<double>(const cplx<double>*, const cplx<double>*, int, const DiagDev&, int, int,
                                        double*, double*, hipStream_t);
 
+// ---- cross densities of several bits at once (adjoint sweep) ---------------
+namespace {
+
+constexpr int kRhoThreads = 1024;
+constexpr int kRhoWaves = kRhoThreads / 64;
+
+__device__ __forceinline__ uint32_t rho_lds_off(uint32_t pos) { return pos + ((pos >> 5) << 1); }
+
+// One workgroup per coset of the tile bits [0, L) U [a, a + h): phi and lambda
+// tiles staged in LDS; then wave w takes the requested tile bits w, w + 16, ...
+// and, over all of the tile's pairs along its bit, the eight sums
+// rho_b[r][c] = sum conj(lam_r) phi_c.  Each lane sums its share of pairs in the
+// state's precision; the folds across the wave (fixed order) and across tiles
+// (compensated, rho_finalize) are FP64.
+template <class R>
+__global__ void __launch_bounds__(kRhoThreads) rho_tile_kernel(const cplx<R>* __restrict__ phi,
+                                                               const cplx<R>* __restrict__ lam, RhoTileArgs A,
+                                                               double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t M = 1u << A.m;
+  cplx<R>* P = reinterpret_cast<cplx<R>*>(smem_raw);
+  cplx<R>* Q = P + rho_lds_off(M);
+  const uint32_t coset = blockIdx.x;
+  const uint32_t nlo = A.a - A.L, top = A.a + A.h;
+  const uint32_t base = ((coset & ((1u << nlo) - 1u)) << A.L) | (top >= 32 ? 0u : ((coset >> nlo) << top));
+  const uint32_t lmask = (1u << A.L) - 1u;
+  for (uint32_t pos = 2u * threadIdx.x; pos < M; pos += 2u * kRhoThreads) {
+    const uint32_t g = base | (pos & lmask) | ((pos >> A.L) << A.a);
+    *reinterpret_cast<cplx2<R>*>(P + rho_lds_off(pos)) = ld_nt(reinterpret_cast<const cplx2<R>*>(phi + g));
+    *reinterpret_cast<cplx2<R>*>(Q + rho_lds_off(pos)) = ld_nt(reinterpret_cast<const cplx2<R>*>(lam + g));
+  }
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  for (uint32_t bi = wave; bi < A.nbits; bi += kRhoWaves) {
+    const uint32_t b = A.tbit[bi];
+    // a lane's sum over its <= 2^(m-7) pairs in the state's precision, the
+    // folds across lanes and tiles in FP64
+    R a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t j = lane; j < M / 2; j += 64) {
+      const uint32_t p0 = insert0(j, b), p1 = p0 | (1u << b);
+      const cplx<R> f0 = P[rho_lds_off(p0)], f1 = P[rho_lds_off(p1)];
+      const cplx<R> l0 = Q[rho_lds_off(p0)], l1 = Q[rho_lds_off(p1)];
+      const R f0r = f0.re, f0i = f0.im, f1r = f1.re, f1i = f1.im;
+      const R l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
+      R* acc = a8;
+      acc[0] += l0r * f0r + l0i * f0i;
+      acc[1] += l0r * f0i - l0i * f0r;
+      acc[2] += l0r * f1r + l0i * f1i;
+      acc[3] += l0r * f1i - l0i * f1r;
+      acc[4] += l1r * f0r + l1i * f0i;
+      acc[5] += l1r * f0i - l1i * f0r;
+      acc[6] += l1r * f1r + l1i * f1i;
+      acc[7] += l1r * f1i - l1i * f1r;
+    }
+    double acc[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      double x = a8[v];
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+      acc[v] = x;
+    }
+    if (lane < 8) {
+      double x = acc[0];
+#pragma unroll
+      for (int v = 1; v < 8; ++v) x = lane == (uint32_t)v ? acc[v] : x;
+      partials[((size_t)blockIdx.x * A.nbits + bi) * 8 + lane] = x;
+    }
+  }
+}
+
+// out[o] = sum over tiles t of partials[t * nv + o], compensated, fixed order.
+__global__ void __launch_bounds__(kThreads) rho_finalize(const double* __restrict__ partials, uint32_t ntiles,
+                                                         uint32_t nv, double* __restrict__ out) {
+  const uint32_t o = blockIdx.x;
+  Acc a = {0.0, 0.0};
+  for (uint32_t t = threadIdx.x; t < ntiles; t += kThreads) nadd(a, partials[(size_t)t * nv + o]);
+  __shared__ Acc red[kThreads];
+  a = block_fold(a, red);
+  if (threadIdx.x == 0) out[o] = a.s + a.c;
+}
+
+}  // namespace
+
+size_t rho_tile_partials(int n, const RhoTileArgs& A) { return ((size_t)1 << (n - A.m)) * A.nbits * 8; }
+
+bool rho_tile_fits(uint32_t m, size_t amp_bytes) {
+  const uint32_t M = 1u << m;
+  return m >= 7 && 2 * amp_bytes * (M + ((M >> 5) << 1)) <= 160 * 1024;
+}
+
+template <class R>
+bool launch_rho_tile(const cplx<R>* phi, const cplx<R>* lam, int n, const RhoTileArgs& A, double* partials,
+                     double* out, hipStream_t s) {
+  constexpr size_t kMaxDynamic = 160 * 1024;
+  const uint32_t M = 1u << A.m;
+  const size_t lds = 2 * sizeof(cplx<R>) * (M + ((M >> 5) << 1));
+  if (!rho_tile_fits(A.m, sizeof(cplx<R>)) || A.nbits == 0 || A.nbits > 32) return false;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute((const void*)rho_tile_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kMaxDynamic) != hipSuccess)
+      return false;
+    attr_set = true;
+  }
+  const uint32_t ntiles = 1u << (n - A.m);
+  QS_LAUNCH("reduce_rho_tile", s, rho_tile_kernel<R>, dim3(ntiles), dim3(kRhoThreads), lds, s, phi, lam, A,
+            partials);
+  QS_LAUNCH("reduce_rho_finalize", s, rho_finalize, dim3(A.nbits * 8), dim3(kThreads), 0, s, partials, ntiles,
+            A.nbits * 8, out);
+  return true;
+}
+template bool launch_rho_tile<float>(const cplx<float>*, const cplx<float>*, int, const RhoTileArgs&, double*, double*,
+                                     hipStream_t);
+template bool launch_rho_tile<double>(const cplx<double>*, const cplx<double>*, int, const RhoTileArgs&, double*,
+                                      double*, hipStream_t);
+
 size_t batch_observable_partials(uint32_t count, uint32_t n) {
   uint32_t cs, ls;
   batch_obs_shape(n, &cs, &ls);

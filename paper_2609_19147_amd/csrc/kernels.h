@@ -137,6 +137,20 @@ void launch_pauli_apply(const cplx<R>* psi, cplx<R>* out, int n, const uint32_t*
 template <class R>
 void launch_pair_rho(const cplx<R>* phi, const cplx<R>* lam, int n, int b, double* partials, double* out,
                      hipStream_t s);
+// The same eight sums for several bits at once, over the tiles of a tile-pass
+// geometry ([0, L) U [a, a + h), m = L + h): tbit[] are tile positions.
+// out[8 j + v] for requested bit j.  Returns false (nothing launched) when the
+// two staged tiles do not fit in LDS; partials needs rho_tile_partials doubles.
+struct RhoTileArgs {
+  uint32_t L, a, h, m;
+  uint32_t nbits;
+  uint32_t tbit[32];
+};
+size_t rho_tile_partials(int n, const RhoTileArgs& A);
+bool rho_tile_fits(uint32_t m, size_t amp_bytes);  // both tiles of 2^m amplitudes fit in LDS
+template <class R>
+bool launch_rho_tile(const cplx<R>* phi, const cplx<R>* lam, int n, const RhoTileArgs& A, double* partials,
+                     double* out, hipStream_t s);
 // out[g] = sum_x count_g(x) Im(conj(lam_x) phi_x) for groups [g0, g0 + ng), ng <= 8.
 template <class R>
 void launch_diag_grad(const cplx<R>* phi, const cplx<R>* lam, int n, const DiagDev& D, int g0, int ng,
