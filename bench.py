@@ -107,15 +107,33 @@ def bench_batched_qaoa(qs, torch, count=512, depth=4, seed=512, reps=3):
     """512 MaxCut QAOA instances (n uniform over 16..24 even, 3-regular graphs,
     p = 4, angles U[0, pi)) as one recorded graph launch + one batched FP64
     expectation, against the per-instance fused and plain per-gate paths."""
+    from paper_2609_19147_amd.tune import TileTuner
     insts = W.qaoa_instances(count, seed, depth=depth)
-    plans, obs = [], []
-    for inst in insts:
+
+    def make_plan(inst, tb):
         prm = np.empty(2 * depth)
         prm[0::2] = inst.gammas
         prm[1::2] = inst.betas
-        plans.append(qs.Plan(inst.n, W.qaoa_stream(inst, param_offset=0, h_layer=False), n_params=2 * depth,
-                             max_tile_bits=qaoa_tile_bits(inst.n), params=prm))
-        obs.append(W.maxcut_terms(inst.edges))
+        return qs.Plan(inst.n, W.qaoa_stream(inst, param_offset=0, h_layer=False), n_params=2 * depth,
+                       max_tile_bits=tb, params=prm)
+
+    # tile limit per qubit count, tuned on a batch of 16 instances (untimed)
+    tuner = TileTuner()
+    tile_bits = {}
+    for n in sorted({i.n for i in insts}):
+        sample = [i for i in insts if i.n == n][:16]
+        built = {}
+
+        def run(tb, sample=sample, built=built):
+            if tb not in built:
+                built[tb] = qs.Batch([make_plan(i, tb) for i in sample], init="plus")
+            built[tb].run()
+
+        cands = range(max(8, qaoa_tile_bits(n) - 3), min(14, n - 2) + 1)
+        tile_bits[n] = tuner.best(f"qaoa-maxcut-p{depth}-batched", n, "c64", run, cands)
+        del built
+    plans = [make_plan(inst, tile_bits[inst.n]) for inst in insts]
+    obs = [W.maxcut_terms(inst.edges) for inst in insts]
     t0 = time.perf_counter()
     B = qs.Batch(plans, init="plus")
     t_record = time.perf_counter() - t0
@@ -161,7 +179,8 @@ def bench_batched_qaoa(qs, torch, count=512, depth=4, seed=512, reps=3):
             "ms_batch": round(1e3 * t_batch, 2), "ms_record_graph": round(1e3 * t_record, 1),
             "max_abs_diff_vs_plain": float(np.max(np.abs(c_batch - c_plain))),
             "max_abs_diff_vs_fused": float(np.max(np.abs(c_batch - c_fused))),
-            "mean_cut": round(float(np.mean(c_batch)), 4)}
+            "mean_cut": round(float(np.mean(c_batch)), 4),
+            "tile_bits_by_n": {str(k): v for k, v in tile_bits.items()}}
 
 
 def bench_adjoint(qs, torch, n=24, layers=8, seed=24, ps_sample=16):

@@ -101,6 +101,7 @@ void build_descs(qs_batch& B) {
         A.ops = (const TileOp*)(base + d.pass_ops[L.index]);
         A.coef = (const cplx<R>*)(base + d.pass_coef[L.index]);
         A.diag = d.pass_diag[L.index] ? (const DiagDev*)(base + d.pass_diag[L.index]) : nullptr;
+        A.qtab = (const int8_t*)(base + d.pass_qtab[L.index]);
         A.L = T.L;
         A.a = T.a;
         A.h = T.h;

@@ -239,4 +239,55 @@ __device__ __forceinline__ void diag_apply(cplx<R>* a, uint32_t i0, const uint32
   }
 }
 
+// The 16 amplitudes of a tile round: index i0 | (any subset of the round's
+// state bits b[0..3]), register j holding subset j.  For groups whose pair
+// table (qt, 8 bytes per group) says the count is a polynomial of degree <= 2
+// in the four bits, counts come from 5 evaluations (i0 and the single flips)
+// and the pair coefficients; other groups evaluate all 16 indices.
+template <class R>
+__device__ __forceinline__ void diag_apply_round(cplx<R>* a, uint32_t i0, uint32_t b0, uint32_t b1, uint32_t b2,
+                                                 uint32_t b3, const DiagDev& D, const int8_t* qt_) {
+  const cplx<R>* __restrict__ lut = (const cplx<R>*)D.lut;
+  const cptr<DiagGroup> groups = to_const(D.groups);
+  const cptr<int8_t> qt = to_const(qt_);
+  for (int g = 0; g < D.n_groups; ++g) {
+    const int lb = groups[g].lut_begin;
+    int cnt[16];
+    if (qt[8 * g]) {
+      const uint32_t off5[5] = {0u, b0, b1, b2, b3};
+      int c5[5];
+      diag_counts<5>(i0, off5, D.terms, groups[g].term_begin, groups[g].term_end, c5);
+      const int d[4] = {c5[1] - c5[0], c5[2] - c5[0], c5[3] - c5[0], c5[4] - c5[0]};
+      const int q01 = qt[8 * g + 1], q02 = qt[8 * g + 2], q03 = qt[8 * g + 3];
+      const int q12 = qt[8 * g + 4], q13 = qt[8 * g + 5], q23 = qt[8 * g + 6];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        int c = c5[0];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if ((j >> k) & 1) c += d[k];
+        if ((j & 3) == 3) c += q01;
+        if ((j & 5) == 5) c += q02;
+        if ((j & 9) == 9) c += q03;
+        if ((j & 6) == 6) c += q12;
+        if ((j & 10) == 10) c += q13;
+        if ((j & 12) == 12) c += q23;
+        cnt[j] = c;
+      }
+    } else {
+      uint32_t off[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        off[j] = ((j & 1) ? b0 : 0u) | ((j & 2) ? b1 : 0u) | ((j & 4) ? b2 : 0u) | ((j & 8) ? b3 : 0u);
+      diag_counts<16>(i0, off, D.terms, groups[g].term_begin, groups[g].term_end, cnt);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      cplx<R> v = lut[lb + cnt[j]];
+      if (D.conj) v.im = -v.im;
+      a[j] = cmul(a[j], v);
+    }
+  }
+}
+
 }  // namespace qs

@@ -262,12 +262,8 @@ struct RoundLoop {
       const uint32_t gglobal = C.base | C.dep(gpos);
       if (kDiag && R_->diag >= 0) {
         // register j holds index gglobal | dep(round bits of j)
-        const uint32_t b0 = C.dep(1u << t0), b1 = C.dep(1u << t1), b2 = C.dep(1u << t2), b3 = C.dep(1u << t3);
-        uint32_t off[RN];
-#pragma unroll
-        for (int j = 0; j < RN; ++j)
-          off[j] = ((j & 1) ? b0 : 0u) | ((j & 2) ? b1 : 0u) | ((j & 4) ? b2 : 0u) | ((j & 8) ? b3 : 0u);
-        diag_apply<R, RN>(a, gglobal, off, diag_slot(A.diag, R_->diag));
+        diag_apply_round<R>(a, gglobal, C.dep(1u << t0), C.dep(1u << t1), C.dep(1u << t2), C.dep(1u << t3),
+                            diag_slot(A.diag, R_->diag), A.qtab + R_->qoff);
       }
       f(a, gglobal);
 #pragma unroll
@@ -279,24 +275,25 @@ struct RoundLoop {
 // kDiag: the pass carries diagonal layers.  Passes without them use an
 // instantiation that has no phase-evaluation code at all, which keeps the
 // butterfly rounds' register allocation and schedule tight.
-template <class R, bool kDiag>
-__device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t coset) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
-  const uint32_t M = 1u << A.m;
-  const uint32_t nthr = blockDim.x;
+// Coset `coset` of the pass's tile bits: its index bits outside the tile.
+template <class R>
+__device__ __forceinline__ Ctx coset_ctx(const TileKArgs<R>& A, uint32_t coset) {
   Ctx C;
   C.L = A.L;
   C.a = A.a;
   const uint32_t nlo = A.a - A.L;  // coset bits placed at [L, a)
   const uint32_t top = A.a + A.h;  // first coset bit above the high tile range
   C.base = ((coset & ((1u << nlo) - 1u)) << A.L) | (top >= 32 ? 0u : ((coset >> nlo) << top));
-  cplx<R>* __restrict__ psi = A.psi;
+  return C;
+}
 
-  // ---- load: pairs (pos, pos+1) are adjacent in memory (tile bit 0 = state bit 0).
-  // Tiles of >= 1024 amplitudes give every thread a multiple of kChunk pairs,
-  // so the batch of loads is issued without per-element guards.
-  const uint32_t stride = 2 * nthr;
+// ---- load: pairs (pos, pos+1) are adjacent in memory (tile bit 0 = state bit 0).
+// Tiles of >= 1024 amplitudes give every thread a multiple of kChunk pairs,
+// so the batch of loads is issued without per-element guards.
+template <class R>
+__device__ __forceinline__ void tile_load(const TileKArgs<R>& A, const Ctx& C, cplx<R>* T) {
+  const uint32_t M = 1u << A.m, stride = 2 * blockDim.x;
+  const cplx<R>* __restrict__ psi = A.psi;
   if (M >= stride * kChunk) {
     for (uint32_t p0 = 2 * threadIdx.x; p0 < M; p0 += stride * kChunk) {
       cplx2<R> v[kChunk];
@@ -310,9 +307,13 @@ __device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t 
     for (uint32_t pos = 2 * threadIdx.x; pos < M; pos += stride)
       *reinterpret_cast<cplx2<R>*>(T + lds_off(pos)) = ld_nt(reinterpret_cast<const cplx2<R>*>(psi + (C.base | C.dep(pos))));
   }
-  __syncthreads();
+}
 
-  // ---- rounds: the pattern is uniform per round, so the dispatch sits
+template <class R, bool kDiag>
+__device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C, cplx<R>* T) {
+  const uint32_t M = 1u << A.m;
+  const uint32_t nthr = blockDim.x;
+  // the pattern is uniform per round, so the dispatch sits
   // outside the per-thread group loop and every pattern runs its own loop
   // (registers loaded, transformed and stored with no value crossing a join)
   const uint32_t ngroups = M >> RB;
@@ -393,7 +394,13 @@ __device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t 
     __syncthreads();
   }
 
-  // ---- store, with the pass's butterfly normalisation
+}
+
+template <class R>
+__device__ __forceinline__ void tile_store(const TileKArgs<R>& A, const Ctx& C, const cplx<R>* T) {
+  const uint32_t M = 1u << A.m, stride = 2 * blockDim.x;
+  cplx<R>* __restrict__ psi = A.psi;
+  // with the pass's butterfly normalisation
   const R sc = (R)A.scale;
   const bool do_scale = A.scale != 1.0;
   if (M >= stride * kChunk) {
@@ -425,6 +432,17 @@ __device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t 
 }
 
 template <class R, bool kDiag>
+__device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t coset) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
+  const Ctx C = coset_ctx(A, coset);
+  tile_load<R>(A, C, T);
+  __syncthreads();
+  tile_rounds<R, kDiag>(A, C, T);
+  tile_store<R>(A, C, T);
+}
+
+template <class R, bool kDiag>
 __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
   tile_body<R, kDiag>(A, blockIdx.x);
 }
@@ -437,19 +455,17 @@ tile_kernel_c64(TileKArgs<float> A) {
   tile_body<float, false>(A, blockIdx.x);
 }
 
-// Many instances of one tile geometry in one grid: block b runs coset
-// (b & (2^shift - 1)) of instance (b >> shift).
-template <class R, bool kDiag>
-__global__ void __launch_bounds__(kMaxThreads) tile_kernel_batched(const TileKArgs<R>* __restrict__ descs,
-                                                                    uint32_t shift) {
-  // the instance's argument block, read field by field with scalar loads
-  const cptr<TileKArgs<R>> P = to_const(descs) + (blockIdx.x >> shift);
+// A batched instance's argument block, read field by field with scalar loads.
+template <class R>
+__device__ __forceinline__ TileKArgs<R> load_args(const TileKArgs<R>* descs, uint32_t i) {
+  const cptr<TileKArgs<R>> P = to_const(descs) + i;
   TileKArgs<R> A;
   A.psi = P->psi;
   A.rounds = P->rounds;
   A.ops = P->ops;
   A.coef = P->coef;
   A.diag = P->diag;
+  A.qtab = P->qtab;
   A.L = P->L;
   A.a = P->a;
   A.h = P->h;
@@ -457,7 +473,15 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel_batched(const TileKAr
   A.n_rounds = P->n_rounds;
   A.n = P->n;
   A.scale = P->scale;
-  tile_body<R, kDiag>(A, blockIdx.x & ((1u << shift) - 1u));
+  return A;
+}
+
+// Many instances of one tile geometry in one grid: block b runs coset
+// (b & (2^shift - 1)) of instance (b >> shift).
+template <class R, bool kDiag>
+__global__ void __launch_bounds__(kMaxThreads) tile_kernel_batched(const TileKArgs<R>* __restrict__ descs,
+                                                                    uint32_t shift) {
+  tile_body<R, kDiag>(load_args(descs, blockIdx.x >> shift), blockIdx.x & ((1u << shift) - 1u));
 }
 
 inline uint32_t tile_threads(uint32_t m) {

@@ -75,7 +75,9 @@ struct TileRound {
   int32_t diag_conj;         // 1: multiply by the conjugate phase (inverse)
   int32_t type;              // TileRoundType
   int32_t coef4;             // RT_MAT4*: coefficient offset of the four matrices
-  int32_t pad[2];
+  int32_t qoff;              // diag: byte offset of the round's pair table in the pass's
+                             // quadratic table, or -1 (evaluate every amplitude's counts)
+  int32_t pad;
   uint32_t loff[1 << kRoundBits];  // LDS element offset of register element j
 };
 

@@ -998,6 +998,7 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
   auto emit_round = [&](std::vector<int> bits, const std::vector<int>& ops) {
     TileRound r;
     std::memset(&r, 0, sizeof r);
+    r.qoff = -1;
     for (int tb = 0; (int)bits.size() < RB && tb < m; ++tb)
       if (std::find(bits.begin(), bits.end(), tb) == bits.end()) bits.push_back(tb);
     std::sort(bits.begin(), bits.end());

@@ -28,6 +28,38 @@ std::vector<cplx<R>> cast(const std::vector<cd>& v) {
   return o;
 }
 
+// Pair coefficients of a diagonal round.  Over the round's four register bits
+// (state bits g_0..g_3) a group's count is a polynomial of degree <= 2 when all
+// its terms are BITS, SHIFT_XOR or SHIFT_AND: x XOR y = x + y - 2xy and
+// x AND y = xy for a bond on two register bits, linear or constant otherwise.
+// The kernel then evaluates the count at the group's base index and at the
+// four single-bit flips, and adds q_kl for every pair of set register bits.
+// Table per group: {quadratic flag, q01, q02, q03, q12, q13, q23, 0}.
+void round_pair_table(const DiagNumeric& num, const int g[4], std::vector<int8_t>& out) {
+  static const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
+  for (const DiagGroup& G : num.groups) {
+    int8_t row[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+    int q[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = G.term_begin; t < G.term_end; ++t) {
+      const DiagTerm& T = num.terms[t];
+      if (T.form == DT_BITS) continue;
+      if (T.form != DT_SHIFT_XOR && T.form != DT_SHIFT_AND) {
+        row[0] = 0;
+        break;
+      }
+      for (int e = 0; e < 6; ++e) {
+        const int lo = std::min(g[pk[e]], g[pl[e]]), hi = std::max(g[pk[e]], g[pl[e]]);
+        if (hi - lo == T.shift && ((T.mask >> lo) & 1u)) q[e] += T.form == DT_SHIFT_XOR ? -2 : 1;
+      }
+    }
+    for (int e = 0; e < 6; ++e) {
+      if (q[e] < -127 || q[e] > 127) row[0] = 0;
+      row[1 + e] = (int8_t)q[e];
+    }
+    out.insert(out.end(), row, row + 8);
+  }
+}
+
 template <class R>
 void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
   const PlanIR& P = p.ir;
@@ -35,21 +67,34 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
   d.diag_groups.assign(P.diags.size(), 0);
   d.diag_lut.assign(P.diags.size(), 0);
   d.diag_ngroups.assign(P.diags.size(), 0);
+  std::vector<DiagNumeric> nums;
   for (size_t i = 0; i < P.diags.size(); ++i) {
     DiagNumeric num = diag_numeric(P.diags[i], p.params);
     d.diag_terms[i] = b.put(num.terms);
     d.diag_groups[i] = b.put(num.groups);
     d.diag_lut[i] = b.put(cast<R>(num.lut));
     d.diag_ngroups[i] = (int)num.groups.size();
+    nums.push_back(std::move(num));
   }
   d.pass_rounds.assign(P.passes.size(), 0);
   d.pass_ops.assign(P.passes.size(), 0);
   d.pass_coef.assign(P.passes.size(), 0);
   d.pass_diag.assign(P.passes.size(), 0);
+  d.pass_qtab.assign(P.passes.size(), 0);
   for (size_t i = 0; i < P.passes.size(); ++i) {
     const TilePassIR& T = P.passes[i];
     std::vector<TileRound> rounds;
     std::vector<cd> coef = pass_coefficients_device(P, T, p.params, rounds);
+    std::vector<int8_t> qtab;
+    for (TileRound& r : rounds) {
+      r.qoff = -1;
+      if (r.diag < 0) continue;
+      int g[4];
+      for (int k = 0; k < 4; ++k) g[k] = r.tbit[k] < T.L ? r.tbit[k] : r.tbit[k] - T.L + T.a;
+      r.qoff = (int32_t)qtab.size();
+      round_pair_table(nums[T.diag_slots[r.diag]], g, qtab);
+    }
+    if (!qtab.empty()) d.pass_qtab[i] = b.put(qtab);
     d.pass_rounds[i] = b.put(rounds);
     d.pass_ops[i] = b.put(T.ops);
     d.pass_coef[i] = b.put(cast<R>(coef));
@@ -167,6 +212,7 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
         A.ops = (const TileOp*)(base + d.pass_ops[L.index]);
         A.coef = (const cplx<R>*)(base + d.pass_coef[L.index]);
         A.diag = d.pass_diag[L.index] ? (const DiagDev*)(base + d.pass_diag[L.index]) : nullptr;
+        A.qtab = (const int8_t*)(base + d.pass_qtab[L.index]);
         A.L = T.L;
         A.a = T.a;
         A.h = T.h;

@@ -44,6 +44,7 @@ struct PlanDev {
   std::vector<int> diag_ngroups;
   std::vector<size_t> pass_rounds, pass_ops, pass_coef;
   std::vector<size_t> pass_diag;  // per pass: its diagonal slots as DiagDev[] (0: none)
+  std::vector<size_t> pass_qtab;  // per pass: pair coefficients of its diagonal rounds
   std::vector<size_t> dense_mat, dense_mat_dagger;  // per dense block
   std::vector<size_t> plain_mat;  // per layer (only dense plain gates), else 0
 };
