@@ -359,6 +359,47 @@ def bench_dense(qs, torch, n=30, blocks=20, seed=6, reps=2):
     return out
 
 
+def bench_families(qs, torch, n=25, reps=3):
+    """Weighted diagonal families at 25 qubits (complex64), fused plan against
+    the plain per-gate path: 5 first-order steps of the long-range Ising
+    chain (300 bonds in 24 distance groups, J(r) = 1 / r^1.5, h = 0.8,
+    dt = 0.05) and phase estimation of P(0.4) with 24 counting qubits (ladder
+    angles up to 0.4 2^23 rad)."""
+    S = 8 * (1 << n)
+    out = {}
+    cases = {"long_range_ising_5_steps": W.long_range_ising_stream(n, 1.0, 1.5, 0.8, 0.05, 5),
+             "qpe_ladder_24_counting": W.qpe_ladder_stream(n - 1, 0.4)}
+    st = qs.State(n, "c64")
+    for name, stream in cases.items():
+        plan = qs.Plan(n, stream)
+        kinds = [L["kind"] for L in plan.describe()["layers"]]
+        st.set_basis(0)
+        qs.apply(st, plan)
+        torch.cuda.synchronize()
+        with qs.profile() as prof:
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st.set_basis(0)
+                qs.apply(st, plan)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+        st.set_basis(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qs.apply_gates(st, stream)
+        st.sync()
+        t_plain = time.perf_counter() - t0
+        kern = {r["kernel"]: {"launches": r["launches"] // reps,
+                              "GBs": round(2 * S * r["launches"] / r["total_ms"] / 1e6, 1)}
+                for r in prof.report if r["kernel"] not in ("fill_basis",)}
+        out[name] = {"gates": len(stream), "layers": len(kinds), "ms_fused": round(1e3 * t, 3),
+                     "ms_plain": round(1e3 * t_plain, 2), "speedup_vs_plain": round(t_plain / t, 1),
+                     "GBs_per_pass": round(len(kinds) * 2 * S / t / 1e9, 1), "kernels": kern}
+    del st
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -473,6 +514,8 @@ def main():
         out["dense_blocks"] = bench_dense(qs, torch)
         log("single layers: 30 qubits")
         out["layers_30q"] = bench_layers(qs, torch)
+        log("weighted diagonal families: 25 qubits")
+        out["diag_families_25q"] = bench_families(qs, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

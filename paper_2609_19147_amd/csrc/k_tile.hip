@@ -94,6 +94,12 @@ __device__ __forceinline__ void op_qft(cplx<R>* a, cplx<R> w, cptr<cplx<R>> E) {
   }
 }
 
+// Twiddle numerator of a stage on bit p of a register whose lowest bit is
+// base: the index bits in [base, p).
+__device__ __forceinline__ uint32_t stage_low(uint32_t g, int p, int base) {
+  return g & ((1u << p) - 1u) & ~((1u << base) - 1u);
+}
+
 // ---- straight-line round patterns -------------------------------------------
 // Group twiddle of a stage with stage bit p: exp(i pi (g mod 2^p) / 2^p), or the
 // square of the previous stage's (bit p + 1 of the same round) when flagged.
@@ -101,8 +107,7 @@ template <class R>
 __device__ __forceinline__ cplx<R> qft_w(cptr<TileOp> op, uint32_t gglobal, cplx<R> wprev) {
   if (op->square) return cmul(wprev, wprev);
   const int p = op->sbit;
-  const uint32_t low = p == 0 ? 0u : (gglobal & ((1u << p) - 1u));
-  return cispi<R>(low, p);
+  return cispi<R>(stage_low(gglobal, p, op->base), p);
 }
 
 template <class R>
@@ -215,9 +220,9 @@ struct FMat1 {
 template <int S, class R, bool kThenH, bool kInv>
 struct FQft1 {
   cptr<cplx<R>> E;
-  int p;
+  int p, base;
   __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const {
-    const cplx<R> w = cispi<R>(p == 0 ? 0u : (g & ((1u << p) - 1u)), p);
+    const cplx<R> w = cispi<R>(stage_low(g, p, base), p);
     op_qft<S, R, kInv>(a, w, E);
     if (kThenH) op_h<S>(a);
   }
@@ -365,28 +370,28 @@ __device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C,
       case RT_QH1: {
         const cptr<TileOp> op = ops + R_->op_begin;
         const cptr<cplx<R>> E = coef + op->coef;
-        const int p = op->sbit;
+        const int p = op->sbit, base = op->base;
         switch (op->rbit & 3) {
-          case 0: L(FQft1<0, R, true, false>{E, p}); break;
-          case 1: L(FQft1<1, R, true, false>{E, p}); break;
-          case 2: L(FQft1<2, R, true, false>{E, p}); break;
-          default: L(FQft1<3, R, true, false>{E, p}); break;
+          case 0: L(FQft1<0, R, true, false>{E, p, base}); break;
+          case 1: L(FQft1<1, R, true, false>{E, p, base}); break;
+          case 2: L(FQft1<2, R, true, false>{E, p, base}); break;
+          default: L(FQft1<3, R, true, false>{E, p, base}); break;
         }
         break;
       }
       default: {  // RT_QFT1
         const cptr<TileOp> op = ops + R_->op_begin;
         const cptr<cplx<R>> E = coef + op->coef;
-        const int p = op->sbit;
+        const int p = op->sbit, base = op->base;
         switch ((op->kind == OP_QFT_INV ? 4 : 0) + (op->rbit & 3)) {
-          case 0: L(FQft1<0, R, false, false>{E, p}); break;
-          case 1: L(FQft1<1, R, false, false>{E, p}); break;
-          case 2: L(FQft1<2, R, false, false>{E, p}); break;
-          case 3: L(FQft1<3, R, false, false>{E, p}); break;
-          case 4: L(FQft1<0, R, false, true>{E, p}); break;
-          case 5: L(FQft1<1, R, false, true>{E, p}); break;
-          case 6: L(FQft1<2, R, false, true>{E, p}); break;
-          default: L(FQft1<3, R, false, true>{E, p}); break;
+          case 0: L(FQft1<0, R, false, false>{E, p, base}); break;
+          case 1: L(FQft1<1, R, false, false>{E, p, base}); break;
+          case 2: L(FQft1<2, R, false, false>{E, p, base}); break;
+          case 3: L(FQft1<3, R, false, false>{E, p, base}); break;
+          case 4: L(FQft1<0, R, false, true>{E, p, base}); break;
+          case 5: L(FQft1<1, R, false, true>{E, p, base}); break;
+          case 6: L(FQft1<2, R, false, true>{E, p, base}); break;
+          default: L(FQft1<3, R, false, true>{E, p, base}); break;
         }
         break;
       }

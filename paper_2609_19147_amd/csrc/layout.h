@@ -41,7 +41,9 @@ struct TileOp {
   int32_t coef;    // offset into the pass's coefficient array (complex entries)
   int32_t slot;    // OP_GRAD: gradient accumulator index; else -1
   int32_t square;  // OP_QFT: 1 = the group twiddle is the square of the previous op's
-  int32_t pad[2];
+  int32_t base;    // OP_QFT / OP_QFT_INV: lowest state bit of the register (the
+                   // twiddle reads state bits [base, sbit))
+  int32_t pad;
 };
 
 // LDS layout of a tile: position j is stored at element j + 2 (j >> 5) (two

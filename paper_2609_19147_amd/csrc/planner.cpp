@@ -328,10 +328,20 @@ DiagIR diag_observable(int n, const qs_pauli* terms, size_t n_terms) {
   return build_diag(raw, gl);
 }
 
+// exp(i c th) with the product c th carried as hi + lo (lo = the rounding error
+// of the FP64 product, exact by FMA); the library's sin / cos reduce hi
+// exactly, so large angles (e.g. phase ladders up to ~1e7 rad) lose nothing
+// to a reduction against an FP64 approximation of 2 pi.
+static cd cis_product(double th, int c) {
+  const double hi = th * (double)c;
+  const double lo = std::fma(th, (double)c, -hi);
+  return std::polar(1.0, hi) * cd(std::cos(lo), std::sin(lo));
+}
+
 DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj) {
   DiagNumeric out;
   double gl = d.global.eval(params);
-  cd gph = std::polar(1.0, std::remainder(gl, 2 * kPi));
+  cd gph = std::polar(1.0, gl);
   if (d.groups.empty()) {
     out.groups.push_back({0, 0, 0, 1});
     out.lut.push_back(conj ? std::conj(gph) : gph);
@@ -347,9 +357,7 @@ DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, boo
     dg.lut_len = G.max_count + 1;
     double th = G.angle.eval(params);
     for (int c = 0; c <= G.max_count; ++c) {
-      // angle * count in FP64, reduced mod 2 pi before the trigonometry
-      double ang = std::remainder(th * (double)c, 2 * kPi);
-      cd v = std::polar(1.0, ang);
+      cd v = cis_product(th, c);
       if (gi == 0) v *= gph;
       out.lut.push_back(conj ? std::conj(v) : v);
     }
@@ -651,10 +659,24 @@ class Builder {
     while (i < G.size()) {
       const NGate& g = G[i];
       size_t used = 0;
-      if (g.kind == QS_GATE_H && (used = qft_stage_len(i)) > 0) {
+      int base = 0;
+      if (g.kind == QS_GATE_H && (used = qft_stage_len(i, &base)) > 0) {
         close_open();
-        add_op_item(OpIR{OP_QFT, g.bits[0], {}, false, -1});
+        OpIR op{OP_QFT, g.bits[0], {}, false, -1};
+        op.base = base;
+        add_op_item(op);
         last_qft_bit = g.bits[0];
+        last_qft_base = base;
+        i += used;
+        continue;
+      }
+      if (g.kind == QS_GATE_CPHASE && (used = qft_inv_stage_len(i, &base)) > 0) {
+        // inverse QFT stage: the controlled-phase ladder undone, then H
+        close_open();
+        OpIR op{OP_QFT_INV, P.gates[i + used - 1].bits[0], {}, false, -1};
+        op.base = base;
+        add_op_item(op);
+        last_qft_bit = -1;
         i += used;
         continue;
       }
@@ -706,28 +728,62 @@ class Builder {
   std::vector<int> diag, perm, pp;
   std::vector<std::vector<int>> window;
   std::vector<Item> seg;
-  int last_qft_bit = -1;
+  int last_qft_bit = -1, last_qft_base = 0;
 
-  // Number of gates of a QFT stage starting at gate i (H on bit p followed by
-  // CPHASE(pi / 2^(p-b)) on (b, p) for every b < p, in any order), or 0.
-  size_t qft_stage_len(size_t i) const {
+  // Number of gates of a QFT stage starting at gate i, or 0: H on bit p
+  // followed by CPHASE(pi / 2^(p-b)) on (b, p) for every b in [r0, p), in any
+  // order (a register whose lowest bit is r0, *base).  A lone H right after the
+  // stage on bit p + 1 of a register based at p is that register's last stage.
+  size_t qft_stage_len(size_t i, int* base) const {
     const auto& G = P.gates;
-    int p = G[i].bits[0];
-    if (p == 0) return last_qft_bit == 1 ? 1 : 0;
-    if (i + (size_t)p >= G.size()) return 0;
+    const int p = G[i].bits[0];
     uint32_t seen = 0;
-    for (int j = 1; j <= p; ++j) {
-      const NGate& c = G[i + j];
-      if (c.kind != QS_GATE_CPHASE || !c.angle.is_const()) return 0;
-      int a = c.bits[0], b = c.bits[1];
-      int other = a == p ? b : b == p ? a : -1;
-      if (other < 0 || other >= p) return 0;
-      if ((seen >> other) & 1) return 0;
-      double want = std::ldexp(kPi, -(p - other));
-      if (c.angle.c0 != want) return 0;
+    size_t j = i + 1;
+    for (; j < G.size(); ++j) {
+      const NGate& c = G[j];
+      if (c.kind != QS_GATE_CPHASE || !c.angle.is_const()) break;
+      const int a = c.bits[0], b = c.bits[1];
+      const int other = a == p ? b : b == p ? a : -1;
+      if (other < 0 || other >= p || ((seen >> other) & 1)) break;
+      if (c.angle.c0 != std::ldexp(kPi, -(p - other))) break;
       seen |= 1u << other;
     }
-    return (size_t)p + 1;
+    const int k = (int)(j - i - 1);
+    if (k == 0) {
+      *base = p;
+      return last_qft_bit == p + 1 && last_qft_base == p ? 1 : 0;
+    }
+    const int r0 = p - k;
+    if (seen != (((1u << p) - 1u) & ~((1u << r0) - 1u))) return 0;
+    *base = r0;
+    return (size_t)k + 1;
+  }
+
+  // Number of gates of an inverse QFT stage starting at gate i, or 0:
+  // CPHASE(-pi / 2^(p-b)) on (b, p) for every b in [r0, p), in any order, then
+  // H on bit p (*base = r0).
+  size_t qft_inv_stage_len(size_t i, int* base) const {
+    const auto& G = P.gates;
+    const NGate& g0 = G[i];
+    if (g0.bits.size() != 2) return 0;
+    const int p = std::max(g0.bits[0], g0.bits[1]);
+    uint32_t seen = 0;
+    size_t j = i;
+    for (; j < G.size(); ++j) {
+      const NGate& c = G[j];
+      if (c.kind != QS_GATE_CPHASE || !c.angle.is_const()) break;
+      const int a = c.bits[0], b = c.bits[1];
+      const int other = a == p ? b : b == p ? a : -1;
+      if (other < 0 || other >= p || ((seen >> other) & 1)) break;
+      if (c.angle.c0 != -std::ldexp(kPi, -(p - other))) break;
+      seen |= 1u << other;
+    }
+    const int k = (int)(j - i);
+    if (k == 0 || j >= G.size() || G[j].kind != QS_GATE_H || G[j].bits[0] != p) return 0;
+    const int r0 = p - k;
+    if (seen != (((1u << p) - 1u) & ~((1u << r0) - 1u))) return 0;
+    *base = r0;
+    return (size_t)k + 1;
   }
 
   void open_block(Open o) {
@@ -768,7 +824,7 @@ class Builder {
     Item it;
     it.ir = {0, (int32_t)P.ops.size()};
     it.W = 1u << op.bit;
-    if (op.kind == OP_QFT) it.R = (op.bit == 0) ? 0u : ((1u << op.bit) - 1);
+    if (op.kind == OP_QFT || op.kind == OP_QFT_INV) it.R = ((1u << op.bit) - 1u) & ~((1u << op.base) - 1u);
     P.ops.push_back(std::move(op));
     seg.push_back(it);
   }
@@ -947,8 +1003,9 @@ int tile_state_bit(const TilePassIR& T, int tb) { return tb < T.L ? tb : T.a + (
 // writes its bit; a QFT stage on bit p also reads every bit below p.
 bool ops_conflict(const OpIR& a, const OpIR& b) {
   uint32_t Wa = 1u << a.bit, Wb = 1u << b.bit;
-  uint32_t Ra = a.kind == OP_QFT && a.bit ? (1u << a.bit) - 1 : 0;
-  uint32_t Rb = b.kind == OP_QFT && b.bit ? (1u << b.bit) - 1 : 0;
+  const bool qa = a.kind == OP_QFT || a.kind == OP_QFT_INV, qb = b.kind == OP_QFT || b.kind == OP_QFT_INV;
+  uint32_t Ra = qa ? ((1u << a.bit) - 1u) & ~((1u << a.base) - 1u) : 0;
+  uint32_t Rb = qb ? ((1u << b.bit) - 1u) & ~((1u << b.base) - 1u) : 0;
   return (Wa & (Wb | Rb)) || (Wb & Ra);
 }
 
@@ -1018,13 +1075,14 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
       std::memset(&op, 0, sizeof op);
       op.kind = o.kind;
       op.sbit = o.bit;
+      op.base = o.base;
       int tb = tile_pos(T, o.bit);
       op.rbit = (int32_t)(std::find(bits.begin(), bits.end(), tb) - bits.begin());
       op.coef = T.n_coef;
       op.slot = -1;
       if (o.kind == OP_MAT) T.n_coef += 4;
       else if (o.kind == OP_DIAG) T.n_coef += 2;
-      else if (o.kind == OP_QFT) T.n_coef += 1 << op.rbit;
+      else if (o.kind == OP_QFT || o.kind == OP_QFT_INV) T.n_coef += 1 << op.rbit;
       if (o.kind == OP_QFT) {
         // exp(i pi low_p / 2^p) = (exp(i pi low_{p+1} / 2^{p+1}))^2 when bit p is a
         // round bit (zero in the group base); square at most once in a row
@@ -1032,7 +1090,7 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
         prev_fresh = !op.square;
         prev_qft_bit = o.bit;
       }
-      if (o.kind == OP_H || o.kind == OP_QFT) T.n_butterfly += 1;
+      if (o.kind == OP_H || o.kind == OP_QFT || o.kind == OP_QFT_INV) T.n_butterfly += 1;
       T.ops.push_back(op);
       T.op_src.push_back(oi);
     }
@@ -1215,8 +1273,10 @@ std::vector<cd> pass_coefficients(const PlanIR& P, const TilePassIR& T, const st
       int s = op.rbit, p = op.sbit;
       for (int kk = 0; kk < (1 << s); ++kk) {
         double frac = 0.0;  // sum bit_t(kk) 2^(sb_t - p), exact in FP64
-        for (int t = 0; t < s; ++t)
-          if ((kk >> t) & 1) frac += std::ldexp(1.0, tile_state_bit(T, R->tbit[t]) - p);
+        for (int t = 0; t < s; ++t) {
+          const int sb = tile_state_bit(T, R->tbit[t]);
+          if (((kk >> t) & 1) && sb >= op.base) frac += std::ldexp(1.0, sb - p);
+        }
         coef[op.coef + kk] = std::polar(1.0, kPi * frac);
       }
     }
@@ -1287,11 +1347,12 @@ static TilePassIR invert_pass(const PlanIR& P, const TilePassIR& F) {
     for (auto it = fwd_ops.rbegin(); it != fwd_ops.rend(); ++it) {
       TileOp op = F.ops[*it];
       if (op.kind == OP_QFT) op.kind = OP_QFT_INV;
+      else if (op.kind == OP_QFT_INV) op.kind = OP_QFT;
       op.square = 0;
       op.coef = T.n_coef;
       if (op.kind == OP_MAT) T.n_coef += 4;
       else if (op.kind == OP_DIAG) T.n_coef += 2;
-      else if (op.kind == OP_QFT_INV) T.n_coef += 1 << op.rbit;
+      else if (op.kind == OP_QFT_INV || op.kind == OP_QFT) T.n_coef += 1 << op.rbit;
       T.ops.push_back(op);
       T.op_src.push_back(F.op_src[*it]);
     }
@@ -1309,13 +1370,14 @@ static TilePassIR invert_pass(const PlanIR& P, const TilePassIR& F) {
         q.diag = first ? r.diag : -1;
         first = false;
         q.op_begin = k;
-        if (T.ops[k].kind == OP_QFT_INV) {
+        if (T.ops[k].kind == OP_QFT_INV || T.ops[k].kind == OP_QFT) {
           q.op_end = k + 1;
           q.type = RT_QFT1;
         } else {
           uint32_t seen = 0;
           int e = k;
-          while (e < r.op_end && T.ops[e].kind != OP_QFT_INV && !((seen >> T.ops[e].rbit) & 1)) {
+          while (e < r.op_end && T.ops[e].kind != OP_QFT_INV && T.ops[e].kind != OP_QFT &&
+                 !((seen >> T.ops[e].rbit) & 1)) {
             seen |= 1u << T.ops[e].rbit;
             ++e;
           }
@@ -1579,7 +1641,7 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
         auto& op = T.ops[k];
         if (k) o << ",";
         o << "{\"kind\":" << op.kind << ",\"bit\":" << op.sbit << ",\"rbit\":" << op.rbit
-          << ",\"square\":" << op.square;
+          << ",\"square\":" << op.square << ",\"base\":" << op.base;
         if (bound) {
           int nc = op.kind == OP_MAT ? 4 : op.kind == OP_DIAG ? 2
                    : (op.kind == OP_QFT || op.kind == OP_QFT_INV) ? (1 << op.rbit) : 0;

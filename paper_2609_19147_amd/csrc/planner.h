@@ -79,6 +79,7 @@ struct OpIR {
   std::vector<int32_t> gates;
   bool fixed_h = false;  // OP_H produced by a basis change (no source gates)
   int32_t fixed_mat = -1;  // basis-change matrix id (0: H S^dagger, 1: S H)
+  int32_t base = 0;        // OP_QFT / OP_QFT_INV: the register's lowest state bit
 };
 
 struct ItemIR {

@@ -4,8 +4,8 @@ Applies the layers exactly as the plan states them -- tile passes round by
 round, diagonal layers from their FP64 lookup tables, GF(2) gathers from
 their row masks -- so the planner's rewrite can be checked against the
 one-gate-at-a-time oracle on the CPU, without a GPU.  QFT stages use the
-plain stage definition (butterfly on bit p, then exp(i pi (i mod 2^p) / 2^p)
-on the bit-p = 1 half).  Dense layers apply the matrix the plan carries;
+plain stage definition (butterfly on bit p, then exp(i pi low / 2^p) on the
+bit-p = 1 half, low = the index bits in [base, p)).  Dense layers apply the matrix the plan carries;
 plain layers call the oracle's gate application.
 """
 from __future__ import annotations
@@ -110,13 +110,13 @@ def apply_layer(psi, n, L, stream, params):
             elif op["kind"] == 2:
                 apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
                 i = np.arange(1 << n, dtype=np.int64)
-                low = i & ((1 << b) - 1)
+                low = i & ((1 << b) - 1) & ~((1 << op.get("base", 0)) - 1)
                 tw = np.exp(1j * math.pi * low / (1 << b))
                 sel = ((i >> b) & 1) == 1
                 psi[sel] *= tw[sel]
             elif op["kind"] == 4:  # inverse QFT stage: undo the twiddle, then the butterfly
                 i = np.arange(1 << n, dtype=np.int64)
-                low = i & ((1 << b) - 1)
+                low = i & ((1 << b) - 1) & ~((1 << op.get("base", 0)) - 1)
                 tw = np.exp(-1j * math.pi * low / (1 << b))
                 sel = ((i >> b) & 1) == 1
                 psi[sel] *= tw[sel]

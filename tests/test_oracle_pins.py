@@ -383,3 +383,36 @@ def test_inverse_stream_returns_input():
     psi0 = W.gaussian_state(n, 8)
     back = sv.run(sv.run(psi0, n, st), n, sv.inverse_stream(st))
     assert metrics.infidelity(back, psi0) < 1e-28
+
+
+# ---------------------------------------------------------------- weighted diagonal families
+@pytest.mark.parametrize("t,j", [(5, 0), (5, 19), (7, 100), (8, 255)])
+def test_qpe_exact_phase_gives_one_basis_state(t, j):
+    # theta = 2 pi j / 2^t: the counting register ends in |j>, target in |1>
+    n = t + 1
+    psi = sv.run(sv.basis(n, 0), n, W.qpe_ladder_stream(t, 2 * math.pi * j / 2 ** t))
+    assert abs(abs(psi[(j << 1) | 1]) ** 2 - 1) < 1e-12
+
+
+def test_qpe_large_angle_ladder_equals_small_angle_ladder():
+    # theta 2^p with theta 2^p = 2 pi j / 2^t + 2 pi m: the same state although
+    # the ladder's angles reach ~1e7 rad (exercises the phase reduction)
+    t, j, p = 6, 11, 20
+    theta = (2 * math.pi * j / 2 ** t + 2 * math.pi * 3) / 2 ** p
+    n = t + 1
+    big = sv.run(sv.basis(n, 0), n, W.qpe_ladder_stream(t, theta, first_power=p))
+    assert abs(abs(big[(j << 1) | 1]) ** 2 - 1) < 1e-9
+
+
+def test_long_range_ising_zz_layer_is_exact_diagonal_evolution():
+    # one step with h = 0: exp(+i dt sum J(r) Z_i Z_j) exactly (all terms commute)
+    n, j0, alpha, dt = 6, 1.0, 1.5, 0.07
+    stream = W.long_range_ising_stream(n, j0, alpha, 0.0, dt, 1)
+    psi0 = W.gaussian_state(n, 8)
+    got = sv.run(psi0, n, stream)
+    terms = []
+    for i in range(n):
+        for k in range(i + 1, n):
+            terms.append((-j0 / (k - i) ** alpha, 0, (1 << i) | (1 << k)))
+    ref = hamiltonian.evolve(n, terms, dt, psi0)
+    assert np.max(np.abs(got - ref)) < 1e-13

@@ -266,3 +266,33 @@ def test_inverse_plan_undoes_the_plan(case):
         np.testing.assert_allclose(fwd, sv.run(psi0, n, st, params), atol=1e-12)
         back = run_plan(inv.describe(), fwd, st, params)
         assert np.max(np.abs(back - psi0)) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["lr_ising", "qpe_big"])
+def test_weighted_diagonal_families(case):
+    if case == "lr_ising":
+        n = 10
+        st = W.long_range_ising_stream(n, 1.0, 1.5, 0.8, 0.05, 2)
+        d = check_plan(n, st, tol=1e-12)
+        groups = [len(dd["lut_groups"]) for L in d["layers"] for dd in L.get("diags", [L.get("diag")]) if dd]
+        assert max(groups) == n - 1  # one group per bond distance
+    else:
+        t = 9
+        st = W.qpe_ladder_stream(t, 0.4, first_power=23 - (t - 1))  # angles up to 0.4 * 2^23
+        check_plan(t + 1, st, psi0=sv.basis(t + 1, 0), tol=1e-12)
+
+
+@pytest.mark.parametrize("offset", [1, 3])
+def test_qft_and_inverse_qft_on_an_upper_register(offset):
+    # the register's wires are 0..t-1 of an (t + offset)-qubit state: its lowest
+    # state bit is `offset`, so every stage's twiddle reads bits [offset, p)
+    t = 8
+    n = t + offset
+    fwd = W.qft_stream(t)
+    inv = [W.G("CPHASE", *g.wires, theta=-g.theta) if g.name == "CPHASE" else g for g in reversed(fwd)]
+    for stream, kind in ((fwd, 2), (inv, 4)):
+        d = check_plan(n, stream, tol=1e-12)
+        ops = [o for L in d["layers"] for o in L.get("ops", [])]
+        stages = [o for o in ops if o["kind"] == kind]
+        assert len(stages) >= t - 1 and all(o["base"] == offset for o in stages)
+        assert "diag" not in kinds(d)

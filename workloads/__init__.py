@@ -365,6 +365,38 @@ def random_unitary(dim: int, rng: np.random.Generator) -> np.ndarray:
     return q * (d / np.abs(d))
 
 
+def long_range_ising_stream(n: int, j0: float, alpha: float, h: float, dt: float, steps: int) -> List[Gate]:
+    """Long-range transverse-field Ising Trotter evolution from |0...0>:
+    H = -sum_{i<j} J(|i-j|) Z_i Z_j + h sum_i X_i with J(r) = j0 / r^alpha (all
+    n(n-1)/2 bonds, n-1 distance classes).  Per first-order step: the ZZ layer
+    as RZZ(-2 J(r) dt) on every bond (bonds ordered by distance), then
+    RX(2 h dt) on every qubit."""
+    out: List[Gate] = []
+    for _ in range(steps):
+        for r in range(1, n):
+            th = -2.0 * j0 / r ** alpha * dt
+            out += [G("RZZ", i, i + r, theta=th) for i in range(n - r)]
+        out += [G("RX", q, theta=2.0 * h * dt) for q in range(n)]
+    return out
+
+
+def qpe_ladder_stream(t: int, theta: float, first_power: int = 0) -> List[Gate]:
+    """Phase estimation of P(theta) on one target qubit (wire t, prepared in
+    |1>, its e^{i theta} eigenstate) with t counting qubits: H on the counting
+    wires, controlled-P(theta 2^(first_power + k)) from counting wire k to the
+    target, then the inverse QFT (the QFT stream reversed, conjugated) on the
+    counting wires.  For theta 2^first_power = 2 pi j / 2^t the counting
+    register ends in |j> exactly.  The ladder's angles reach
+    theta 2^(first_power + t - 1)."""
+    out: List[Gate] = [G("X", t)] + [G("H", q) for q in range(t)]
+    for k in range(t):
+        out.append(G("CPHASE", k, t, theta=theta * 2.0 ** (first_power + k)))
+    inv = []
+    for g in reversed(qft_stream(t)):
+        inv.append(G("CPHASE", *g.wires, theta=-g.theta) if g.name == "CPHASE" else g)
+    return out + inv
+
+
 def dense_block_stream(n: int, count: int, k: int, seed: int) -> List[Gate]:
     """``count`` UNITARY gates on k distinct random wires each, with Haar-ish
     2^k x 2^k matrices (the dense-block microbenchmark's input)."""
