@@ -181,7 +181,7 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
     for (const auto& kv : diag_slot[fl]) {
       const char* base = (const char*)d.blob;
       const int di = kv.first.first;
-      DiagDev D;
+      DiagDev D{};
       D.terms = (const DiagTerm*)(base + d.diag_terms[di]);
       D.groups = (const DiagGroup*)(base + d.diag_groups[di]);
       D.lut = base + d.diag_lut[di];

@@ -132,9 +132,11 @@ __device__ __forceinline__ cplx<double> cispi<double>(uint32_t num, int p) { ret
 struct DiagDev {
   const DiagTerm* terms;
   const DiagGroup* groups;
-  const void* lut;  // cplx<R>
+  const void* lut;      // cplx<R>
   int32_t n_groups;
   int32_t conj;
+  const double* theta;  // per group: its angle reduced to (-pi, pi] (angle mode)
+  double global;        // the layer's global phase angle, reduced (angle mode)
 };
 
 template <class R>
@@ -244,6 +246,77 @@ __device__ __forceinline__ void diag_apply(cplx<R>* a, uint32_t i0, const uint32
 // table (qt, 8 bytes per group) says the count is a polynomial of degree <= 2
 // in the four bits, counts come from 5 evaluations (i0 and the single flips)
 // and the pair coefficients; other groups evaluate all 16 indices.
+// exp(i x) for an FP64 angle: reduced to [-pi, pi] against 2 pi split in two
+// doubles, then sin / cos in the state's precision.
+__device__ __forceinline__ double reduce_2pi(double x) {
+  const double k = rint(x * 0.15915494309189535);
+  x = fma(-k, 6.283185307179586, x);
+  return fma(-k, 2.4492935982947064e-16, x);
+}
+template <class R>
+__device__ __forceinline__ cplx<R> cis_reduced(double x);
+template <>
+__device__ __forceinline__ cplx<float> cis_reduced<float>(double x) {
+  float s, c;
+  sincosf((float)reduce_2pi(x), &s, &c);
+  return {c, s};
+}
+template <>
+__device__ __forceinline__ cplx<double> cis_reduced<double>(double x) {
+  double s, c;
+  sincos(reduce_2pi(x), &s, &c);
+  return {c, s};
+}
+
+// Angle mode: every group quadratic in the round's bits, so the total phase
+// angle sum_g theta_g count_g over the 16 amplitudes is A0 + sum_k x_k D_k +
+// sum_{k<l} x_k x_l Q_kl; A0 and D_k come from 5 evaluations per group in
+// FP64, exp(i Q_kl) are host constants (qp[0..5] for pairs 01 02 03 12 13 23).
+template <class R>
+__device__ __forceinline__ void diag_apply_angles(cplx<R>* a, uint32_t i0, uint32_t b0, uint32_t b1, uint32_t b2,
+                                                  uint32_t b3, const DiagDev& D, const cplx<R>* qp_) {
+  const cptr<DiagGroup> groups = to_const(D.groups);
+  const cptr<double> theta = to_const(D.theta);
+  const cptr<cplx<R>> qp = to_const(qp_);
+  const uint32_t off5[5] = {0u, b0, b1, b2, b3};
+  double A0 = D.global, Dk[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g = 0; g < D.n_groups; ++g) {
+    int c5[5];
+    diag_counts<5>(i0, off5, D.terms, groups[g].term_begin, groups[g].term_end, c5);
+    const double th = theta[g];
+    A0 = fma(th, (double)c5[0], A0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Dk[k] = fma(th, (double)(c5[k + 1] - c5[0]), Dk[k]);
+  }
+  const double sg = D.conj ? -1.0 : 1.0;
+  cplx<R> e[4], ph[16];
+  ph[0] = cis_reduced<R>(sg * A0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) e[k] = cis_reduced<R>(sg * Dk[k]);
+  cplx<R> q[4][4];
+  {
+    const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const cplx<R> v = ldc(qp, t);
+      q[pk[t]][pl[t]] = D.conj ? cconj(v) : v;
+    }
+  }
+  // ph[j] = ph[j without its top bit t] e_t prod_{k in rest} exp(i Q_kt)
+#pragma unroll
+  for (int j = 1; j < 16; ++j) {
+    const int t = j >= 8 ? 3 : j >= 4 ? 2 : j >= 2 ? 1 : 0;
+    const int rest = j & ~(1 << t);
+    cplx<R> v = cmul(ph[rest], e[t]);
+#pragma unroll
+    for (int k = 0; k < t; ++k)
+      if ((rest >> k) & 1) v = cmul(v, q[k][t]);
+    ph[j] = v;
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) a[j] = cmul(a[j], ph[j]);
+}
+
 template <class R>
 __device__ __forceinline__ void diag_apply_round(cplx<R>* a, uint32_t i0, uint32_t b0, uint32_t b1, uint32_t b2,
                                                  uint32_t b3, const DiagDev& D, const int8_t* qt_) {

@@ -237,6 +237,8 @@ __device__ __forceinline__ DiagDev diag_slot(const DiagDev* slots, int d) {
   D.lut = S->lut;
   D.n_groups = S->n_groups;
   D.conj = S->conj;
+  D.theta = S->theta;
+  D.global = S->global;
   return D;
 }
 
@@ -267,8 +269,11 @@ struct RoundLoop {
       const uint32_t gglobal = C.base | C.dep(gpos);
       if (kDiag && R_->diag >= 0) {
         // register j holds index gglobal | dep(round bits of j)
-        diag_apply_round<R>(a, gglobal, C.dep(1u << t0), C.dep(1u << t1), C.dep(1u << t2), C.dep(1u << t3),
-                            diag_slot(A.diag, R_->diag), A.qtab + R_->qoff);
+        const uint32_t b0 = C.dep(1u << t0), b1 = C.dep(1u << t1), b2 = C.dep(1u << t2), b3 = C.dep(1u << t3);
+        if (R_->qcoef >= 0)
+          diag_apply_angles<R>(a, gglobal, b0, b1, b2, b3, diag_slot(A.diag, R_->diag), A.coef + R_->qcoef);
+        else
+          diag_apply_round<R>(a, gglobal, b0, b1, b2, b3, diag_slot(A.diag, R_->diag), A.qtab + R_->qoff);
       }
       f(a, gglobal);
 #pragma unroll

@@ -79,7 +79,8 @@ struct TileRound {
   int32_t coef4;             // RT_MAT4*: coefficient offset of the four matrices
   int32_t qoff;              // diag: byte offset of the round's pair table in the pass's
                              // quadratic table, or -1 (evaluate every amplitude's counts)
-  int32_t pad;
+  int32_t qcoef;             // diag, angle mode: coefficient offset of the six pair
+                             // phases exp(i Q_kl); -1: lookup-table mode
   uint32_t loff[1 << kRoundBits];  // LDS element offset of register element j
 };
 

@@ -338,13 +338,21 @@ static cd cis_product(double th, int c) {
   return std::polar(1.0, hi) * cd(std::cos(lo), std::sin(lo));
 }
 
+double reduce_2pi(double x) {
+  const double hi = 6.283185307179586, lo = 2.4492935982947064e-16;  // 2 pi = hi + lo
+  const double k = std::nearbyint(x / hi);
+  return std::fma(-k, lo, std::fma(-k, hi, x));
+}
+
 DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj) {
   DiagNumeric out;
   double gl = d.global.eval(params);
   cd gph = std::polar(1.0, gl);
+  out.global = reduce_2pi(conj ? -gl : gl);
   if (d.groups.empty()) {
     out.groups.push_back({0, 0, 0, 1});
     out.lut.push_back(conj ? std::conj(gph) : gph);
+    out.theta.push_back(0.0);
     return out;
   }
   for (size_t gi = 0; gi < d.groups.size(); ++gi) {
@@ -356,6 +364,7 @@ DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, boo
     dg.lut_begin = (int32_t)out.lut.size();
     dg.lut_len = G.max_count + 1;
     double th = G.angle.eval(params);
+    out.theta.push_back(reduce_2pi(conj ? -th : th));
     for (int c = 0; c <= G.max_count; ++c) {
       cd v = cis_product(th, c);
       if (gi == 0) v *= gph;

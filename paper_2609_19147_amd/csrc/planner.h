@@ -158,7 +158,11 @@ struct DiagNumeric {
   std::vector<DiagTerm> terms;
   std::vector<DiagGroup> groups;
   std::vector<cd> lut;
+  std::vector<double> theta;  // per group: its angle reduced to [-pi, pi]
+  double global = 0.0;        // global phase angle, reduced
 };
+// x mod 2 pi in [-pi, pi], against 2 pi carried in two doubles.
+double reduce_2pi(double x);
 DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj = false);
 // Diagonal observable sum_t c_t Z-string_t as value(i) = global + sum_g angle_g
 // count_g(i) (the groups' "angles" are the real weights -2 c).

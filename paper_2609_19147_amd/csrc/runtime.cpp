@@ -28,6 +28,10 @@ std::vector<cplx<R>> cast(const std::vector<cd>& v) {
   return o;
 }
 
+// Diagonal rounds of layers with at least this many groups (all quadratic)
+// evaluate the total phase angle instead of one table lookup per group.
+constexpr int kAngleModeGroups = 3;
+
 // Pair coefficients of a diagonal round.  Over the round's four register bits
 // (state bits g_0..g_3) a group's count is a polynomial of degree <= 2 when all
 // its terms are BITS, SHIFT_XOR or SHIFT_AND: x XOR y = x + y - 2xy and
@@ -67,6 +71,8 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
   d.diag_groups.assign(P.diags.size(), 0);
   d.diag_lut.assign(P.diags.size(), 0);
   d.diag_ngroups.assign(P.diags.size(), 0);
+  d.diag_theta.assign(P.diags.size(), 0);
+  d.diag_global.assign(P.diags.size(), 0.0);
   std::vector<DiagNumeric> nums;
   for (size_t i = 0; i < P.diags.size(); ++i) {
     DiagNumeric num = diag_numeric(P.diags[i], p.params);
@@ -74,6 +80,8 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
     d.diag_groups[i] = b.put(num.groups);
     d.diag_lut[i] = b.put(cast<R>(num.lut));
     d.diag_ngroups[i] = (int)num.groups.size();
+    d.diag_theta[i] = b.put(num.theta);
+    d.diag_global[i] = num.global;
     nums.push_back(std::move(num));
   }
   d.pass_rounds.assign(P.passes.size(), 0);
@@ -88,11 +96,25 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
     std::vector<int8_t> qtab;
     for (TileRound& r : rounds) {
       r.qoff = -1;
+      r.qcoef = -1;
       if (r.diag < 0) continue;
       int g[4];
       for (int k = 0; k < 4; ++k) g[k] = r.tbit[k] < T.L ? r.tbit[k] : r.tbit[k] - T.L + T.a;
       r.qoff = (int32_t)qtab.size();
-      round_pair_table(nums[T.diag_slots[r.diag]], g, qtab);
+      const DiagNumeric& num = nums[T.diag_slots[r.diag]];
+      round_pair_table(num, g, qtab);
+      // angle mode for layers with many groups, all quadratic: the six pair
+      // phases exp(i sum_g theta_g q_g,kl) join the pass's coefficients
+      bool all_quad = num.groups.size() >= (size_t)kAngleModeGroups;
+      for (size_t gi = 0; gi < num.groups.size(); ++gi) all_quad = all_quad && qtab[r.qoff + 8 * gi] != 0;
+      if (all_quad) {
+        r.qcoef = (int32_t)coef.size();
+        for (int e = 0; e < 6; ++e) {
+          double Q = 0.0;
+          for (size_t gi = 0; gi < num.groups.size(); ++gi) Q += num.theta[gi] * qtab[r.qoff + 8 * gi + 1 + e];
+          coef.push_back(std::polar(1.0, Q));
+        }
+      }
     }
     if (!qtab.empty()) d.pass_qtab[i] = b.put(qtab);
     d.pass_rounds[i] = b.put(rounds);
@@ -111,12 +133,14 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
 }
 
 DiagDev diag_dev(const PlanDev& d, const char* base, int i, bool conj) {
-  DiagDev D;
+  DiagDev D{};
   D.terms = (const DiagTerm*)(base + d.diag_terms[i]);
   D.groups = (const DiagGroup*)(base + d.diag_groups[i]);
   D.lut = base + d.diag_lut[i];
   D.n_groups = d.diag_ngroups[i];
   D.conj = conj ? 1 : 0;
+  D.theta = (const double*)(base + d.diag_theta[i]);
+  D.global = d.diag_global[i];
   return D;
 }
 

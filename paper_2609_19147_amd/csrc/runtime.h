@@ -42,6 +42,8 @@ struct PlanDev {
   bool valid = false;
   std::vector<size_t> diag_terms, diag_groups, diag_lut;
   std::vector<int> diag_ngroups;
+  std::vector<size_t> diag_theta;   // per diagonal layer: reduced group angles (double)
+  std::vector<double> diag_global;  // per diagonal layer: reduced global phase angle
   std::vector<size_t> pass_rounds, pass_ops, pass_coef;
   std::vector<size_t> pass_diag;  // per pass: its diagonal slots as DiagDev[] (0: none)
   std::vector<size_t> pass_qtab;  // per pass: pair coefficients of its diagonal rounds
