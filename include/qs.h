@@ -210,6 +210,21 @@ qs_status qs_infidelity(qs_state* a, qs_state* b, double* out);
  * host_amps (count amplitudes of the state's dtype, interleaved; sync). */
 qs_status qs_amplitudes(qs_state* s, const uint64_t* idx, size_t count, void* host_amps);
 
+/* ---- read-out (paper, Sections "State Management" and "Algorithm
+ * Implementations": measurement and sampling from the state) ------------- */
+/* Shot sampling of p_i = |psi_i|^2 / ||psi||^2.  For each caller-provided
+ * uniform number u[k] in [0, 1) (host, count of them), out[k] (host) receives
+ * the first index i whose cumulative mass sum_{j<=i} |psi_j|^2 exceeds
+ * u[k] ||psi||^2; the cumulative sums are FP64 with a fixed summation order,
+ * so equal inputs give equal draws.  A drawn index always has p_i > 0.
+ * QS_EINVAL for u outside [0, 1) or a state without mass (nothing is drawn). */
+qs_status qs_sample(qs_state* s, const double* u, size_t count, uint64_t* out);
+/* Marginal distribution (unnormalised: sums of |psi_i|^2, FP64) over the
+ * qubits set in qubit_mask (bit q = qubit q, at most 16 of them) into out
+ * (host, 2^k doubles).  Bin index: the selected qubits read as a sub-register,
+ * the lowest-numbered selected qubit most significant (MSB-first). */
+qs_status qs_marginal(qs_state* s, uint64_t qubit_mask, double* out);
+
 /* ---- adjoint gradients -------------------------------------------------- */
 
 /* Energy E = <psi_L|H|psi_L> and dE/dparams of the plan applied to the given

@@ -22,11 +22,14 @@ Modules
   closed       per-amplitude definitions used for sampled checks at sizes
                where a dense host state is too large (QFT, Walsh, index
                permutations)
+  readout      marginal distributions and inverse-CDF shot sampling
 
 Pins (see ``tests/test_oracle_pins.py``): dense brute force via Kronecker
 products at <= 10 qubits, unitarity and norm preservation, the QFT closed form
 and numpy.fft, the Walsh closed form and scipy.linalg.hadamard, GHZ and Bell
 amplitudes, Grover success probability, the paper's Trotter-error table
 (``tests/golden/trotter_error_n6.txt``), the p=1 QAOA closed form, XXZ
-expectation closed forms, and exact gradients of single-gate circuits.
+expectation closed forms, exact gradients of single-gate circuits, and for
+the read-out a hand-worked sampling table, sample frequencies, product-state
+and GHZ marginals and a per-index loop.
 """

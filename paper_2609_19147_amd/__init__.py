@@ -315,6 +315,30 @@ def amplitudes(state: State, idx) -> np.ndarray:
     return out
 
 
+def sample(state: State, u) -> np.ndarray:
+    """Indices drawn from |psi_i|^2 / ||psi||^2 for the uniform numbers u in [0, 1)
+    (one draw each; the library takes the first index whose cumulative mass
+    exceeds u ||psi||^2)."""
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).ravel())
+    out = np.empty(uu.size, dtype=np.uint64)
+    if uu.size:
+        check(lib().qs_sample(state.h, uu.ctypes.data_as(C.POINTER(C.c_double)), uu.size,
+                              out.ctypes.data_as(C.POINTER(C.c_uint64))))
+    return out
+
+
+def marginal(state: State, qubits) -> np.ndarray:
+    """Unnormalised marginal over the given qubits (at most 16): 2^k FP64 sums,
+    the lowest-numbered qubit most significant in the bin index."""
+    mask = 0
+    for q in qubits:
+        mask |= 1 << int(q)
+    k = bin(mask).count("1")
+    out = np.zeros(1 << k)
+    check(lib().qs_marginal(state.h, C.c_uint64(mask), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
 def adjoint_grad(state: State, plan: Plan, terms):
     """Energy <psi_L|H|psi_L> and its gradient w.r.t. the plan's parameters by
     the adjoint method; ``state`` holds psi_0 on entry and psi_L on return."""

@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libqs.so")
 
 SOURCES = ["planner.cpp", "api.cpp", "runtime.cpp", "adjoint.cpp", "batch.cpp",
-           "k_tile.hip", "k_dense.hip", "k_stream.hip", "k_plain.hip", "k_reduce.hip"]
+           "k_tile.hip", "k_dense.hip", "k_sample.hip", "k_stream.hip", "k_plain.hip", "k_reduce.hip"]
 
 ARCH = os.environ.get("QS_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are kept out of every kernel.

@@ -444,6 +444,69 @@ extern "C" qs_status qs_amplitudes(qs_state* s, const uint64_t* idx, size_t coun
   });
 }
 
+// ---------------------------------------------------------------- read-out
+extern "C" qs_status qs_sample(qs_state* s, const double* u, size_t count, uint64_t* out) {
+  return guarded([&] {
+    check_state(s);
+    if (count == 0) return;
+    if (!u || !out) fail(QS_EINVAL, "NULL argument");
+    for (size_t k = 0; k < count; ++k)
+      if (!(u[k] >= 0.0 && u[k] < 1.0)) fail(QS_EINVAL, "uniform numbers must lie in [0, 1)");
+    const double nrm = state_norm2(*s);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) fail(QS_EINVAL, "the state has no probability mass");
+    const size_t nscr = sample_scratch_doubles(s->n);
+    void* buf = nullptr;
+    check_hip(hipMalloc(&buf, (nscr + 2 * count) * 8), "hipMalloc");
+    struct Guard {
+      void* p;
+      ~Guard() { hipFree(p); }
+    } guard{buf};
+    double* scratch = (double*)buf;
+    double* du = scratch + nscr;
+    uint64_t* dout = (uint64_t*)(du + count);
+    check_hip(hipMemcpyAsync(du, u, count * 8, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+    if (s->dtype == QS_C64)
+      launch_sample<float>((const cplx<float>*)s->cur_ptr(), s->n, du, count, dout, scratch, s->stream);
+    else
+      launch_sample<double>((const cplx<double>*)s->cur_ptr(), s->n, du, count, dout, scratch, s->stream);
+    check_hip(hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+    s->sync();
+  });
+}
+
+extern "C" qs_status qs_marginal(qs_state* s, uint64_t qubit_mask, double* out) {
+  return guarded([&] {
+    check_state(s);
+    if (!out) fail(QS_EINVAL, "NULL argument");
+    if (s->n < 64 && (qubit_mask >> s->n)) fail(QS_EINVAL, "qubit mask out of range");
+    const int k = __builtin_popcountll(qubit_mask);
+    if (k > 16) fail(QS_EINVAL, "at most 16 qubits in a marginal");
+    if (k == 0) {
+      out[0] = state_norm2(*s);
+      return;
+    }
+    int sel[16], m = 0;
+    for (int b = 0; b < s->n; ++b)  // ascending state bits = descending qubits
+      if ((qubit_mask >> (s->n - 1 - b)) & 1) sel[m++] = b;
+    const MarginalArgs A = marginal_geometry(s->n, sel, k);
+    const size_t np = marginal_partials(A), bins = (size_t)1 << k;
+    void* buf = nullptr;
+    check_hip(hipMalloc(&buf, (np + bins) * 8), "hipMalloc");
+    struct Guard {
+      void* p;
+      ~Guard() { hipFree(p); }
+    } guard{buf};
+    double* part = (double*)buf;
+    double* dout = part + np;
+    if (s->dtype == QS_C64)
+      launch_marginal<float>((const cplx<float>*)s->cur_ptr(), A, part, dout, s->stream);
+    else
+      launch_marginal<double>((const cplx<double>*)s->cur_ptr(), A, part, dout, s->stream);
+    check_hip(hipMemcpyAsync(out, dout, bins * 8, hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+    s->sync();
+  });
+}
+
 // ---------------------------------------------------------------- profiling
 extern "C" qs_status qs_profile_enable(int on) {
   return guarded([&] {

@@ -127,6 +127,31 @@ template <class R>
 void launch_expect_x(const cplx<R>* psi, int n, uint32_t x, const uint32_t* z, const int* ny, int nt,
                      double* partials, double* out, hipStream_t s);
 
+// ---- read-out ----
+// Shot sampling: out[k] = the first index whose cumulative probability exceeds
+// u[k] ||psi||^2 (cumulative sums hierarchical, FP64, fixed order); u and out
+// in device memory; scratch needs sample_scratch_doubles(n) doubles.
+struct SampleGeom {
+  uint32_t sub_len, subs_per_block;
+  uint64_t n_sub, n_blk;
+};
+SampleGeom sample_geometry(int n);
+size_t sample_scratch_doubles(int n);
+template <class R>
+void launch_sample(const cplx<R>* psi, int n, const double* u_dev, uint64_t count, uint64_t* out_dev,
+                   double* scratch, hipStream_t s);
+// Marginal over k <= 16 state bits sel[0] < sel[1] < ...: out[bin] (device),
+// bin bit j = state bit sel[j].
+struct MarginalArgs {
+  uint32_t k, chunks;
+  uint64_t chunk_len;
+  uint32_t sel[32];
+};
+MarginalArgs marginal_geometry(int n, const int* sel_bits, int k);
+size_t marginal_partials(const MarginalArgs& A);
+template <class R>
+void launch_marginal(const cplx<R>* psi, const MarginalArgs& A, double* partials, double* out, hipStream_t s);
+
 // ---- adjoint support ----
 // out_i = sum_t c_t (-1)^{popcount((i ^ x_t) & z_t)} psi_{i ^ x_t}, terms sorted by x
 // (c_t complex: the Pauli coefficient times i^{#Y}); arrays in device memory.

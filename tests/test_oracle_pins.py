@@ -416,3 +416,57 @@ def test_long_range_ising_zz_layer_is_exact_diagonal_evolution():
             terms.append((-j0 / (k - i) ** alpha, 0, (1 << i) | (1 << k)))
     ref = hamiltonian.evolve(n, terms, dt, psi0)
     assert np.max(np.abs(got - ref)) < 1e-13
+
+
+# ---------------------------------------------------------------- read-out
+def test_sampling_hand_worked_table():
+    """Three qubits, mass 1/4 at indices 0, 2, 3, 4 (exact in binary): the
+    inverse CDF skips zero-mass indices and moves on at each quarter."""
+    from oracle import readout
+    psi = np.array([0.5, 0, 0.5j, -0.5, 0.5, 0, 0, 0], dtype=np.complex128)
+    u = [0.0, 0.1, 0.25, 0.49, 0.5, 0.74, 0.75, 0.999]
+    assert list(readout.inverse_cdf_sample(psi, u)) == [0, 0, 2, 2, 3, 3, 4, 4]
+    # an unnormalised state draws the same indices (mass 4 in all)
+    assert list(readout.inverse_cdf_sample(2.0 * psi, u)) == [0, 0, 2, 2, 3, 3, 4, 4]
+
+
+def test_sampling_frequencies_match_probabilities():
+    from oracle import readout
+    n = 4
+    psi = W.gaussian_state(n, 5)
+    p = np.abs(psi) ** 2 / np.sum(np.abs(psi) ** 2)
+    u = np.random.default_rng(9).random(200_000)
+    freq = np.bincount(readout.inverse_cdf_sample(psi, u).astype(np.int64), minlength=1 << n) / u.size
+    sigma = np.sqrt(p * (1 - p) / u.size)
+    assert np.all(np.abs(freq - p) <= 5 * sigma + 1e-12)
+
+
+def test_marginal_product_state_and_ghz():
+    from oracle import readout
+    rng = np.random.default_rng(4)
+    n = 5
+    singles = [rng.normal(size=2) + 1j * rng.normal(size=2) for _ in range(n)]
+    singles = [v / np.linalg.norm(v) for v in singles]
+    psi = singles[0]
+    for v in singles[1:]:
+        psi = np.kron(psi, v)                      # qubit 0 most significant
+    p1 = [np.abs(v) ** 2 for v in singles]
+    assert np.allclose(readout.marginal(psi, n, [1, 3]), np.kron(p1[1], p1[3]), atol=1e-15)
+    assert np.allclose(readout.marginal(psi, n, [4, 0, 2]), np.kron(np.kron(p1[0], p1[2]), p1[4]), atol=1e-15)
+    assert np.allclose(readout.marginal(psi, n, list(range(n))), np.abs(psi) ** 2, atol=1e-15)
+    assert readout.marginal(psi, n, []).shape == (1,)
+    ghz = sv.run(sv.basis(n, 0), n, W.ghz_stream(n))
+    for pair in ([0, 1], [2, 4], [1, 3]):
+        assert np.allclose(readout.marginal(ghz, n, pair), [0.5, 0, 0, 0.5], atol=1e-15)
+
+
+def test_marginal_per_index_loop():
+    from oracle import readout
+    n = 6
+    psi = W.gaussian_state(n, 12)
+    qubits = [4, 1]
+    ref = np.zeros(4)
+    for i in range(1 << n):
+        b = (((i >> (n - 1 - 1)) & 1) << 1) | ((i >> (n - 1 - 4)) & 1)
+        ref[b] += abs(psi[i]) ** 2
+    assert np.allclose(readout.marginal(psi, n, qubits), ref, rtol=1e-14)
