@@ -400,6 +400,67 @@ def bench_families(qs, torch, n=25, reps=3):
     return out
 
 
+def bench_xxz(qs, torch, reps=3):
+    """Pauli-pair Trotter families, complex64, from the Neel state: the XXZ
+    chain (delta = 0.5) and the Heisenberg chain with random fields
+    h ~ U[-1, 1] at 25 qubits, 10 first-order steps, dt = 0.05 (conjugated XX /
+    YY layers); the two-leg Heisenberg ladder at 24 qubits (12 rungs), 5 steps
+    (families interleaved per bond: dense windows); and a 25-qubit QFT written
+    out as phase gates and CNOTs (dense windows).  Fused plan against the
+    structured plan without windows and the plain per-gate path."""
+    cases = {
+        "xxz_chain_25q_10_steps": (25, W.heisenberg_stream(25, 1.0, 0.5, 0.05, 10)),
+        "heisenberg_random_field_25q_10_steps": (25, W.heisenberg_stream(25, 1.0, 1.0, 0.05, 10,
+                                                                         W.random_fields(25, 1.0, 25))),
+        "ladder_24q_5_steps": (24, W.ladder_stream(12, 1.0, 1.0, 0.05, 5)),
+        "decomposed_qft_25q": (25, W.decomposed_qft_stream(25)),
+    }
+    out = {}
+    for name, (n, stream) in cases.items():
+        st = qs.State(n, "c64")
+        init = W.neel_index(n)
+
+        def timed(plan):
+            st.set_basis(init)
+            qs.apply(st, plan)
+            torch.cuda.synchronize()
+            best = float("inf")
+            for _ in range(reps):
+                st.set_basis(init)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                qs.apply(st, plan)
+                st.sync()
+                best = min(best, time.perf_counter() - t0)
+            return best
+
+        plan = qs.Plan(n, stream)
+        d = plan.describe()
+        kinds = [L["kind"] for L in d["layers"]]
+        t_fused = timed(plan)
+        z = qs.expect(st, W.z_terms(n))
+        rec = {"n_qubits": n, "gates": len(stream), "layers": len(kinds), "windows": d["windows"],
+               "dense_layers": kinds.count("dense"), "ms_fused": round(1e3 * t_fused, 3), "sum_Z": z}
+        if d["windows"]:
+            structured = qs.Plan(n, stream, window_k=-1)
+            rec["layers_structured"] = structured.num_layers()
+            t_s = timed(structured)
+            rec["ms_structured"] = round(1e3 * t_s, 3)
+            rec["speedup_vs_structured"] = round(t_s / t_fused, 1)
+        st.set_basis(init)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qs.apply_gates(st, stream)
+        st.sync()
+        t_plain = time.perf_counter() - t0
+        rec["ms_plain"] = round(1e3 * t_plain, 2)
+        rec["speedup_vs_plain"] = round(t_plain / t_fused, 1)
+        out[name] = rec
+        del st
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,6 +577,8 @@ def main():
         out["layers_30q"] = bench_layers(qs, torch)
         log("weighted diagonal families: 25 qubits")
         out["diag_families_25q"] = bench_families(qs, torch)
+        log("Pauli-pair Trotter families and decomposed streams: 24-25 qubits")
+        out["xxz_families"] = bench_xxz(qs, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

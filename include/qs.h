@@ -15,7 +15,8 @@
  *     twiddle operations, several stages per pass;
  *   - Hadamard layers become Walsh-Hadamard butterflies;
  *   - same-family XX / YY runs are conjugated into the diagonal machinery;
- *   - other small windows may run as dense k-qubit blocks on the matrix cores.
+ *   - dense k-qubit gates, and windows of decomposed gates with no cheaper
+ *     structure, run as dense blocks on the matrix cores.
  * The plain path applies one kernel per gate (the paper's per-gate pure tier,
  * Appendix A).  Reductions (norms, overlaps, Pauli expectations, gradients) are
  * accumulated in FP64 with compensated sums.
@@ -117,8 +118,15 @@ typedef enum { QS_PLAIN = 0, QS_FUSED = 1 } qs_mode;
 typedef struct {
   int32_t mode;             /* QS_PLAIN: one layer per gate; QS_FUSED: detectors on */
   int32_t max_tile_bits;    /* 0 = default; amplitudes per tile pass = 2^max_tile_bits */
-  int32_t dense_k_max;      /* 0 = default; largest window run as a dense block */
-  int32_t flags;            /* reserved, 0 */
+  int32_t dense_k_max;      /* 0 = default (6); largest UNITARY gate run as a dense block */
+  int32_t window_k;         /* dense-window fusion (generic matrix fusion of decomposed
+                               blocks, Section "Limitations and Future Work"): 0 = default
+                               (5), 4..6 = largest window, -1 = off.  Consecutive constant
+                               gates are collected into windows of at most window_k qubits;
+                               the window plan is used when it needs fewer passes than the
+                               structured plan. */
+  int32_t low_bits;         /* 0 = default (4); 2..4: contiguous low bits of a tile pass
+                               over high bits (runs of 2^low_bits amplitudes in HBM) */
 } qs_plan_opts;
 
 typedef struct qs_state qs_state;

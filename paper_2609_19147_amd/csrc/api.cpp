@@ -272,17 +272,23 @@ extern "C" qs_status qs_plan_create(int n, const qs_gate* gates, size_t n_gates,
   return guarded([&] {
     if (!out) fail(QS_EINVAL, "out is NULL");
     PlanOptions o;
+    int low = 4;
     if (opts) {
       if (opts->mode != QS_PLAIN && opts->mode != QS_FUSED) fail(QS_EINVAL, "unknown plan mode");
       o.mode = opts->mode;
       o.max_tile_bits = opts->max_tile_bits;
       if (opts->dense_k_max) o.dense_k_max = opts->dense_k_max;
+      if (opts->window_k < -1 || (opts->window_k > 0 && (opts->window_k < 4 || opts->window_k > 6)))
+        fail(QS_EINVAL, "window_k must be -1, 0 or 4..6");
+      if (opts->window_k) o.window_k = opts->window_k;
+      if (opts->low_bits && (opts->low_bits < 2 || opts->low_bits > 8)) fail(QS_EINVAL, "low_bits must be 0 or 2..8");
+      if (opts->low_bits) low = opts->low_bits;
     }
     int tb = o.max_tile_bits ? o.max_tile_bits : 13;
     if (tb < kRoundBits + 1 || tb > kMaxTileBits) fail(QS_EINVAL, "max_tile_bits out of range");
     auto g = normalise_gates(n, gates, n_gates, n_params);
     auto p = std::make_unique<qs_plan>();
-    p->ir = build_plan(n, std::move(g), n_params, o, tb, 4);
+    p->ir = build_plan(n, std::move(g), n_params, o, tb, low);
     p->bound = n_params == 0;
     *out = p.release();
   });

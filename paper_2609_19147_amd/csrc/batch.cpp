@@ -184,6 +184,7 @@ extern "C" qs_status qs_batch_create(size_t n_inst, const int* n_qubits, const q
       if (!p->bound) fail(QS_EINVAL, "plan parameters are not bound");
       for (const LayerIR& L : p->ir.layers) {
         if (L.kind == L_GF2) fail(QS_EUNSUPPORTED, "permutation layers are not supported in batches");
+        if (L.kind == L_DENSE) fail(QS_EUNSUPPORTED, "dense blocks are not supported in batches");
         if (L.kind == L_PLAIN && p->ir.gates[L.index].bits.size() > 2)
           fail(QS_EUNSUPPORTED, "dense gates on more than two qubits are not supported in batches");
       }

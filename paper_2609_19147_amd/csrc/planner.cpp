@@ -586,11 +586,142 @@ Gf2Args gf2_args(int n, const Gf2IR& g, int c_bits) {
 }
 
 // ---------------------------------------------------------------- plan building
+// ---------------------------------------------------------------- dense windows
+// Gates that cannot change the fused operator of a window: constant angle and
+// no more bits than the window may hold.
+static bool window_fusable(const NGate& g, int kmax) {
+  if (!g.angle.is_const()) return false;
+  return (int)g.bits.size() <= kmax;
+}
+
+static uint32_t gate_mask(const NGate& g) {
+  uint32_t m = 0;
+  for (int b : g.bits) m |= 1u << b;
+  return m;
+}
+
+// U <- E(g) U, where E(g) is gate g on its bits inside a window whose matrix
+// index bit u holds state bit asc[u].
+static void window_apply(std::vector<cd>& U, const std::vector<int>& asc, const NGate& g) {
+  const std::vector<double> none;
+  const std::vector<cd> M = gate_matrix(g, none);
+  const int k = (int)asc.size(), K = 1 << k;
+  const int a = (int)g.bits.size(), A = 1 << a;
+  std::vector<int> lb(a);  // window bit of gate-matrix bit t (gate wire j is matrix bit a-1-j)
+  uint32_t gm = 0;
+  for (int j = 0; j < a; ++j) {
+    const int u = (int)(std::find(asc.begin(), asc.end(), g.bits[j]) - asc.begin());
+    lb[a - 1 - j] = u;
+    gm |= 1u << u;
+  }
+  std::vector<int> ex(A, 0);
+  for (int t = 0; t < A; ++t)
+    for (int v = 0; v < a; ++v)
+      if ((t >> v) & 1) ex[t] |= 1 << lb[v];
+  std::vector<cd> out((size_t)K * K);
+  for (int r0 = 0; r0 < K; ++r0) {
+    if (r0 & (int)gm) continue;
+    for (int c = 0; c < K; ++c)
+      for (int s = 0; s < A; ++s) {
+        cd acc = 0;
+        for (int t = 0; t < A; ++t) acc += M[(size_t)s * A + t] * U[(size_t)(r0 | ex[t]) * K + c];
+        out[(size_t)(r0 | ex[s]) * K + c] = acc;
+      }
+  }
+  U.swap(out);
+}
+
+int fuse_windows(int n, const std::vector<NGate>& in, int kmax, std::vector<NGate>& out) {
+  struct Win {
+    uint32_t mask;
+    std::vector<int> gates;
+  };
+  std::vector<Win> open;
+  int formed = 0;
+  out.clear();
+  auto emit = [&](Win& w) {
+    if (w.gates.size() < 2 || __builtin_popcount(w.mask) < 2) {
+      for (int gi : w.gates) out.push_back(in[gi]);
+      return;
+    }
+    uint32_t m = w.mask;
+    for (int b = 0; b < n && __builtin_popcount(m) < 4; ++b) m |= 1u << b;  // identity padding
+    std::vector<int> asc;
+    for (int b = 0; b < n; ++b)
+      if ((m >> b) & 1) asc.push_back(b);
+    const int k = (int)asc.size(), K = 1 << k;
+    std::vector<cd> U((size_t)K * K, cd(0, 0));
+    for (int i = 0; i < K; ++i) U[(size_t)i * K + i] = 1;
+    for (int gi : w.gates) window_apply(U, asc, in[gi]);
+    NGate g;
+    g.kind = QS_GATE_UNITARY;
+    g.bits.assign(asc.rbegin(), asc.rend());  // first listed bit = most significant matrix bit
+    g.mat = std::move(U);
+    g.index = in[w.gates.front()].index;
+    g.fused = (int32_t)w.gates.size();
+    out.push_back(std::move(g));
+    ++formed;
+  };
+  for (size_t i = 0; i < in.size(); ++i) {
+    const NGate& g = in[i];
+    const uint32_t gm = gate_mask(g);
+    std::vector<size_t> hit;
+    for (size_t w = 0; w < open.size(); ++w)
+      if (open[w].mask & gm) hit.push_back(w);
+    if (!window_fusable(g, kmax)) {
+      // close every window it touches, keep the others open (they commute with g)
+      for (size_t w : hit) emit(open[w]);
+      for (size_t j = hit.size(); j-- > 0;) open.erase(open.begin() + (long)hit[j]);
+      out.push_back(g);
+      continue;
+    }
+    // Windows on disjoint bits commute, so the touched windows can be
+    // concatenated and g appended.  When they do not all fit, the smallest
+    // ones are merged while they fit and the rest are emitted first.
+    std::vector<size_t> order = hit;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+      return __builtin_popcount(open[x].mask) < __builtin_popcount(open[y].mask);
+    });
+    Win W{gm, {}};
+    std::vector<char> take(open.size(), 0);
+    for (size_t w : order)
+      if (__builtin_popcount(W.mask | open[w].mask) <= kmax) {
+        W.mask |= open[w].mask;
+        take[w] = 1;
+      }
+    for (size_t w : hit)
+      if (!take[w]) emit(open[w]);
+    for (size_t w : hit)
+      if (take[w]) W.gates.insert(W.gates.end(), open[w].gates.begin(), open[w].gates.end());
+    W.gates.push_back((int)i);
+    for (size_t j = hit.size(); j-- > 0;) open.erase(open.begin() + (long)hit[j]);
+    open.push_back(std::move(W));
+  }
+  for (Win& w : open) emit(w);
+  return formed;
+}
+
+double plan_cost(const PlanIR& P) {
+  double c = 0.0;
+  for (const LayerIR& L : P.layers) {
+    if (L.kind == L_DENSE) {
+      const int k = (int)P.denses[L.index].bits.size();
+      c += k <= 4 ? 1.0 : k == 5 ? 1.2 : 2.0;
+    } else if (L.kind == L_PLAIN) {
+      const int k = (int)P.gates[L.index].bits.size();
+      c += k <= 2 ? 1.0 : (double)(1 << (k - 2));
+    } else {
+      c += 1.0;
+    }
+  }
+  return c;
+}
+
 namespace {
 
 struct Sched {
   int n;
-  int L;                                // low bits of high tiles
+  int L;                                // least low bits of a high tile
   std::vector<std::array<int, 3>> grp;  // (L, a, h)
   std::vector<uint32_t> gmask;
 };
@@ -613,8 +744,11 @@ Sched make_groups(int n, int tile_bits, int low_bits) {
   int a = m0;
   for (int k = 0; k < ng; ++k) {
     int h = rest / ng + (k < rest % ng ? 1 : 0);
-    s.grp.push_back({low_bits, a, h});
-    uint32_t m = (1u << low_bits) - 1;
+    // a group of h high bits fills its tile with the lowest tile_bits - h
+    // state bits: longer contiguous runs per HBM access (2^L amplitudes)
+    const int L = tile_bits - h;
+    s.grp.push_back({L, a, h});
+    uint32_t m = (1u << L) - 1;
     for (int b = a; b < a + h; ++b) m |= 1u << b;
     s.gmask.push_back(m);
     a += h;
@@ -923,6 +1057,12 @@ class Builder {
       F = compose_gf2(n, F, G);
       return;
     }
+    // a lone X / CNOT / SWAP moves half the state in place on the per-gate
+    // kernel; a gather moves all of it
+    if (G.gates.size() == 1) {
+      barrier({L_PLAIN, (int32_t)G.gates[0]});
+      return;
+    }
     barrier({L_GF2, (int32_t)P.gf2s.size()});
     P.gf2s.push_back(std::move(G));
   }
@@ -1225,6 +1365,28 @@ PlanIR build_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOp
   Builder B(P, tile_bits, low_bits);
   B.run();
   for (auto& T : P.passes) finalize_pass(P, T);
+  // Generic matrix fusion of decomposed blocks (Section "Limitations and
+  // Future Work"): the same stream with dense windows, kept when it needs
+  // fewer passes than the structured plan.
+  const int kw = std::min(std::min(opt.window_k, opt.dense_k_max), std::min(n - 4, QS_MAX_GATE_WIRES));
+  if (kw >= 4) {
+    std::vector<NGate> fused;
+    const int formed = fuse_windows(n, P.gates, kw, fused);
+    if (formed > 0) {
+      PlanIR Q;
+      Q.n = n;
+      Q.n_params = n_params;
+      Q.opt = opt;
+      Q.gates = std::move(fused);
+      Q.tile_bits = tile_bits;
+      Q.low_bits = low_bits;
+      Q.windows = formed;
+      Builder BQ(Q, tile_bits, low_bits);
+      BQ.run();
+      for (auto& T : Q.passes) finalize_pass(Q, T);
+      if (plan_cost(Q) < plan_cost(P)) return Q;
+    }
+  }
   return P;
 }
 
@@ -1455,6 +1617,7 @@ PlanIR invert_plan(const PlanIR& F) {
   P.ops = F.ops;
   P.tile_bits = F.tile_bits;
   P.low_bits = F.low_bits;
+  P.windows = F.windows;
   for (auto it = F.layers.rbegin(); it != F.layers.rend(); ++it) {
     LayerIR L = *it;
     if (L.kind == L_TILE) {
@@ -1601,7 +1764,7 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
   std::ostringstream o;
   o << "{\"n\":" << P.n << ",\"n_params\":" << P.n_params << ",\"mode\":"
     << (P.opt.mode == QS_PLAIN ? "\"plain\"" : "\"fused\"") << ",\"tile_bits\":" << P.tile_bits
-    << ",\"bound\":" << (bound ? "true" : "false") << ",\"layers\":[";
+    << ",\"bound\":" << (bound ? "true" : "false") << ",\"windows\":" << P.windows << ",\"layers\":[";
   for (size_t li = 0; li < P.layers.size(); ++li) {
     if (li) o << ",";
     const LayerIR& L = P.layers[li];
@@ -1616,7 +1779,8 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
       o << "],\"cprime\":" << G.cprime << ",\"n_gates\":" << G.gates.size() << "}";
     } else if (L.kind == L_DENSE) {
       const DenseIR& D = P.denses[L.index];
-      o << "{\"kind\":\"dense\",\"inverse\":" << L.inverse << ",\"gate\":" << D.gate << ",\"bits\":[";
+      o << "{\"kind\":\"dense\",\"inverse\":" << L.inverse << ",\"gate\":" << P.gates[D.gate].index
+        << ",\"window\":" << P.gates[D.gate].fused << ",\"bits\":[";
       for (size_t b = 0; b < D.bits.size(); ++b) { if (b) o << ","; o << D.bits[b]; }
       o << "],\"mat\":[";
       const std::vector<cd>& M = L.inverse ? D.mat_dagger : D.mat;
@@ -1628,7 +1792,7 @@ std::string describe_json(const PlanIR& P, const std::vector<double>& params, bo
       o << "]}";
     } else if (L.kind == L_PLAIN) {
       const NGate& g = P.gates[L.index];
-      o << "{\"kind\":\"plain\",\"inverse\":" << L.inverse << ",\"gate\":" << L.index
+      o << "{\"kind\":\"plain\",\"inverse\":" << L.inverse << ",\"gate\":" << g.index
         << ",\"gate_kind\":" << g.kind << ",\"bits\":[";
       for (size_t b = 0; b < g.bits.size(); ++b) { if (b) o << ","; o << g.bits[b]; }
       o << "]}";

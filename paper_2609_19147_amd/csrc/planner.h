@@ -43,7 +43,8 @@ struct NGate {
   uint32_t all_mask = 0;   // MCZ / MCP support
   Angle angle;
   std::vector<cd> mat;     // U, CU (2x2), UNITARY (2^k x 2^k)
-  int32_t index = 0;       // position in the stream
+  int32_t index = 0;       // position in the stream (first gate of a fused window)
+  int32_t fused = 0;       // > 0: a dense window standing for this many consecutive gates
 };
 
 bool gate_is_diagonal(int kind);
@@ -129,6 +130,7 @@ struct PlanOptions {
   int mode = QS_FUSED;
   int max_tile_bits = 0;  // 0 = default by dtype at apply time
   int dense_k_max = 6;    // largest UNITARY gate run as a dense block (< 4: none)
+  int window_k = 5;       // dense-window fusion: largest window (< 4: off)
 };
 
 struct PlanIR {
@@ -144,7 +146,18 @@ struct PlanIR {
   std::vector<LayerIR> layers;
   int tile_bits = 13;  // tile size used to build the passes
   int low_bits = 4;    // L of high tiles
+  int windows = 0;     // dense windows formed by window fusion (0: structured plan)
 };
+
+// Estimated cost of a plan in state passes (a dense block of 5 or 6 bits
+// costs more than one pass: its arithmetic leaves the memory-bound regime).
+double plan_cost(const PlanIR& P);
+// Dense-window fusion of a gate stream: consecutive constant gates are
+// collected into windows of at most kmax bits (open windows on disjoint bits,
+// so reordering them is exact) and every window of two or more gates on two
+// or more bits becomes one UNITARY gate, padded with identity bits to at least
+// 4 bits.  Returns the number of windows formed.
+int fuse_windows(int n, const std::vector<NGate>& in, int kmax, std::vector<NGate>& out);
 
 // Validate + normalise the user's gates.
 std::vector<NGate> normalise_gates(int n, const qs_gate* g, size_t count, size_t n_params);

@@ -470,3 +470,52 @@ def test_marginal_per_index_loop():
         b = (((i >> (n - 1 - 1)) & 1) << 1) | ((i >> (n - 1 - 4)) & 1)
         ref[b] += abs(psi[i]) ** 2
     assert np.allclose(readout.marginal(psi, n, qubits), ref, rtol=1e-14)
+
+
+# ---------------------------------------------------------------- XXZ chain and ladder
+def ladder_terms(rungs, J, delta):
+    out = []
+    for a, b in W.ladder_bonds(rungs):
+        out += [W.pauli(J, {a: "X", b: "X"}), W.pauli(J, {a: "Y", b: "Y"}), W.pauli(J * delta, {a: "Z", b: "Z"})]
+    return out
+
+
+def test_single_bond_triple_is_exact_xxz_evolution():
+    # XX, YY and ZZ on one pair commute: one Trotter step of one bond is exact
+    J, delta, dt = 0.7, 0.4, 0.3
+    psi0 = W.gaussian_state(2, 3)
+    ref = hamiltonian.evolve(2, W.xxz_terms(2, delta, J), dt, psi0)
+    assert np.max(np.abs(sv.run(psi0, 2, W.heisenberg_stream(2, J, delta, dt, 1)) - ref)) < 1e-13
+    assert np.max(np.abs(sv.run(psi0, 2, W.ladder_stream(1, J, delta, dt, 1)) - ref)) < 1e-13
+
+
+def test_heisenberg_random_field_first_order_convergence():
+    n, J, delta, T = 6, 1.0, 1.0, 0.5
+    h = W.random_fields(n, 1.0, 3)
+    terms = W.xxz_terms(n, delta, J) + [(float(h[q]), 0, 1 << q) for q in range(n)]
+    psi0 = sv.basis(n, W.neel_index(n))
+    exact = hamiltonian.evolve(n, terms, T, psi0)
+    err = [np.linalg.norm(sv.run(psi0, n, W.heisenberg_stream(n, J, delta, T / r, r, h)) - exact)
+           for r in (10, 20, 40)]
+    # first-order product formula: the error halves when the step halves
+    assert 1.8 < err[0] / err[1] < 2.2 and 1.8 < err[1] / err[2] < 2.2
+
+
+def test_ladder_conserves_magnetisation_and_converges():
+    rungs, J, delta, T = 3, 1.0, 0.5, 0.4
+    n = 2 * rungs
+    psi0 = sv.basis(n, W.neel_index(n))
+    exact = hamiltonian.evolve(n, ladder_terms(rungs, J, delta), T, psi0)
+    err = []
+    for r in (8, 16, 32):
+        psi = sv.run(psi0, n, W.ladder_stream(rungs, J, delta, T / r, r))
+        # each bond factor exp(-i dt (XX + YY + delta ZZ)) commutes with sum Z
+        assert abs(sum(sv.expect_terms(psi, n, W.z_terms(n)))) < 1e-12
+        err.append(np.linalg.norm(psi - exact))
+    assert 1.8 < err[0] / err[1] < 2.2 and 1.8 < err[1] / err[2] < 2.2
+
+
+@pytest.mark.parametrize("n", [3, 6])
+def test_decomposed_qft_equals_qft(n):
+    psi0 = W.gaussian_state(n, 4)
+    assert np.max(np.abs(sv.run(psi0, n, W.decomposed_qft_stream(n)) - sv.run(psi0, n, W.qft_stream(n)))) < 1e-13

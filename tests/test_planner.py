@@ -164,14 +164,15 @@ def test_multi_controlled_and_dense_gates():
 def test_unitary_blocks_become_dense_layers(k):
     n = 11
     st = W.dense_block_stream(n, 3, k, 40 + k) + W.random_stream(n, 30, k) + W.dense_block_stream(n, 2, k, 50 + k)
-    d = check_plan(n, st, tol=1e-12)
+    check_plan(n, st, tol=1e-12)                       # whichever plan the cost model keeps
+    d = check_plan(n, st, tol=1e-12, window_k=-1)      # structured plan: one dense layer per block
     dense = [L for L in d["layers"] if L["kind"] == "dense"]
     assert len(dense) == 5
     for L in dense:
         assert L["bits"] == sorted(L["bits"]) and len(L["bits"]) == k
     # the plain path keeps them as per-gate layers, a small cap or a small state disables them
     assert "dense" not in kinds(plan_of(n, st, mode="plain").describe())
-    assert "dense" not in kinds(plan_of(n, st, dense_k_max=k - 1).describe())
+    assert "dense" not in kinds(plan_of(n, st, dense_k_max=k - 1, window_k=-1).describe())
     assert "dense" not in kinds(plan_of(k + 3, W.dense_block_stream(k + 3, 1, k, 1)).describe())
 
 
@@ -296,3 +297,81 @@ def test_qft_and_inverse_qft_on_an_upper_register(offset):
         stages = [o for o in ops if o["kind"] == kind]
         assert len(stages) >= t - 1 and all(o["base"] == offset for o in stages)
         assert "diag" not in kinds(d)
+
+
+# ---------------------------------------------------------------- dense-window fusion
+@pytest.mark.parametrize("rungs", [4, 5, 7])
+def test_ladder_fuses_to_dense_windows(rungs):
+    """The two-leg ladder interleaves XX, YY and ZZ per bond, so no same-family
+    run forms; dense windows take it in fewer passes, exactly."""
+    n = 2 * rungs
+    stream = W.ladder_stream(rungs, 1.0, 0.5, 0.05, 2)
+    d = check_plan(n, stream, tol=1e-12)
+    assert d["windows"] > 0 and "dense" in kinds(d)
+    assert all(len(L["bits"]) <= 5 for L in d["layers"] if L["kind"] == "dense")
+    d0 = qs.Plan(n, stream, window_k=-1).describe()
+    assert d0["windows"] == 0 and len(d["layers"]) < len(d0["layers"])
+    # the windows cover every gate exactly once
+    assert sum(L["window"] for L in d["layers"] if L["kind"] == "dense") + sum(
+        1 for L in d["layers"] if L["kind"] == "plain") <= len(stream)
+
+
+@pytest.mark.parametrize("n,k", [(9, 4), (10, 5), (12, 6)])
+def test_decomposed_qft_window_plans(n, k):
+    stream = W.decomposed_qft_stream(n)
+    d = check_plan(n, stream, tol=1e-11, window_k=k)
+    assert all(len(L["bits"]) <= k for L in d["layers"] if L["kind"] == "dense")
+    d0 = qs.Plan(n, stream, window_k=-1).describe()
+    assert len(d["layers"]) <= len(d0["layers"])
+
+
+def test_window_fusion_on_random_decomposed_streams():
+    for seed in range(6):
+        n = 8 + seed % 3
+        stream = W.random_stream(n, 120, 40 + seed, kinds=("H", "RX", "RZ", "CNOT", "CZ", "SWAP", "RXX", "CU", "T"))
+        check_plan(n, stream, tol=1e-11)
+        check_plan(n, stream, tol=1e-11, window_k=4)
+        check_plan(n, stream, tol=1e-11, window_k=6)
+
+
+def test_structured_streams_keep_structured_plans():
+    cases = [(20, W.qft_stream(20)), (16, W.tfim_strang_stream(16, 1.0, 0.8, 0.05, 3)),
+             (12, W.qaoa_stream(W.qaoa_instances(1, 5, depth=2, n_choices=(12,))[0])),
+             (14, W.heisenberg_stream(14, 1.0, 0.5, 0.05, 2, W.random_fields(14, 1.0, 2))),
+             (30, W.qft_stream(30) + W.wht_stream(30) + W.random_perm_block(30, 200, 31))]
+    for n, stream in cases:
+        assert qs.Plan(n, stream).describe()["windows"] == 0, n
+
+
+def test_window_fusion_leaves_parametrised_gates():
+    n = 9
+    stream = W.ladder_stream(4, 1.0, 0.5, 0.05, 1)[:30]
+    stream[7] = W.G("RZZ", 0, 1, theta=0.1, param=0)
+    stream[20] = W.G("RX", 5, theta=0.0, param=1)
+    stream += [W.G("H", q) for q in range(n)]
+    p = plan_of(n, stream, n_params=2)
+    for params in ([0.3, -1.1], [2.0, 0.25]):
+        p.set_params(params)
+        got = run_plan(p.describe(), W.gaussian_state(n, 3), stream, params)
+        ref = sv.run(W.gaussian_state(n, 3), n, stream, params)
+        assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_window_inverse_plan_returns_input():
+    rungs = 5
+    n = 2 * rungs
+    stream = W.ladder_stream(rungs, 1.0, 0.5, 0.05, 1)
+    p = qs.Plan(n, stream)
+    psi0 = W.gaussian_state(n, 9)
+    fwd = run_plan(p.describe(), psi0, stream)
+    back = run_plan(p.inverse().describe(), fwd, stream)
+    assert p.describe()["windows"] > 0
+    assert np.max(np.abs(back - psi0)) < 1e-12
+
+
+def test_window_option_validation():
+    for bad in (3, 7, -2):
+        with pytest.raises(Exception):
+            qs.Plan(10, W.ladder_stream(5, 1.0, 0.5, 0.05, 1), window_k=bad)
+    # fewer than 8 qubits: no window (a dense block needs 4 other bits)
+    assert qs.Plan(6, W.ladder_stream(3, 1.0, 0.5, 0.05, 1)).describe()["windows"] == 0

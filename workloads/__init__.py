@@ -397,6 +397,74 @@ def qpe_ladder_stream(t: int, theta: float, first_power: int = 0) -> List[Gate]:
     return out + inv
 
 
+def random_fields(n: int, width: float, seed: int) -> np.ndarray:
+    """Random longitudinal fields h_q ~ U[-width, width] (seeded)."""
+    return np.random.default_rng(seed).uniform(-width, width, size=n)
+
+
+def heisenberg_stream(n: int, J: float, delta: float, dt: float, steps: int,
+                      fields: Optional[Sequence[float]] = None) -> List[Gate]:
+    """First-order Trotter evolution under the open-chain XXZ Hamiltonian
+    H = J sum_i (X_i X_{i+1} + Y_i Y_{i+1} + delta Z_i Z_{i+1}) + sum_q h_q Z_q.
+    Per step: RXX(2 J dt) on every bond, then RYY(2 J dt) on every bond, then
+    RZZ(2 J delta dt) on every bond, then RZ(2 h_q dt) per qubit (one same-family
+    run per Pauli pair; delta = 1 is the Heisenberg chain)."""
+    out: List[Gate] = []
+    for _ in range(steps):
+        for name, th in (("RXX", 2.0 * J * dt), ("RYY", 2.0 * J * dt), ("RZZ", 2.0 * J * delta * dt)):
+            out += [G(name, i, i + 1, theta=th) for i in range(n - 1)]
+        if fields is not None:
+            out += [G("RZ", q, theta=2.0 * float(fields[q]) * dt) for q in range(n)]
+    return out
+
+
+def ladder_bonds(rungs: int) -> List[Tuple[int, int]]:
+    """Bonds of a two-leg ladder with site (rung r, leg l) on qubit 2 r + l, in
+    rung order: the rung (2r, 2r+1), then the leg bonds to rung r + 1."""
+    out: List[Tuple[int, int]] = []
+    for r in range(rungs):
+        out.append((2 * r, 2 * r + 1))
+        if r + 1 < rungs:
+            out += [(2 * r, 2 * r + 2), (2 * r + 1, 2 * r + 3)]
+    return out
+
+
+def ladder_stream(rungs: int, J: float, delta: float, dt: float, steps: int) -> List[Gate]:
+    """First-order Trotter evolution of the two-leg XXZ ladder
+    H = J sum_bonds (XX + YY + delta ZZ): per step and per bond, in bond order,
+    RXX(2 J dt), RYY(2 J dt), RZZ(2 J delta dt).  The three Pauli pairs of one
+    bond commute, so each bond's triple is exactly exp(-i dt h_bond); the
+    families interleave, so no same-family run forms."""
+    out: List[Gate] = []
+    for _ in range(steps):
+        for a, b in ladder_bonds(rungs):
+            out += [G("RXX", a, b, theta=2.0 * J * dt), G("RYY", a, b, theta=2.0 * J * dt),
+                    G("RZZ", a, b, theta=2.0 * J * delta * dt)]
+    return out
+
+
+def neel_index(n: int) -> int:
+    """Basis index of |0101...> (qubit q in state q mod 2)."""
+    return sum(1 << (n - 1 - q) for q in range(1, n, 2))
+
+
+def decomposed_qft_stream(n: int) -> List[Gate]:
+    """The QFT stream with every controlled phase written out as phase gates
+    and CNOTs: CP(t) on (c, g) = P(t/2) c, CNOT(c, g), P(-t/2) g, CNOT(c, g),
+    P(t/2) g (the form a transpiled file carries; no controlled-phase ladder
+    remains for a stage detector)."""
+    out: List[Gate] = []
+    for g in qft_stream(n):
+        if g.name != "CPHASE":
+            out.append(g)
+            continue
+        c, t = g.wires
+        th = g.theta
+        out += [G("P", c, theta=th / 2), G("CNOT", c, t), G("P", t, theta=-th / 2), G("CNOT", c, t),
+                G("P", t, theta=th / 2)]
+    return out
+
+
 def dense_block_stream(n: int, count: int, k: int, seed: int) -> List[Gate]:
     """``count`` UNITARY gates on k distinct random wires each, with Haar-ish
     2^k x 2^k matrices (the dense-block microbenchmark's input)."""
