@@ -125,8 +125,9 @@ typedef struct {
                                gates are collected into windows of at most window_k qubits;
                                the window plan is used when it needs fewer passes than the
                                structured plan. */
-  int32_t low_bits;         /* 0 = default (4); 2..4: contiguous low bits of a tile pass
-                               over high bits (runs of 2^low_bits amplitudes in HBM) */
+  int32_t low_bits;         /* contiguous low state bits of a tile pass over high bits
+                               (runs of 2^low_bits amplitudes in HBM): 0 = per group, the
+                               tile's remaining bits (at least 4); 2..8 = fixed */
 } qs_plan_opts;
 
 typedef struct qs_state qs_state;

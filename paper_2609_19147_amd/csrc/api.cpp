@@ -272,7 +272,7 @@ extern "C" qs_status qs_plan_create(int n, const qs_gate* gates, size_t n_gates,
   return guarded([&] {
     if (!out) fail(QS_EINVAL, "out is NULL");
     PlanOptions o;
-    int low = 4;
+    int low = 0;
     if (opts) {
       if (opts->mode != QS_PLAIN && opts->mode != QS_FUSED) fail(QS_EINVAL, "unknown plan mode");
       o.mode = opts->mode;

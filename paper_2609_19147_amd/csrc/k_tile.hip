@@ -499,6 +499,15 @@ inline uint32_t tile_threads(uint32_t m) {
   return threads < 64 ? 64 : (threads > (uint32_t)kMaxThreads ? (uint32_t)kMaxThreads : threads);
 }
 
+// The complex64 kernels with diagonal slots need more than 128 VGPRs (three
+// waves per SIMD, twelve per CU); 256-thread workgroups let two tiles of 2^13
+// amplitudes share a CU, so one tile's loads overlap the other's rounds.
+template <class R, bool kDiag>
+inline uint32_t tile_threads_for(uint32_t m) {
+  const uint32_t t = tile_threads(m);
+  return (kDiag && sizeof(R) == 4 && t > 256u) ? 256u : t;
+}
+
 inline size_t tile_lds(uint32_t m, size_t elem) {
   const uint32_t M = 1u << m;
   return elem * (M + ((M >> 5) << 1));
@@ -515,7 +524,7 @@ void launch_tile_batched_k(const TileKArgs<R>* descs_dev, uint32_t count, uint32
     attr_set = true;
   }
   const uint32_t shift = n - m;
-  QS_LAUNCH("tile_pass_batched", s, (tile_kernel_batched<R, kDiag>), dim3(count << shift), dim3(tile_threads(m)),
+  QS_LAUNCH("tile_pass_batched", s, (tile_kernel_batched<R, kDiag>), dim3(count << shift), dim3(tile_threads_for<R, kDiag>(m)),
             tile_lds(m, sizeof(cplx<R>)), s, descs_dev, shift);
 }
 
@@ -537,7 +546,7 @@ void launch_tile_k(const TileKArgs<R>& A, hipStream_t s) {
   }
   // one thread per register group of a round, between 64 and 512 threads
   const uint32_t n_cosets = 1u << (A.n - A.m);
-  QS_LAUNCH("tile_pass", s, (tile_kernel<R, kDiag>), dim3(n_cosets), dim3(tile_threads(A.m)),
+  QS_LAUNCH("tile_pass", s, (tile_kernel<R, kDiag>), dim3(n_cosets), dim3(tile_threads_for<R, kDiag>(A.m)),
             tile_lds(A.m, sizeof(cplx<R>)), s, A);
 }
 

@@ -729,7 +729,7 @@ struct Sched {
 Sched make_groups(int n, int tile_bits, int low_bits) {
   Sched s;
   s.n = n;
-  s.L = low_bits;
+  s.L = low_bits > 0 ? low_bits : 4;
   if (n <= tile_bits) {
     s.grp.push_back({n, n, 0});
     s.gmask.push_back(n >= 32 ? 0xffffffffu : ((1u << n) - 1));
@@ -739,14 +739,17 @@ Sched make_groups(int n, int tile_bits, int low_bits) {
   s.grp.push_back({m0, m0, 0});
   s.gmask.push_back((1u << m0) - 1);
   int rest = n - m0;
-  int hmax = tile_bits - low_bits;
+  // low_bits > 0: every high tile holds the lowest low_bits state bits;
+  // low_bits == 0: a group of h high bits fills its tile with the lowest
+  // tile_bits - h state bits (at least 4), i.e. longer contiguous runs per HBM
+  // access (2^L amplitudes) at the price of larger tiles
+  const int Lmin = low_bits > 0 ? low_bits : 4;
+  int hmax = tile_bits - Lmin;
   int ng = (rest + hmax - 1) / hmax;
   int a = m0;
   for (int k = 0; k < ng; ++k) {
     int h = rest / ng + (k < rest % ng ? 1 : 0);
-    // a group of h high bits fills its tile with the lowest tile_bits - h
-    // state bits: longer contiguous runs per HBM access (2^L amplitudes)
-    const int L = tile_bits - h;
+    const int L = low_bits > 0 ? low_bits : tile_bits - h;
     s.grp.push_back({L, a, h});
     uint32_t m = (1u << L) - 1;
     for (int b = a; b < a + h; ++b) m |= 1u << b;
@@ -1106,6 +1109,23 @@ class Builder {
       T.L = sched.grp[best][0];
       T.a = sched.grp[best][1];
       T.h = sched.grp[best][2];
+      // A pass with diagonal slots runs a kernel with more registers (fewer
+      // waves per SIMD): it does better with smaller tiles, more of them per
+      // compute unit, than with longer HBM runs.  Such a high pass keeps only
+      // the minimum of low bits; ops on the bits given up wait for a later pass.
+      bool has_diag = false;
+      for (int idx : best_list) has_diag = has_diag || seg[idx].ir.type == 1;
+      if (has_diag && T.h > 0 && T.L > sched.L) {
+        const uint32_t small = ((1u << sched.L) - 1u) | (((1u << T.h) - 1u) << T.a);
+        std::vector<int> list;
+        scan_mask(small, deps, done, list);
+        bool diag_kept = false;
+        for (int idx : list) diag_kept = diag_kept || seg[idx].ir.type == 1;
+        if (diag_kept) {
+          T.L = sched.L;
+          best_list = list;
+        }
+      }
       for (int idx : best_list) {
         T.items.push_back(seg[idx].ir);
         done[idx] = 1;
@@ -1119,6 +1139,13 @@ class Builder {
 
   int scan(size_t g, const std::vector<std::vector<int>>& deps, const std::vector<char>& done,
            std::vector<int>& list) {
+    return scan_mask(sched.gmask[g], deps, done, list);
+  }
+
+  // Every ready item in stream order whose written bits lie in the tile mask
+  // (at most kMaxDiagSlots diagonal layers); returns the number of ops taken.
+  int scan_mask(uint32_t gmask, const std::vector<std::vector<int>>& deps, const std::vector<char>& done,
+                std::vector<int>& list) {
     std::vector<char> taken(seg.size(), 0);
     int ops = 0, ndiag = 0;
     for (size_t j = 0; j < seg.size(); ++j) {
@@ -1128,7 +1155,7 @@ class Builder {
         if (!done[d] && !taken[d]) { ok = false; break; }
       if (!ok) continue;
       if (seg[j].ir.type == 0) {
-        if ((seg[j].W & ~sched.gmask[g]) != 0) continue;
+        if ((seg[j].W & ~gmask) != 0) continue;
         ++ops;
       } else {
         if (ndiag == kMaxDiagSlots) continue;

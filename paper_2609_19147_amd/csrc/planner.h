@@ -145,7 +145,7 @@ struct PlanIR {
   std::vector<DenseIR> denses;
   std::vector<LayerIR> layers;
   int tile_bits = 13;  // tile size used to build the passes
-  int low_bits = 4;    // L of high tiles
+  int low_bits = 0;    // L of high tiles (0: per group, tile_bits - h)
   int windows = 0;     // dense windows formed by window fusion (0: structured plan)
 };
 
