@@ -363,4 +363,12 @@ __device__ __forceinline__ void diag_apply_round(cplx<R>* a, uint32_t i0, uint32
   }
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup w on XCD w mod 8).
+// Virtual block (w mod 8) G/8 + w/8 gives each XCD a contiguous range of the
+// G blocks, so the work one XCD has in flight is contiguous in memory.  A
+// bijection of [0, G) when G is a multiple of 8 (identity otherwise).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t w, uint32_t grid) {
+  return (grid & 7u) == 0u ? (w & 7u) * (grid >> 3) + (w >> 3) : w;
+}
+
 }  // namespace qs

@@ -35,7 +35,8 @@ __global__ void __launch_bounds__(kThreads) reduce_kernel(F f, uint64_t count, d
   Acc acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = {0.0, 0.0};
-  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < count; t += (uint64_t)gridDim.x * kThreads)
+  for (uint64_t t = xcd_block(blockIdx.x, gridDim.x) * (uint64_t)kThreads + threadIdx.x; t < count;
+       t += (uint64_t)gridDim.x * kThreads)
     f(t, acc);
   __shared__ Acc red[NV][kThreads];
 #pragma unroll
@@ -393,7 +394,7 @@ __global__ void __launch_bounds__(kRhoThreads) rho_tile_kernel(const cplx<R>* __
   const uint32_t M = 1u << A.m;
   cplx<R>* P = reinterpret_cast<cplx<R>*>(smem_raw);
   cplx<R>* Q = P + rho_lds_off(M);
-  const uint32_t coset = blockIdx.x;
+  const uint32_t coset = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t nlo = A.a - A.L, top = A.a + A.h;
   const uint32_t base = ((coset & ((1u << nlo) - 1u)) << A.L) | (top >= 32 ? 0u : ((coset >> nlo) << top));
   const uint32_t lmask = (1u << A.L) - 1u;

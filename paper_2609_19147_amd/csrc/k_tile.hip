@@ -454,7 +454,7 @@ __device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t 
 
 template <class R, bool kDiag>
 __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
-  tile_body<R, kDiag>(A, blockIdx.x);
+  tile_body<R, kDiag>(A, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // complex64 passes without diagonal layers: registers capped at 128 so that
@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
 // or four of 2^12, share a CU's LDS).
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 tile_kernel_c64(TileKArgs<float> A) {
-  tile_body<float, false>(A, blockIdx.x);
+  tile_body<float, false>(A, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // A batched instance's argument block, read field by field with scalar loads.

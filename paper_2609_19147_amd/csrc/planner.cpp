@@ -266,6 +266,7 @@ static DiagIR build_diag(const std::vector<DiagTermIR>& raw, const Angle& global
   }
   DiagIR d;
   d.global = global;
+  d.raw = terms;
   for (auto& t : terms) d.support |= t.mask;
   // group by bit-identical symbolic angle, skipping exact zeros
   std::vector<std::vector<const DiagTermIR*>> groups;
@@ -875,6 +876,11 @@ class Builder {
   std::vector<std::vector<int>> window;
   std::vector<Item> seg;
   int last_qft_bit = -1, last_qft_base = 0;
+  // the closing basis change of the last XX / YY run: the segment size right
+  // after it, its bits and its family
+  size_t pp_tail_end = (size_t)-1;
+  uint32_t pp_tail_inv = 0;
+  bool pp_tail_yy = false;
 
   // Number of gates of a QFT stage starting at gate i, or 0: H on bit p
   // followed by CPHASE(pi / 2^(p-b)) on (b, p) for every b in [r0, p), in any
@@ -959,6 +965,16 @@ class Builder {
   }
 
   void add_diag_item(DiagIR d) {
+    // a diagonal layer right after another one (no op in between) multiplies
+    // into it: one table lookup pass instead of two
+    if (!seg.empty() && seg.back().ir.type == 1) {
+      DiagIR& prev = P.diags[seg.back().ir.index];
+      std::vector<DiagTermIR> raw = prev.raw;
+      raw.insert(raw.end(), d.raw.begin(), d.raw.end());
+      prev = build_diag(raw, prev.global.plus(d.global));
+      seg.back().R = prev.support;
+      return;
+    }
     Item it;
     it.ir = {1, (int32_t)P.diags.size()};
     it.R = d.support;
@@ -1046,11 +1062,26 @@ class Builder {
       diag_terms_of(z, raw, gl);
     }
     pp.clear();
-    for (int b = 0; b < n; ++b)
-      if ((inv >> b) & 1) add_op_item(OpIR{yy ? OP_MAT : OP_H, b, {}, true, yy ? 0 : -1});
+    // Opening basis change.  When the previous run of the other family closed
+    // on the same bits with nothing in between, its closing change and this
+    // opening one multiply into one 2x2 per bit (one op instead of two).
+    if (pp_tail_end == seg.size() && pp_tail_inv == inv && pp_tail_yy != yy) {
+      for (size_t k = seg.size() - (size_t)__builtin_popcount(inv); k < seg.size(); ++k) {
+        OpIR& op = P.ops[seg[k].ir.index];
+        op.kind = OP_MAT;
+        op.fixed_h = true;
+        op.fixed_mat = yy ? 2 : 3;
+      }
+    } else {
+      for (int b = 0; b < n; ++b)
+        if ((inv >> b) & 1) add_op_item(OpIR{yy ? OP_MAT : OP_H, b, {}, true, yy ? 0 : -1});
+    }
     add_diag_item(build_diag(raw, gl));
     for (int b = 0; b < n; ++b)
       if ((inv >> b) & 1) add_op_item(OpIR{yy ? OP_MAT : OP_H, b, {}, true, yy ? 1 : -1});
+    pp_tail_end = seg.size();
+    pp_tail_inv = inv;
+    pp_tail_yy = yy;
   }
 
   void barrier_gf2(Gf2IR G) {
@@ -1424,6 +1455,9 @@ std::vector<cd> op_matrix(const PlanIR& P, const OpIR& op, const std::vector<dou
   if (op.fixed_h) {
     if (op.fixed_mat == 0) return {r, -I * r, r, I * r};   // H S^dagger
     if (op.fixed_mat == 1) return {r, r, I * r, -I * r};   // S H
+    // closing change of one family times the opening change of the other
+    if (op.fixed_mat == 2) return mul2({r, -I * r, r, I * r}, {r, r, r, -r});   // (H S^dagger) H
+    if (op.fixed_mat == 3) return mul2({r, r, r, -r}, {r, r, I * r, -I * r});   // H (S H)
     return {r, r, r, -r};
   }
   if (op.kind == OP_H) return {r, r, r, -r};

@@ -69,6 +69,7 @@ struct DiagIR {
   std::vector<DiagGroupIR> groups;
   Angle global;
   uint32_t support = 0;
+  std::vector<DiagTermIR> raw;  // the merged terms the groups were built from
 };
 
 // One butterfly operation of a tile pass.
