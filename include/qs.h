@@ -200,6 +200,15 @@ qs_status qs_plan_inverse(const qs_plan* p, qs_plan** out);
 /* Apply layers [first, first + count) of a plan to a state (asynchronous, on
  * the state's stream).  count = (size_t)-1 applies through the last layer. */
 qs_status qs_apply_layer(qs_state* s, const qs_plan* p, size_t first, size_t count);
+/* Apply every layer of a plan, then write ||psi||^2 of the result (FP64) to
+ * *norm2 (host; the call waits for the device).  When the plan ends in a
+ * tile pass or a GF(2) gather, that kernel sums |psi|^2 over the amplitudes
+ * it writes, in a fixed order, so the norm costs no extra read of the state;
+ * otherwise a separate reduction runs (the same value as qs_norm2 up to the
+ * order of the FP64 sums).  Allocates a small per-state partials buffer on
+ * first use (8 bytes per tile, or per wavefront of a gather, of the last
+ * layer). */
+qs_status qs_apply_norm2(qs_state* s, const qs_plan* p, double* norm2);
 /* Plain per-gate path: one kernel per gate, no fusion (the baseline). */
 qs_status qs_apply_gates(qs_state* s, const qs_gate* gates, size_t n_gates,
                          const double* params, size_t n_params);

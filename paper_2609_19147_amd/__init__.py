@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib
 from ._lib import QsError, QsGate, QsPauli, QsPlanOpts, check, lib
 
-__all__ = ["State", "StateView", "Batch", "Plan", "apply", "apply_gates", "expect", "norm2", "overlap", "infidelity",
+__all__ = ["State", "StateView", "Batch", "Plan", "apply", "apply_norm2", "apply_gates", "expect", "norm2", "overlap", "infidelity",
            "amplitudes", "to_c_gates", "to_c_terms", "profile", "QsError", "version", "adjoint_grad",
            "energy_function"]
 
@@ -286,6 +286,14 @@ def expect(state: State, terms, per_term: bool = False):
     tot = C.c_double()
     check(lib().qs_expect(state.h, arr, len(terms), out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(tot)))
     return (tot.value, out) if per_term else tot.value
+
+
+def apply_norm2(state: State, plan: Plan) -> float:
+    """Apply the whole plan and return ||psi||^2 of the result (FP64); the last
+    layer's kernel accumulates it when it is a tile pass or a gather."""
+    out = C.c_double()
+    check(lib().qs_apply_norm2(state.h, plan.h, C.byref(out)))
+    return out.value
 
 
 def norm2(state: State) -> float:

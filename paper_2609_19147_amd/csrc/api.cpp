@@ -29,6 +29,14 @@ void check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) fail(QS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+void allow_dynamic_lds(const void* kernel, int bytes, const char* name) {
+  const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(QS_EDEVICE, std::string("LDS limit of ") + name + ": " + hipGetErrorString(e));
+  }
+}
+
 void check_launch(const char* name) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) fail(QS_EDEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e));
@@ -129,6 +137,18 @@ void qs_state::ensure_red() {
   check_hip(hipMalloc(&red_out, sizeof(double) * 16), "hipMalloc");
 }
 
+void qs_state::ensure_norm(uint64_t tiles) {
+  if (norm_cap >= tiles) return;
+  if (norm_part) {
+    check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    check_hip(hipFree(norm_part), "hipFree");
+    norm_part = nullptr;
+    norm_cap = 0;
+  }
+  check_hip(hipMalloc(&norm_part, sizeof(double) * tiles), "hipMalloc");
+  norm_cap = tiles;
+}
+
 void qs_state::sync() { check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
 
 static qs_state* check_state(qs_state* s) {
@@ -171,6 +191,7 @@ qs_state::~qs_state() {
     if (owned[k] && buf[k]) hipFree(buf[k]);
   if (red_partials) hipFree(red_partials);
   if (red_out) hipFree(red_out);
+  if (norm_part) hipFree(norm_part);
   if (matbuf) hipFree(matbuf);
 }
 
@@ -359,6 +380,17 @@ extern "C" qs_status qs_apply_layer(qs_state* s, const qs_plan* p, size_t first,
     if (first > L) fail(QS_EINVAL, "first layer out of range");
     size_t last = (count == (size_t)-1 || count > L - first) ? L : first + count;
     apply_layers(*s, const_cast<qs_plan&>(*p), first, last);
+  });
+}
+
+extern "C" qs_status qs_apply_norm2(qs_state* s, const qs_plan* p, double* norm2) {
+  return guarded([&] {
+    check_state(s);
+    if (!p) fail(QS_EINVAL, "plan is NULL");
+    if (!norm2) fail(QS_EINVAL, "norm2 is NULL");
+    if (p->ir.n != s->n) fail(QS_EINVAL, "plan and state qubit counts differ");
+    if (!p->bound) fail(QS_EINVAL, "plan parameters are not bound");
+    *norm2 = apply_norm2(*s, const_cast<qs_plan&>(*p));
   });
 }
 

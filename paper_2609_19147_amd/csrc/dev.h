@@ -371,4 +371,33 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t w, uint32_t grid) {
   return (grid & 7u) == 0u ? (w & 7u) * (grid >> 3) + (w >> 3) : w;
 }
 
+// |a|^2 in FP64.
+template <class R>
+__device__ __forceinline__ double abs2_d(const cplx<R>& a) {
+  const double x = (double)a.re, y = (double)a.im;
+  return x * x + y * y;
+}
+
+// Wavefront sum of one FP64 value per lane in a fixed butterfly order (every
+// lane receives the total).
+__device__ __forceinline__ double wave_sum_fixed(double x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// Workgroup sum of one FP64 value per thread in a fixed order (butterflies
+// within each wavefront, then the wavefronts in order); thread 0 receives
+// the total.  Every thread of the workgroup must call it.
+__device__ __forceinline__ double block_sum_fixed(double x) {
+  __shared__ double wsum[16];
+  x = wave_sum_fixed(x);
+  if ((threadIdx.x & 63u) == 0) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (uint32_t k = 0; k < (blockDim.x >> 6); ++k) t += wsum[k];
+  return t;
+}
+
 }  // namespace qs

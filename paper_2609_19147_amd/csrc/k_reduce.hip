@@ -84,18 +84,13 @@ __global__ void __launch_bounds__(kThreads) finalize_kernel(const double* __rest
   if (threadIdx.x == 0) out[v] = a.s + a.c;
 }
 
-template <class R>
-__device__ __forceinline__ double abs2d(cplx<R> a) {
-  const double x = (double)a.re, y = (double)a.im;
-  return x * x + y * y;
-}
 
 template <class R>
 struct NormF {
   const cplx2<R>* psi;
   __device__ void operator()(uint64_t t, Acc* acc) const {
     const cplx2<R> v = psi[t];
-    nadd(acc[0], abs2d(v.a) + abs2d(v.b));
+    nadd(acc[0], abs2_d(v.a) + abs2_d(v.b));
   }
 };
 
@@ -135,7 +130,7 @@ struct ExpectZF {
   int nt;
   __device__ void operator()(uint64_t t, Acc* acc) const {
     const cplx2<R> v = psi[t];
-    const double p0 = abs2d(v.a), p1 = abs2d(v.b);
+    const double p0 = abs2_d(v.a), p1 = abs2_d(v.b);
     const uint32_t i = (uint32_t)(2 * t);
 #pragma unroll
     for (int k = 0; k < kMaxTermsPerLaunch; ++k) {
@@ -240,8 +235,8 @@ __global__ void __launch_bounds__(kThreads) batch_obs_kernel(const ObsDev* __res
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const cplx2<R> x = psi[(i0 >> 1) + k * kThreads];
-        p[2 * k] = abs2d(x.a);
-        p[2 * k + 1] = abs2d(x.b);
+        p[2 * k] = abs2_d(x.a);
+        p[2 * k + 1] = abs2_d(x.b);
       }
 #pragma unroll
       for (int j = 0; j < 2 * K; ++j) v[j] = O.c0;
@@ -261,7 +256,7 @@ __global__ void __launch_bounds__(kThreads) batch_obs_kernel(const ObsDev* __res
     for (uint32_t t = threadIdx.x; t < len / 2; t += kThreads) {
       const uint32_t i0 = base + 2u * t;
       const cplx2<R> x = psi[i0 >> 1];
-      const double p[2] = {abs2d(x.a), abs2d(x.b)};
+      const double p[2] = {abs2_d(x.a), abs2_d(x.b)};
       double v[2] = {O.c0, O.c0};
       for (int g = 0; g < O.n_groups; ++g) {
         const DiagGroup G = O.groups[g];
@@ -305,6 +300,21 @@ inline int nblocks_for(uint64_t count) {
   uint64_t b = (count + kThreads - 1) / kThreads;
   if (b > (uint64_t)kRedBlocks) b = kRedBlocks;
   return (int)(b < 1 ? 1 : b);
+}
+
+// Block b sums the partials [b chunk, (b + 1) chunk) with its threads
+// strided (compensated), then pairwise (a fixed order throughout).
+__global__ void __launch_bounds__(kThreads) fold_kernel(const double* __restrict__ partials, uint64_t count,
+                                                        uint64_t chunk, double* __restrict__ out) {
+  const uint64_t b0 = blockIdx.x * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
+  Acc a = {0.0, 0.0};
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kThreads) nadd(a, partials[i]);
+  __shared__ Acc red[kThreads];
+  a = block_fold(a, red);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = a.s;
+    out[2 * blockIdx.x + 1] = a.c;
+  }
 }
 
 template <int NV, class F>
@@ -473,8 +483,10 @@ bool launch_rho_tile(const cplx<R>* phi, const cplx<R>* lam, int n, const RhoTil
   static bool attr_set = false;
   if (!attr_set) {
     if (hipFuncSetAttribute((const void*)rho_tile_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kMaxDynamic) != hipSuccess)
+                            (int)kMaxDynamic) != hipSuccess) {
+      (void)hipGetLastError();  // the caller falls back to the per-bit path
       return false;
+    }
     attr_set = true;
   }
   const uint32_t ntiles = 1u << (n - A.m);
@@ -507,6 +519,16 @@ void launch_batch_observable(const ObsDev* obs_dev, uint32_t count, uint32_t n, 
 }
 template void launch_batch_observable<float>(const ObsDev*, uint32_t, uint32_t, double*, double*, hipStream_t);
 template void launch_batch_observable<double>(const ObsDev*, uint32_t, uint32_t, double*, double*, hipStream_t);
+
+void launch_fold_partials(const double* partials, uint64_t count, double* scratch, double* out, hipStream_t s) {
+  uint64_t nb = (count + kThreads - 1) / kThreads;
+  if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
+  if (nb < 1) nb = 1;
+  const uint64_t chunk = (count + nb - 1) / nb;
+  QS_LAUNCH("fold_partials", s, fold_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, partials, count, chunk,
+            scratch);
+  QS_LAUNCH("reduce_finalize", s, finalize_kernel<1>, dim3(1), dim3(kThreads), 0, s, scratch, (int)nb, out);
+}
 
 template void launch_norm2<float>(const cplx<float>*, uint64_t, double*, double*, hipStream_t);
 template void launch_norm2<double>(const cplx<double>*, uint64_t, double*, double*, hipStream_t);

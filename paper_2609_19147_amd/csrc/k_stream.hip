@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kThreads) diag_kernel(cplx<R>* psi, uint64_t n
 // (aligned runs of 2^c).
 template <class R>
 __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
-                                                       Gf2Args A) {
+                                                       Gf2Args A, double* __restrict__ norm_part) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
   __shared__ uint32_t tl[1 << kGf2MaxC], th[1 << kGf2MaxC], au[1 << kGf2MaxC], vh[1 << kGf2MaxC],
@@ -149,6 +149,12 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
       const uint32_t tt = threadIdx.x + kThreads * k;
       st_nt(out + (y0 ^ (tt & lomask) ^ vh[tt >> A.c]), v[k]);
     }
+    if (norm_part != nullptr) {
+      // the layer's norm, fused: each wavefront's FP64 sum of |psi|^2 over
+      // what it stored (no workgroup barrier)
+      const double t = wave_sum_fixed(abs2_d(v[0]) + abs2_d(v[1]) + abs2_d(v[2]) + abs2_d(v[3]));
+      if ((threadIdx.x & 63u) == 0) norm_part[4 * (size_t)coset + (threadIdx.x >> 6)] = t;
+    }
     return;
   }
   for (uint32_t s = threadIdx.x; s < D; s += kThreads) {
@@ -158,9 +164,16 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
     T[tk ^ hx[tk >> A.c]] = in[x];
   }
   __syncthreads();
+  double nacc = 0.0;
   for (uint32_t t = threadIdx.x; t < D; t += kThreads) {
     const uint32_t y = y0 ^ (t & lomask) ^ vh[t >> A.c];
-    out[y] = T[t ^ hx[t >> A.c]];
+    const cplx<R> v = T[t ^ hx[t >> A.c]];
+    out[y] = v;
+    nacc += abs2_d(v);
+  }
+  if (norm_part != nullptr) {
+    const double t = wave_sum_fixed(nacc);
+    if ((threadIdx.x & 63u) == 0) norm_part[4 * (size_t)coset + (threadIdx.x >> 6)] = t;
   }
 }
 
@@ -240,10 +253,10 @@ void launch_diag(cplx<R>* psi, int n, const DiagDev& D, hipStream_t s) {
             D);
 }
 template <class R>
-void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s) {
+void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s, double* norm_part) {
   const unsigned n_cosets = 1u << (A.n - A.d);
   const size_t lds = sizeof(cplx<R>) << A.d;
-  QS_LAUNCH("gf2_gather", s, gf2_kernel<R>, dim3(n_cosets), dim3(kThreads), lds, s, in, out, A);
+  QS_LAUNCH("gf2_gather", s, gf2_kernel<R>, dim3(n_cosets), dim3(kThreads), lds, s, in, out, A, norm_part);
 }
 
 #define INST(R)                                                                              \
@@ -251,7 +264,7 @@ void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s
   template void launch_fill_uniform<R>(cplx<R>*, uint64_t, double, hipStream_t);            \
   template void launch_gather<R>(const cplx<R>*, const uint64_t*, cplx<R>*, uint64_t, hipStream_t); \
   template void launch_diag<R>(cplx<R>*, int, const DiagDev&, hipStream_t);                 \
-  template void launch_gf2<R>(const cplx<R>*, cplx<R>*, const Gf2Args&, hipStream_t);
+  template void launch_gf2<R>(const cplx<R>*, cplx<R>*, const Gf2Args&, hipStream_t, double*);
 INST(float)
 INST(double)
 template void launch_convert<float, double>(cplx<float>*, const cplx<double>*, uint64_t, hipStream_t);

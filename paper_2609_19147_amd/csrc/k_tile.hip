@@ -406,9 +406,12 @@ __device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C,
 
 }
 
+// Stores the tile; returns this thread's FP64 sum of |psi|^2 over what it
+// stored when the pass reports its norm (0 otherwise).
 template <class R>
-__device__ __forceinline__ void tile_store(const TileKArgs<R>& A, const Ctx& C, const cplx<R>* T) {
+__device__ __forceinline__ double tile_store(const TileKArgs<R>& A, const Ctx& C, const cplx<R>* T) {
   const uint32_t M = 1u << A.m, stride = 2 * blockDim.x;
+  double nacc = 0.0;
   cplx<R>* __restrict__ psi = A.psi;
   // with the pass's butterfly normalisation
   const R sc = (R)A.scale;
@@ -428,6 +431,10 @@ __device__ __forceinline__ void tile_store(const TileKArgs<R>& A, const Ctx& C, 
 #pragma unroll
       for (int k = 0; k < kChunk; ++k)
         st_nt(reinterpret_cast<cplx2<R>*>(psi + (C.base | C.dep(p0 + stride * k))), v[k]);
+      if (A.norm_part != nullptr) {
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) nacc += abs2_d(v[k].a) + abs2_d(v[k].b);
+      }
     }
   } else {
     for (uint32_t pos = 2 * threadIdx.x; pos < M; pos += stride) {
@@ -437,8 +444,10 @@ __device__ __forceinline__ void tile_store(const TileKArgs<R>& A, const Ctx& C, 
         v.b = cscale(v.b, sc);
       }
       st_nt(reinterpret_cast<cplx2<R>*>(psi + (C.base | C.dep(pos))), v);
+      if (A.norm_part != nullptr) nacc += abs2_d(v.a) + abs2_d(v.b);
     }
   }
+  return nacc;
 }
 
 template <class R, bool kDiag>
@@ -449,7 +458,11 @@ __device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t 
   tile_load<R>(A, C, T);
   __syncthreads();
   tile_rounds<R, kDiag>(A, C, T);
-  tile_store<R>(A, C, T);
+  const double nacc = tile_store<R>(A, C, T);
+  if (A.norm_part != nullptr) {
+    const double t = block_sum_fixed(nacc);
+    if (threadIdx.x == 0) A.norm_part[coset] = t;
+  }
 }
 
 template <class R, bool kDiag>
@@ -483,6 +496,7 @@ __device__ __forceinline__ TileKArgs<R> load_args(const TileKArgs<R>* descs, uin
   A.n_rounds = P->n_rounds;
   A.n = P->n;
   A.scale = P->scale;
+  A.norm_part = nullptr;  // batched passes never report a norm
   return A;
 }
 
@@ -508,6 +522,11 @@ inline uint32_t tile_threads_for(uint32_t m) {
   return (kDiag && sizeof(R) == 4 && t > 256u) ? 256u : t;
 }
 
+// Dynamic LDS limit of the tile kernels: the largest tile (2^14 complex64 or
+// 2^13 complex128 amplitudes with padding, 139264 bytes) plus headroom, below
+// the CU's 160 KB so that the kernels' small static LDS still fits.
+constexpr int kTileDynLds = 144 * 1024;
+
 inline size_t tile_lds(uint32_t m, size_t elem) {
   const uint32_t M = 1u << m;
   return elem * (M + ((M >> 5) << 1));
@@ -519,8 +538,7 @@ template <class R, bool kDiag>
 void launch_tile_batched_k(const TileKArgs<R>* descs_dev, uint32_t count, uint32_t n, uint32_t m, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)tile_kernel_batched<R, kDiag>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
+    allow_dynamic_lds((const void*)tile_kernel_batched<R, kDiag>, kTileDynLds, "tile_pass_batched");
     attr_set = true;
   }
   const uint32_t shift = n - m;
@@ -541,7 +559,7 @@ template <class R, bool kDiag>
 void launch_tile_k(const TileKArgs<R>& A, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)tile_kernel<R, kDiag>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    allow_dynamic_lds((const void*)tile_kernel<R, kDiag>, kTileDynLds, "tile_pass");
     attr_set = true;
   }
   // one thread per register group of a round, between 64 and 512 threads
@@ -557,7 +575,7 @@ void launch_tile(const TileKArgs<R>& A, hipStream_t s) {
   } else if constexpr (sizeof(R) == 4) {
     static bool attr_set = false;
     if (!attr_set) {
-      hipFuncSetAttribute((const void*)tile_kernel_c64, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      allow_dynamic_lds((const void*)tile_kernel_c64, kTileDynLds, "tile_pass");
       attr_set = true;
     }
     QS_LAUNCH("tile_pass", s, tile_kernel_c64, dim3(1u << (A.n - A.m)), dim3(tile_threads(A.m)),

@@ -15,6 +15,8 @@ namespace qs {
 void prof_begin(const char* name, hipStream_t s);
 void prof_end(hipStream_t s);
 void check_launch(const char* name);
+// Raise the dynamic LDS limit of a kernel (QS_EDEVICE on failure).
+void allow_dynamic_lds(const void* kernel, int bytes, const char* name);
 
 #define QS_LAUNCH(name, stream, ...)      \
   do {                                    \
@@ -57,7 +59,8 @@ struct TileKArgs {
   uint32_t L, a, h, m;
   uint32_t n_rounds;
   uint32_t n;
-  double scale;  // 2^(-k/2) for the pass's k unscaled butterflies
+  double scale;       // 2^(-k/2) for the pass's k unscaled butterflies
+  double* norm_part;  // null, or one FP64 sum of |psi|^2 as stored per tile
 };
 template <class R> void launch_tile(const TileKArgs<R>& A, hipStream_t s);
 // count instances of one geometry (n qubits, m tile bits), descriptors in device
@@ -105,7 +108,13 @@ template <class R>
 bool launch_dense(cplx<R>* psi, int n, int k, const int* bits_sorted, const cplx<R>* U_dev, hipStream_t s);
 
 template <class R>
-void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s);
+void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s, double* norm_part = nullptr);
+// Norm partials of a gather: one per wavefront of each coset tile (four
+// wavefronts per tile).
+inline uint64_t gf2_norm_slots(const Gf2Args& A) { return 4ull << (A.n - A.d); }
+// out[0] = sum of count FP64 partials in a fixed order (compensated);
+// scratch holds 2 kRedBlocks doubles.
+void launch_fold_partials(const double* partials, uint64_t count, double* scratch, double* out, hipStream_t s);
 
 // ---- FP64 reductions (deterministic: fixed grid, fixed combination order) ----
 // Each writes NV (sum, compensation) pairs per block into partials and then

@@ -215,7 +215,7 @@ namespace qs {
 namespace {
 
 template <class R>
-void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
+void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last, double* norm_last = nullptr) {
   const PlanDev& d = p.device_for(s.dtype);
   const char* base = (const char*)d.blob;
   const PlanIR& P = p.ir;
@@ -244,12 +244,14 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last) {
         A.n_rounds = (uint32_t)T.rounds.size();
         A.n = s.n;
         A.scale = T.scale;
+        A.norm_part = li + 1 == last ? norm_last : nullptr;
         launch_tile<R>(A, s.stream);
         break;
       }
       case L_GF2: {
         s.ensure_other();
-        launch_gf2<R>((const cplx<R>*)s.buf[s.cur], (cplx<R>*)s.buf[1 - s.cur], p.gf2[L.index], s.stream);
+        launch_gf2<R>((const cplx<R>*)s.buf[s.cur], (cplx<R>*)s.buf[1 - s.cur], p.gf2[L.index], s.stream,
+                      li + 1 == last ? norm_last : nullptr);
         s.cur = 1 - s.cur;
         break;
       }
@@ -360,6 +362,34 @@ void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last) {
 void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params, bool inverse) {
   if (s.dtype == QS_C64) plain_t<float>(s, g, params, inverse);
   else plain_t<double>(s, g, params, inverse);
+}
+
+double apply_norm2(qs_state& s, qs_plan& p) {
+  const size_t L = p.ir.layers.size();
+  uint64_t tiles = 0;
+  if (L > 0) {
+    const LayerIR& last = p.ir.layers.back();
+    if (last.kind == L_TILE) {
+      const TilePassIR& T = p.ir.passes[last.index];
+      tiles = 1ull << (s.n - (T.L + T.h));
+    } else if (last.kind == L_GF2) {
+      p.device_for(s.dtype);
+      tiles = gf2_norm_slots(p.gf2[last.index]);
+    }
+  }
+  if (tiles == 0 || tiles > (1ull << 24)) {
+    apply_layers(s, p, 0, L);
+    return state_norm2(s);
+  }
+  s.ensure_red();
+  s.ensure_norm(tiles);
+  if (s.dtype == QS_C64) apply_layers_t<float>(s, p, 0, L, s.norm_part);
+  else apply_layers_t<double>(s, p, 0, L, s.norm_part);
+  launch_fold_partials(s.norm_part, tiles, s.red_partials, s.red_out, s.stream);
+  double o;
+  check_hip(hipMemcpyAsync(&o, s.red_out, sizeof o, hipMemcpyDeviceToHost, s.stream), "hipMemcpyAsync");
+  s.sync();
+  return o;
 }
 
 double state_norm2(qs_state& s) {

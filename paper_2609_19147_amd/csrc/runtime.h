@@ -22,6 +22,8 @@ struct qs_state {
   hipStream_t stream = nullptr;
   double* red_partials = nullptr;
   double* red_out = nullptr;
+  double* norm_part = nullptr;  // per-tile norm partials of a fused apply-and-norm
+  uint64_t norm_cap = 0;
   void* matbuf = nullptr;  // device staging for dense plain gates
 
   size_t amp_bytes() const;
@@ -29,6 +31,7 @@ struct qs_state {
   void* cur_ptr() const { return buf[cur]; }
   void ensure_other();
   void ensure_red();
+  void ensure_norm(uint64_t tiles);
   void sync();
   ~qs_state();
 };
@@ -75,6 +78,10 @@ struct qs_plan {
 namespace qs {
 
 void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last);
+// Apply every layer and return ||psi||^2 of the result (FP64).  When the last
+// layer is a tile pass or a gather, its kernel sums |psi|^2 over what it
+// writes (no separate read of the state); otherwise a reduction follows.
+double apply_norm2(qs_state& s, qs_plan& p);
 void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params, bool inverse = false);
 double state_norm2(qs_state& s);
 std::complex<double> state_overlap(qs_state& a, qs_state& b);
