@@ -98,9 +98,19 @@ __global__ void __launch_bounds__(kThreads) diag_kernel(cplx<R>* psi, uint64_t n
 // Reads: x = x0 ^ s_lo ^ AU[s_hi] (aligned runs of 2^c); the element lands at
 // tile coordinate t = TL[s_lo] ^ TH[s_hi].  Writes: y = y0 ^ t_lo ^ VH[t_hi]
 // (aligned runs of 2^c).
+// Representative y0 of coset c (its bits on the free positions) and its
+// source x0 = A y0 ^ c'.
+__device__ __forceinline__ void gf2_coset_rep(const Gf2Args& A, uint32_t c, uint32_t& y0, uint32_t& x0) {
+  y0 = 0;
+  for (uint32_t j = 0; j < A.n_free; ++j) y0 |= ((c >> j) & 1u) << A.free_bits[j];
+  x0 = A.cprime;
+  for (uint32_t j = 0; j < A.n; ++j)
+    if ((y0 >> j) & 1u) x0 ^= A.acol[j];
+}
+
 template <class R>
 __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
-                                                       Gf2Args A, double* __restrict__ norm_part) {
+                                                       Gf2Args A, double* __restrict__ norm_part, uint32_t per) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
   __shared__ uint32_t tl[1 << kGf2MaxC], th[1 << kGf2MaxC], au[1 << kGf2MaxC], vh[1 << kGf2MaxC],
@@ -114,49 +124,56 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
     vh[k] = A.v_hi[k];
     hx[k] = A.hx[k];
   }
-  // coset representative and its source
-  const uint32_t coset = blockIdx.x;
-  uint32_t y0 = 0;
-  for (uint32_t j = 0; j < A.n_free; ++j) y0 |= ((coset >> j) & 1u) << A.free_bits[j];
-  uint32_t x0 = A.cprime;
-  for (uint32_t j = 0; j < A.n; ++j)
-    if ((y0 >> j) & 1u) x0 ^= A.acol[j];
   __syncthreads();
   const uint32_t D = 1u << A.d;
   const uint32_t lomask = nlo - 1u;
   if (D == kThreads * 4) {
-    // full tiles: four independent loads in flight per thread, then four stores
-    cplx<R> v[4];
-    uint32_t t[4];
+    // full tiles, `per` consecutive cosets per workgroup (the tables above are
+    // loaded once): two 16-byte loads in flight per thread, then two stores
+    for (uint32_t q = 0; q < per; ++q) {
+      const uint32_t coset = blockIdx.x * per + q;
+      uint32_t y0, x0;
+      gf2_coset_rep(A, coset, y0, x0);
+      // 16-byte accesses: source and destination runs are aligned blocks of
+      // 2^c elements (c >= 1) XOR-permuted, so elements 2i, 2i + 1 of a run
+      // share one aligned pair; `f` says whether the pair is swapped
+      cplx<R> v[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t s = threadIdx.x + kThreads * k;
-      const uint32_t slo = s & lomask, shi = s >> A.c;
-      v[k] = ld_nt(in + (x0 ^ slo ^ au[shi]));
-      const uint32_t tk = tl[slo] ^ th[shi];
-      t[k] = tk ^ hx[tk >> A.c];
-    }
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t s = 2u * (threadIdx.x + kThreads * k);
+        const uint32_t slo = s & lomask, shi = s >> A.c;
+        const uint32_t xa = x0 ^ slo ^ au[shi];
+        const cplx2<R> w = ld_nt(reinterpret_cast<const cplx2<R>*>(in + (xa & ~1u)));
+        const uint32_t f = xa & 1u;  // w.a holds source coordinate slo ^ f
+        const uint32_t ta = tl[slo ^ f] ^ th[shi], tb = tl[slo ^ f ^ 1u] ^ th[shi];
+        T[ta ^ hx[ta >> A.c]] = w.a;
+        T[tb ^ hx[tb >> A.c]] = w.b;
+      }
+      __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 4; ++k) T[t[k]] = v[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t tt = threadIdx.x + kThreads * k;
-      v[k] = T[tt ^ hx[tt >> A.c]];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t tt = threadIdx.x + kThreads * k;
-      st_nt(out + (y0 ^ (tt & lomask) ^ vh[tt >> A.c]), v[k]);
-    }
-    if (norm_part != nullptr) {
-      // the layer's norm, fused: each wavefront's FP64 sum of |psi|^2 over
-      // what it stored (no workgroup barrier)
-      const double t = wave_sum_fixed(abs2_d(v[0]) + abs2_d(v[1]) + abs2_d(v[2]) + abs2_d(v[3]));
-      if ((threadIdx.x & 63u) == 0) norm_part[4 * (size_t)coset + (threadIdx.x >> 6)] = t;
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t tt = 2u * (threadIdx.x + kThreads * k);
+        const uint32_t ya = y0 ^ (tt & lomask) ^ vh[tt >> A.c];
+        const uint32_t f = ya & 1u;  // the even destination takes tile coordinate tt ^ f
+        const uint32_t te = tt ^ f, to = tt ^ f ^ 1u;
+        v[2 * k] = T[te ^ hx[te >> A.c]];
+        v[2 * k + 1] = T[to ^ hx[to >> A.c]];
+        st_nt(reinterpret_cast<cplx2<R>*>(out + (ya & ~1u)), cplx2<R>{v[2 * k], v[2 * k + 1]});
+      }
+      if (norm_part != nullptr) {
+        // the layer's norm, fused: each wavefront's FP64 sum of |psi|^2 over
+        // what it stored (no workgroup barrier)
+        const double tn = wave_sum_fixed(abs2_d(v[0]) + abs2_d(v[1]) + abs2_d(v[2]) + abs2_d(v[3]));
+        if ((threadIdx.x & 63u) == 0) norm_part[4 * (size_t)coset + (threadIdx.x >> 6)] = tn;
+      }
+      __syncthreads();  // the next coset rewrites the tile
     }
     return;
   }
+  // partial tiles (d < 10): one coset per workgroup
+  const uint32_t coset = blockIdx.x;
+  uint32_t y0, x0;
+  gf2_coset_rep(A, coset, y0, x0);
   for (uint32_t s = threadIdx.x; s < D; s += kThreads) {
     const uint32_t slo = s & lomask, shi = s >> A.c;
     const uint32_t x = x0 ^ slo ^ au[shi];
@@ -256,7 +273,10 @@ template <class R>
 void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s, double* norm_part) {
   const unsigned n_cosets = 1u << (A.n - A.d);
   const size_t lds = sizeof(cplx<R>) << A.d;
-  QS_LAUNCH("gf2_gather", s, gf2_kernel<R>, dim3(n_cosets), dim3(kThreads), lds, s, in, out, A, norm_part);
+  // full tiles: four cosets per workgroup once there are plenty of them
+  const unsigned per = ((1u << A.d) == kThreads * 4u && n_cosets >= 8192u) ? 4u : 1u;
+  QS_LAUNCH("gf2_gather", s, gf2_kernel<R>, dim3(n_cosets / per), dim3(kThreads), lds, s, in, out, A, norm_part,
+            per);
 }
 
 #define INST(R)                                                                              \
