@@ -500,12 +500,14 @@ __device__ __forceinline__ TileKArgs<R> load_args(const TileKArgs<R>* descs, uin
   return A;
 }
 
-// Many instances of one tile geometry in one grid: block b runs coset
-// (b & (2^shift - 1)) of instance (b >> shift).
+// Many instances of one tile geometry in one grid: virtual block v (the
+// XCD-aware order of the workgroups) runs coset (v & (2^shift - 1)) of
+// instance (v >> shift).
 template <class R, bool kDiag>
 __global__ void __launch_bounds__(kMaxThreads) tile_kernel_batched(const TileKArgs<R>* __restrict__ descs,
                                                                     uint32_t shift) {
-  tile_body<R, kDiag>(load_args(descs, blockIdx.x >> shift), blockIdx.x & ((1u << shift) - 1u));
+  const uint32_t v = xcd_block(blockIdx.x, gridDim.x);
+  tile_body<R, kDiag>(load_args(descs, v >> shift), v & ((1u << shift) - 1u));
 }
 
 inline uint32_t tile_threads(uint32_t m) {
