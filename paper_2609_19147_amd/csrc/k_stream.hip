@@ -8,7 +8,7 @@ namespace qs {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kDiagPairsPerThread = 4;
+constexpr int kDiagPairsPerThread = 8;
 
 inline unsigned grid_for(uint64_t work, int per_block) {
   uint64_t b = (work + per_block - 1) / per_block;
@@ -266,7 +266,8 @@ void launch_gather(const cplx<R>* psi, const uint64_t* idx, cplx<R>* out, uint64
 template <class R>
 void launch_diag(cplx<R>* psi, int n, const DiagDev& D, hipStream_t s) {
   const uint64_t npairs = (1ull << n) / 2;
-  QS_LAUNCH("diag_lut", s, diag_kernel<R>, dim3(grid_for(npairs, kThreads * 4)), dim3(kThreads), 0, s, psi, npairs,
+  QS_LAUNCH("diag_lut", s, diag_kernel<R>, dim3(grid_for(npairs, kThreads * kDiagPairsPerThread)), dim3(kThreads), 0,
+            s, psi, npairs,
             D);
 }
 template <class R>
