@@ -241,6 +241,13 @@ __device__ __forceinline__ void diag_apply(cplx<R>* a, uint32_t i0, const uint32
   }
 }
 
+// a[j] *= exp(i (global + sum_g theta_g count_g(i0 | off[j]))): the layer's
+// total angle per amplitude in FP64, then one sincos (for layers of many
+// groups this replaces a table multiply per group).
+template <class R, int NJ>
+__device__ __forceinline__ void diag_apply_total_angle(cplx<R>* a, uint32_t i0, const uint32_t (&off)[NJ],
+                                                       const DiagDev& D);
+
 // The 16 amplitudes of a tile round: index i0 | (any subset of the round's
 // state bits b[0..3]), register j holding subset j.  For groups whose pair
 // table (qt, 8 bytes per group) says the count is a polynomial of degree <= 2
@@ -266,6 +273,26 @@ __device__ __forceinline__ cplx<double> cis_reduced<double>(double x) {
   double s, c;
   sincos(reduce_2pi(x), &s, &c);
   return {c, s};
+}
+
+template <class R, int NJ>
+__device__ __forceinline__ void diag_apply_total_angle(cplx<R>* a, uint32_t i0, const uint32_t (&off)[NJ],
+                                                       const DiagDev& D) {
+  const cptr<DiagGroup> groups = to_const(D.groups);
+  const cptr<double> theta = to_const(D.theta);
+  double ang[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) ang[j] = D.global;
+  for (int g = 0; g < D.n_groups; ++g) {
+    int cnt[NJ];
+    diag_counts<NJ>(i0, off, D.terms, groups[g].term_begin, groups[g].term_end, cnt);
+    const double th = theta[g];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) ang[j] = fma(th, (double)cnt[j], ang[j]);
+  }
+  const double sg = D.conj ? -1.0 : 1.0;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) a[j] = cmul(a[j], cis_reduced<R>(sg * ang[j]));
 }
 
 // Angle mode: every group quadratic in the round's bits, so the total phase

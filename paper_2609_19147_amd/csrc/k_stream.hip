@@ -9,6 +9,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kDiagPairsPerThread = 8;
+constexpr int kDiagAngleGroups = 4;  // from this many groups: total angle, one sincos per amplitude
 
 inline unsigned grid_for(uint64_t work, int per_block) {
   uint64_t b = (work + per_block - 1) / per_block;
@@ -79,7 +80,8 @@ __global__ void __launch_bounds__(kThreads) diag_kernel(cplx<R>* psi, uint64_t n
         a[2 * k] = v.a;
         a[2 * k + 1] = v.b;
       }
-      diag_apply<R, 2 * K>(a, (uint32_t)(2 * t0), off, D);
+      if (D.n_groups >= kDiagAngleGroups) diag_apply_total_angle<R, 2 * K>(a, (uint32_t)(2 * t0), off, D);
+      else diag_apply<R, 2 * K>(a, (uint32_t)(2 * t0), off, D);
 #pragma unroll
       for (int k = 0; k < K; ++k) st_nt(p2 + t0 + k * kThreads, cplx2<R>{a[2 * k], a[2 * k + 1]});
     }

@@ -56,3 +56,19 @@ def test_qpe_exact_phase_21q(qs, dtype):
     qs.apply(st, qs.Plan(t + 1, W.qpe_ladder_stream(t, 2 * math.pi * j / 2 ** t)))
     amp = qs.amplitudes(st, [(j << 1) | 1])[0]
     assert abs(abs(amp) ** 2 - 1) < (1e-5 if dtype == "c64" else 1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_standalone_many_group_diagonal_layers(qs, dtype):
+    """Diagonal-only streams become one standalone diagonal pass; with many
+    groups it sums each amplitude's angle in FP64 (long-range ZZ couplings,
+    13 distance groups; a controlled-power ladder with angles up to 0.4 2^23)."""
+    n = 14
+    lri = W.long_range_ising_stream(n, 1.0, 1.5, 0.0, 0.07, 1)[: n * (n - 1) // 2]
+    ladder = [W.G("CPHASE", k, n - 1, theta=0.4 * 2.0 ** (10 + k)) for k in range(n - 1)]
+    mixed = lri + ladder + [W.G("RZ", q, theta=0.3 + 0.1 * q) for q in range(n)]
+    for stream in (lri, ladder, mixed):
+        plan = qs.Plan(n, stream)
+        assert [L["kind"] for L in plan.describe()["layers"]] == ["diag"]
+        got, ref = run_both(qs, n, stream, dtype, W.gaussian_state(n, 6))
+        assert metrics.infidelity(got, ref) <= BAR[dtype]
