@@ -463,6 +463,17 @@ def bench_xxz(qs, torch, reps=3):
     return out
 
 
+SECTIONS = {
+    "batched_qaoa": lambda qs, torch: bench_batched_qaoa(qs, torch),
+    "adjoint": lambda qs, torch: bench_adjoint(qs, torch),
+    "tfim25": lambda qs, torch: bench_tfim(qs, torch),
+    "dense_blocks": lambda qs, torch: bench_dense(qs, torch),
+    "layers_30q": lambda qs, torch: bench_layers(qs, torch),
+    "diag_families_25q": lambda qs, torch: bench_families(qs, torch),
+    "xxz_families": lambda qs, torch: bench_xxz(qs, torch),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -473,6 +484,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, adjoint and TFIM sections")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain device copy of the state (2 S bytes) as a counter calibration")
+    ap.add_argument("--only", choices=sorted(SECTIONS),
+                    help="run one extra section alone and print its JSON (a profiling aid; not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU only; sharding over several GPUs is "
@@ -481,6 +494,10 @@ def main():
 
     import torch
     import paper_2609_19147_amd as qs
+
+    if args.only:
+        print(json.dumps({args.only: SECTIONS[args.only](qs, torch)}))
+        return
 
     n = args.n
     S = 8 * (1 << n)
