@@ -1107,7 +1107,36 @@ class Builder {
   }
 
   // ---- tile-pass scheduling of one segment ------------------------------------
+  // A Hadamard butterfly (an H, or a QFT stage whose twiddle bits [base, p)
+  // are empty) followed by another on the same bit, with no item touching the
+  // bit in between, is the identity: both are dropped (exactly; the pass
+  // scale counts the remaining butterflies).
+  bool plain_butterfly(const Item& it) const {
+    if (it.ir.type != 0) return false;
+    const OpIR& op = P.ops[it.ir.index];
+    if (op.kind == OP_H) return op.fixed_mat < 0;
+    return (op.kind == OP_QFT || op.kind == OP_QFT_INV) && op.base == op.bit;
+  }
+
+  void cancel_butterfly_pairs() {
+    std::vector<char> dead(seg.size(), 0);
+    for (size_t i = 0; i < seg.size(); ++i) {
+      if (dead[i] || !plain_butterfly(seg[i])) continue;
+      const uint32_t b = seg[i].W;
+      for (size_t j = i + 1; j < seg.size(); ++j) {
+        if (dead[j] || !((seg[j].W | seg[j].R) & b)) continue;
+        if (plain_butterfly(seg[j]) && seg[j].W == b) dead[i] = dead[j] = 1;
+        break;
+      }
+    }
+    size_t k = 0;
+    for (size_t i = 0; i < seg.size(); ++i)
+      if (!dead[i]) seg[k++] = seg[i];
+    seg.resize(k);
+  }
+
   void flush_segment() {
+    cancel_butterfly_pairs();
     if (seg.empty()) return;
     size_t N = seg.size();
     std::vector<std::vector<int>> deps(N);

@@ -375,3 +375,18 @@ def test_window_option_validation():
             qs.Plan(10, W.ladder_stream(5, 1.0, 0.5, 0.05, 1), window_k=bad)
     # fewer than 8 qubits: no window (a dense block needs 4 other bits)
     assert qs.Plan(6, W.ladder_stream(3, 1.0, 0.5, 0.05, 1)).describe()["windows"] == 0
+
+
+@pytest.mark.parametrize("n", [9, 14, 20])
+def test_trivial_qft_stage_and_hadamard_cancel(n):
+    """The QFT's last stage (on the register's lowest bit: no twiddle bits)
+    is a plain butterfly; the Walsh layer's H on the same bit cancels it."""
+    stream = W.qft_stream(n) + W.wht_stream(n)
+    d = check_plan(n, stream, tol=1e-11)
+    ops = [op for L in d["layers"] if L["kind"] == "tile" for op in L["ops"]]
+    assert len(ops) == 2 * n - 2
+    assert all(op["bit"] != 0 for op in ops)
+    # an H on another bit in between does not block it; a gate on bit 0 does
+    blocked = W.qft_stream(n) + [W.G("T", n - 1)] + W.wht_stream(n)
+    d2 = check_plan(n, blocked, tol=1e-11)
+    assert sum(1 for L in d2["layers"] if L["kind"] == "tile" for op in L["ops"]) > 2 * n - 2
