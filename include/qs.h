@@ -272,6 +272,11 @@ qs_status qs_batch_run(qs_batch* b);
  * only): obs[i] has n_terms[i] terms; out receives n_inst values (sync). */
 qs_status qs_batch_expect_diag(qs_batch* b, const qs_pauli* const* obs,
                                const size_t* n_terms, double* out);
+/* Expectation of any Pauli sum per instance (sync): Z-type terms of all
+ * instances in one batched FP64 reduction, terms with X or Y factors per
+ * instance with pair reads.  obs[i] has n_terms[i] terms; out receives n_inst
+ * values. */
+qs_status qs_batch_expect(qs_batch* b, const qs_pauli* const* obs, const size_t* n_terms, double* out);
 /* State of instance i as a view (valid until the batch is freed). */
 qs_status qs_batch_state(qs_batch* b, size_t i, qs_state** view);
 qs_status qs_batch_free(qs_batch* b);

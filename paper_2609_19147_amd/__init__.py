@@ -200,13 +200,21 @@ class Batch:
     def run(self) -> None:
         check(lib().qs_batch_run(self.h))
 
-    def expect_diag(self, observables) -> np.ndarray:
+    def _expect(self, fn, observables) -> np.ndarray:
         arrs = [to_c_terms(o) for o in observables]
         ptrs = (C.POINTER(QsPauli) * len(arrs))(*[C.cast(a, C.POINTER(QsPauli)) for a in arrs])
         cnt = (C.c_size_t * len(arrs))(*[len(o) for o in observables])
         out = np.zeros(len(arrs))
-        check(lib().qs_batch_expect_diag(self.h, ptrs, cnt, out.ctypes.data_as(C.POINTER(C.c_double))))
+        check(fn(self.h, ptrs, cnt, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
+
+    def expect_diag(self, observables) -> np.ndarray:
+        """Per-instance expectation of Z-type Pauli sums (one batched reduction)."""
+        return self._expect(lib().qs_batch_expect_diag, observables)
+
+    def expect(self, observables) -> np.ndarray:
+        """Per-instance expectation of any Pauli sums (X / Y terms per instance)."""
+        return self._expect(lib().qs_batch_expect, observables)
 
     def state(self, i: int) -> StateView:
         v = C.c_void_p()

@@ -81,6 +81,7 @@ _SIGS = {
     "qs_batch_refresh": ([P], C.c_int),
     "qs_batch_run": ([P], C.c_int),
     "qs_batch_expect_diag": ([P, C.POINTER(C.POINTER(QsPauli)), C.POINTER(SZ), C.POINTER(C.c_double)], C.c_int),
+    "qs_batch_expect": ([P, C.POINTER(C.POINTER(QsPauli)), C.POINTER(SZ), C.POINTER(C.c_double)], C.c_int),
     "qs_batch_state": ([P, SZ, C.POINTER(P)], C.c_int),
     "qs_batch_free": ([P], C.c_int),
     "qs_profile_enable": ([C.c_int], C.c_int),

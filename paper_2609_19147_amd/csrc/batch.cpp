@@ -334,15 +334,19 @@ extern "C" qs_status qs_batch_expect_diag(qs_batch* b, const qs_pauli* const* ob
     host.resize(obs_off + b->n_inst * sizeof(ObsDev));
     size_t need_red = 0;
     for (auto& G : b->groups) need_red = std::max(need_red, batch_observable_partials((uint32_t)G.inst.size(), G.n));
+    // device layout: tables and descriptors, then the results (256-byte
+    // aligned), then the partial sums
+    const size_t out_off = (host.size() + 255) & ~size_t(255);
+    const size_t part_off = out_off + sizeof(double) * (b->n_inst + 8);
     void* dev = nullptr;
-    check_hip(hipMalloc(&dev, host.size() + sizeof(double) * (b->n_inst + need_red + 16)), "hipMalloc");
+    check_hip(hipMalloc(&dev, part_off + sizeof(double) * need_red), "hipMalloc");
     struct Guard {
       void* p;
       ~Guard() { hipFree(p); }
     } guard{dev};
     char* base = (char*)dev;
-    double* dout = (double*)(base + ((host.size() + 255) & ~size_t(255)));
-    double* partials = dout + b->n_inst + 8;
+    double* dout = (double*)(base + out_off);
+    double* partials = (double*)(base + part_off);
     // descriptors in group order
     std::vector<size_t> pos(b->n_inst);
     size_t k = 0;
@@ -374,6 +378,34 @@ extern "C" qs_status qs_batch_expect_diag(qs_batch* b, const qs_pauli* const* ob
               "hipMemcpyAsync");
     check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     for (size_t i = 0; i < b->n_inst; ++i) out[i] = res[pos[i]];
+    return QS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+}
+
+extern "C" qs_status qs_batch_expect(qs_batch* b, const qs_pauli* const* obs, const size_t* n_terms, double* out) {
+  try {
+    if (!b || !obs || !n_terms || !out) fail(QS_EINVAL, "NULL argument");
+    // Z-type terms of every instance in one batched reduction; terms with X or
+    // Y factors per instance (pair reads on its state view)
+    std::vector<std::vector<qs_pauli>> zt(b->n_inst), xt(b->n_inst);
+    std::vector<const qs_pauli*> zp(b->n_inst);
+    std::vector<size_t> zn(b->n_inst);
+    for (size_t i = 0; i < b->n_inst; ++i) {
+      if (n_terms[i] && !obs[i]) fail(QS_EINVAL, "NULL observable");
+      for (size_t t = 0; t < n_terms[i]; ++t) (obs[i][t].x_mask ? xt[i] : zt[i]).push_back(obs[i][t]);
+      zp[i] = zt[i].data();
+      zn[i] = zt[i].size();
+    }
+    const qs_status st = qs_batch_expect_diag(b, zp.data(), zn.data(), out);
+    if (st != QS_OK) return st;
+    for (size_t i = 0; i < b->n_inst; ++i) {
+      if (xt[i].empty()) continue;
+      const std::vector<double> v = state_expect(*b->views[i], xt[i].data(), xt[i].size());
+      for (double x : v) out[i] += x;
+    }
     return QS_OK;
   } catch (const Error& e) {
     g_last_error = e.msg;

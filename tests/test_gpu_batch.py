@@ -94,3 +94,26 @@ def test_batch_rejects_permutation_layers(qs):
     with pytest.raises(qs.QsError) as e:
         qs.Batch([p])
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_expect_general_pauli_sums(qs, dtype):
+    """Mixed observables per instance (the XXZ chain, X and Y fields, the cut
+    counts): the batched Z part plus per-instance X / Y terms against the
+    oracle's expectation of each instance's state."""
+    insts, plans, B = qaoa_batch(qs, 6, 11, 2, (8, 10, 12), dtype)
+    B.run()
+    obs = []
+    for k, inst in enumerate(insts):
+        terms = W.xxz_terms(inst.n, 0.3 + 0.1 * k) + W.maxcut_terms(inst.edges)
+        terms += [W.pauli(0.2 * (q + 1), {q: "Y"}) for q in range(inst.n)] + [(0.7, 0, 0)]
+        obs.append(terms)
+    got = B.expect(obs)
+    tol = 1e-5 if dtype == "c64" else 1e-11
+    for k, inst in enumerate(insts):
+        psi = B.state(k).download().astype(np.complex128)
+        ref = sv.expect(psi, inst.n, obs[k])
+        assert abs(got[k] - ref) <= tol * max(1.0, abs(ref)), (k, got[k], ref)
+    # Z-only observables give the same value as the diagonal entry point
+    zobs = [W.maxcut_terms(i.edges) for i in insts]
+    assert np.allclose(B.expect(zobs), B.expect_diag(zobs), rtol=0, atol=1e-12)
