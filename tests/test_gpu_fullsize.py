@@ -151,3 +151,35 @@ def test_tfim25_strang_against_stored_oracle_run(qs, dtype):
     assert np.max(np.abs(zz - np.array(gold["zz"]))) <= obs_tol
     assert np.max(np.abs(z)) <= obs_tol
     assert abs(qs.norm2(st) - 1.0) <= (1e-5 if dtype == "c64" else 1e-12)
+
+
+def test_max_qubits_32_benchmark_shape(qs):
+    """The largest state the library takes (32 qubits, 32 GiB complex64 plus an
+    equal gather buffer): QFT -> Walsh -> 60-gate X/CNOT/SWAP block on a sparse
+    input, sampled outputs against the closed form, the norm fused into the
+    gather, and the block alone on index tags bit for bit."""
+    import torch
+    n = 32
+    perm = W.random_perm_block(n, 60, 33)
+    stream = W.qft_stream(n) + W.wht_stream(n) + perm
+    plan = qs.Plan(n, stream)
+    assert [L["kind"] for L in plan.describe()["layers"]][-1] == "gf2"
+    st, idx, c = sparse_on_device(qs, n, "c64", seed=9)
+    nrm = qs.apply_norm2(st, plan)
+    assert abs(nrm - float(np.vdot(c, c).real)) <= 1e-5
+    ys = sample_indices(n, 23, 4096)
+    got = qs.amplitudes(st, ys).astype(np.complex128)
+    ref = closed.qft_wht_sparse(n, idx, c, closed.perm_source(n, perm, ys))
+    assert rel_err(got, ref) <= REL["c64"], rel_err(got, ref)
+    # index tags through the block alone
+    t = st.tensor()
+    chunk = 1 << 26
+    for s in range(0, 1 << n, chunk):
+        i = torch.arange(s, s + chunk, dtype=torch.int64, device="cuda")
+        t[s:s + chunk] = torch.complex((i & ((1 << 24) - 1)).to(torch.float32), (i >> 24).to(torch.float32))
+    qs.apply(st, qs.Plan(n, perm))
+    ys = sample_indices(n, 29, 65536)
+    src = closed.perm_source(n, perm, ys)
+    want = ((src & np.uint64((1 << 24) - 1)).astype(np.float32)
+            + 1j * (src >> np.uint64(24)).astype(np.float32)).astype(np.complex64)
+    assert np.array_equal(qs.amplitudes(st, ys), want)
