@@ -202,3 +202,25 @@ def test_error_paths_do_not_touch_the_state(qs):
     with pytest.raises(qs.QsError):
         qs.apply(st, p)  # parameters not bound
     assert np.array_equal(st.download(), psi0.astype(np.complex64))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_empty_and_identity_plans(qs, dtype):
+    """Degenerate plans: no gates, only identities, a gate and its inverse
+    back to back; the state is returned unchanged (bit for bit where no
+    arithmetic runs) and the fused norm falls back to a reduction."""
+    n = 11
+    st, psi0 = start(qs, n, dtype, 21)
+    held = st.download().copy()
+    for stream in ([], [W.G("I", q) for q in range(n)]):
+        plan = qs.Plan(n, stream)
+        assert plan.num_layers() == 0
+        qs.apply(st, plan)
+        qs.apply(st, plan.inverse())
+        nrm = qs.apply_norm2(st, plan)
+        assert np.array_equal(st.download(), held)
+        h128 = held.astype(np.complex128)
+        assert abs(nrm - float(np.vdot(h128, h128).real)) < 1e-12
+    qs.apply(st, qs.Plan(n, [W.G("RX", 3, theta=0.4), W.G("RX", 3, theta=-0.4)]))
+    tol = INF64 if dtype == "c64" else INF128
+    assert metrics.infidelity(st.download(), held.astype(np.complex128)) <= tol
