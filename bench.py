@@ -463,6 +463,32 @@ def bench_xxz(qs, torch, reps=3):
     return out
 
 
+def bench_graphs(qs, torch, steps=40, reps=10):
+    """Launch cost at small sizes: the 40-step Strang TFIM applied eagerly (one
+    launch per layer) and as one recorded HIP graph, complex64, for the fused
+    plan (tens of layers, each long enough to hide its launch) and for the
+    plain per-gate plan (2985 short layers at these sizes)."""
+    out = {}
+    for n in (10, 14, 18):
+        for mode in ("fused", "plain"):
+            plan = qs.Plan(n, W.tfim_strang_stream(n, 1.0, 0.8, 0.05, steps), mode=mode)
+            st = qs.State(n, "c64")
+            res = {"layers": plan.num_layers()}
+            for name, fn in (("eager", qs.apply), ("graph", qs.apply_graph)):
+                fn(st, plan)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn(st, plan)
+                torch.cuda.synchronize()
+                res[f"ms_{name}"] = round(1e3 * (time.perf_counter() - t0) / reps, 4)
+            res["speedup_graph_vs_eager"] = round(res["ms_eager"] / res["ms_graph"], 2)
+            out[f"tfim_{n}q_{mode}"] = res
+            del st
+    torch.cuda.empty_cache()
+    return out
+
+
 SECTIONS = {
     "batched_qaoa": lambda qs, torch: bench_batched_qaoa(qs, torch),
     "adjoint": lambda qs, torch: bench_adjoint(qs, torch),
@@ -471,6 +497,7 @@ SECTIONS = {
     "layers_30q": lambda qs, torch: bench_layers(qs, torch),
     "diag_families_25q": lambda qs, torch: bench_families(qs, torch),
     "xxz_families": lambda qs, torch: bench_xxz(qs, torch),
+    "graphs_small_n": lambda qs, torch: bench_graphs(qs, torch),
 }
 
 
@@ -600,6 +627,8 @@ def main():
         out["diag_families_25q"] = bench_families(qs, torch)
         log("Pauli-pair Trotter families and decomposed streams: 24-25 qubits")
         out["xxz_families"] = bench_xxz(qs, torch)
+        log("whole-plan graphs against eager launches: TFIM at 10-18 qubits")
+        out["graphs_small_n"] = bench_graphs(qs, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

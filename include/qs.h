@@ -200,6 +200,14 @@ qs_status qs_plan_inverse(const qs_plan* p, qs_plan** out);
 /* Apply layers [first, first + count) of a plan to a state (asynchronous, on
  * the state's stream).  count = (size_t)-1 applies through the last layer. */
 qs_status qs_apply_layer(qs_state* s, const qs_plan* p, size_t first, size_t count);
+/* Apply every layer of a plan through one HIP graph launch (asynchronous, on
+ * the state's stream).  The plan's layer sequence is recorded as a graph on
+ * the first call for this state, plan and parameter values (and for the
+ * buffer the state currently starts from), then replayed: for small states
+ * the per-layer launch cost disappears.  Up to 8 graphs are kept per state
+ * (freed with it); new parameters (qs_plan_set_params) record a new graph.
+ * Plans containing plain gates on 3 or more qubits run as qs_apply_layer. */
+qs_status qs_apply_graph(qs_state* s, const qs_plan* p);
 /* Apply every layer of a plan, then write ||psi||^2 of the result (FP64) to
  * *norm2 (host; the call waits for the device).  When the plan ends in a
  * tile pass or a GF(2) gather, that kernel sums |psi|^2 over the amplitudes

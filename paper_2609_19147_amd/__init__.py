@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib
 from ._lib import QsError, QsGate, QsPauli, QsPlanOpts, check, lib
 
-__all__ = ["State", "StateView", "Batch", "Plan", "apply", "apply_norm2", "apply_gates", "expect", "norm2", "overlap", "infidelity",
+__all__ = ["State", "StateView", "Batch", "Plan", "apply", "apply_graph", "apply_norm2", "apply_gates", "expect", "norm2", "overlap", "infidelity",
            "amplitudes", "to_c_gates", "to_c_terms", "profile", "QsError", "version", "adjoint_grad",
            "energy_function"]
 
@@ -294,6 +294,12 @@ def expect(state: State, terms, per_term: bool = False):
     tot = C.c_double()
     check(lib().qs_expect(state.h, arr, len(terms), out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(tot)))
     return (tot.value, out) if per_term else tot.value
+
+
+def apply_graph(state: State, plan: Plan) -> None:
+    """Apply the whole plan as one recorded HIP graph (recorded on first use
+    for this state, plan and parameter values; replayed afterwards)."""
+    check(lib().qs_apply_graph(state.h, plan.h))
 
 
 def apply_norm2(state: State, plan: Plan) -> float:

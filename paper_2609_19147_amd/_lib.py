@@ -67,6 +67,7 @@ _SIGS = {
     "qs_plan_inverse": ([P, C.POINTER(P)], C.c_int),
     "qs_apply_layer": ([P, P, SZ, SZ], C.c_int),
     "qs_apply_norm2": ([P, P, C.POINTER(C.c_double)], C.c_int),
+    "qs_apply_graph": ([P, P], C.c_int),
     "qs_apply_gates": ([P, C.POINTER(QsGate), SZ, C.POINTER(C.c_double), SZ], C.c_int),
     "qs_expect": ([P, C.POINTER(QsPauli), SZ, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "qs_norm2": ([P, C.POINTER(C.c_double)], C.c_int),

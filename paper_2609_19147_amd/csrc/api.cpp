@@ -192,6 +192,7 @@ qs_state::~qs_state() {
   if (red_partials) hipFree(red_partials);
   if (red_out) hipFree(red_out);
   if (norm_part) hipFree(norm_part);
+  free_graphs(*this);
   if (matbuf) hipFree(matbuf);
 }
 
@@ -380,6 +381,16 @@ extern "C" qs_status qs_apply_layer(qs_state* s, const qs_plan* p, size_t first,
     if (first > L) fail(QS_EINVAL, "first layer out of range");
     size_t last = (count == (size_t)-1 || count > L - first) ? L : first + count;
     apply_layers(*s, const_cast<qs_plan&>(*p), first, last);
+  });
+}
+
+extern "C" qs_status qs_apply_graph(qs_state* s, const qs_plan* p) {
+  return guarded([&] {
+    check_state(s);
+    if (!p) fail(QS_EINVAL, "plan is NULL");
+    if (p->ir.n != s->n) fail(QS_EINVAL, "plan and state qubit counts differ");
+    if (!p->bound) fail(QS_EINVAL, "plan parameters are not bound");
+    apply_graph(*s, const_cast<qs_plan&>(*p));
   });
 }
 

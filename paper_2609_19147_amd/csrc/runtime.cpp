@@ -2,6 +2,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -192,6 +193,7 @@ qs_plan& qs_plan::inverse() {
   if (inv_version != version) {
     inv->params = params;
     inv->bound = bound;
+    inv->version += 1;
     inv->refresh_device();
     inv_version = version;
   }
@@ -362,6 +364,86 @@ void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last) {
 void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params, bool inverse) {
   if (s.dtype == QS_C64) plain_t<float>(s, g, params, inverse);
   else plain_t<double>(s, g, params, inverse);
+}
+
+void prof_suspend(bool on);
+
+uint64_t new_plan_uid() {
+  static std::atomic<uint64_t> next{1};
+  return next.fetch_add(1);
+}
+
+void free_graphs(qs_state& s) {
+  for (auto& e : s.graphs)
+    if (e.exec) hipGraphExecDestroy(e.exec);
+  s.graphs.clear();
+  if (s.capture_stream) hipStreamDestroy(s.capture_stream);
+  s.capture_stream = nullptr;
+}
+
+void apply_graph(qs_state& s, qs_plan& p) {
+  const PlanIR& P = p.ir;
+  bool gather = false;
+  for (const LayerIR& L : P.layers) {
+    if (L.kind == L_PLAIN && P.gates[L.index].bits.size() > 2) {
+      apply_layers(s, p, 0, P.layers.size());  // its matrix is staged from the host per call
+      return;
+    }
+    gather = gather || L.kind == L_GF2;
+  }
+  if (P.layers.empty()) return;
+  if (gather) s.ensure_other();
+  p.device_for(s.dtype);
+  PlanGraphEntry* hit = nullptr;
+  for (auto& e : s.graphs)
+    if (e.plan_uid == p.uid && e.version == p.version && e.cur0 == s.cur) hit = &e;
+  if (!hit) {
+    // record on a private stream (the state's stream may be the null stream,
+    // which cannot capture; nothing runs during capture), then launch on the
+    // state's stream; keep at most 8 graphs per state
+    if (!s.capture_stream)
+      check_hip(hipStreamCreateWithFlags(&s.capture_stream, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    const int cur0 = s.cur;
+    const hipStream_t user = s.stream;
+    hipGraph_t g = nullptr;
+    prof_suspend(true);
+    s.stream = s.capture_stream;
+    check_hip(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      apply_layers(s, p, 0, P.layers.size());
+    } catch (...) {
+      hipGraph_t gg = nullptr;
+      hipStreamEndCapture(s.stream, &gg);
+      if (gg) hipGraphDestroy(gg);
+      s.stream = user;
+      prof_suspend(false);
+      s.cur = cur0;
+      throw;
+    }
+    const hipError_t ec = hipStreamEndCapture(s.stream, &g);
+    s.stream = user;
+    prof_suspend(false);
+    PlanGraphEntry e;
+    e.plan_uid = p.uid;
+    e.version = p.version;
+    e.cur0 = cur0;
+    e.cur1 = s.cur;
+    s.cur = cur0;
+    check_hip(ec, "hipStreamEndCapture");
+    const hipError_t ei = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    check_hip(ei, "hipGraphInstantiate");
+    if (s.graphs.size() >= 8) {
+      hipGraphExecDestroy(s.graphs.front().exec);
+      s.graphs.erase(s.graphs.begin());
+    }
+    s.graphs.push_back(e);
+    hit = &s.graphs.back();
+  }
+  prof_begin("plan_graph", s.stream);
+  check_hip(hipGraphLaunch(hit->exec, s.stream), "hipGraphLaunch");
+  prof_end(s.stream);
+  s.cur = hit->cur1;
 }
 
 double apply_norm2(qs_state& s, qs_plan& p) {

@@ -11,6 +11,16 @@
 #include "planner.h"
 #include "qs.h"
 
+// A plan's whole layer sequence recorded as a HIP graph for one state
+// (qs_apply_graph): valid for the plan's parameter version and the buffer the
+// state starts from (gathers flip between the two buffers).
+struct PlanGraphEntry {
+  uint64_t plan_uid = 0;
+  uint64_t version = 0;
+  int cur0 = 0, cur1 = 0;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct qs_state {
   int n = 0;
   qs_dtype dtype = QS_C64;
@@ -24,6 +34,8 @@ struct qs_state {
   double* red_out = nullptr;
   double* norm_part = nullptr;  // per-tile norm partials of a fused apply-and-norm
   uint64_t norm_cap = 0;
+  std::vector<PlanGraphEntry> graphs;  // recorded plans, most recent last
+  hipStream_t capture_stream = nullptr;  // private stream graphs are recorded on
   void* matbuf = nullptr;  // device staging for dense plain gates
 
   size_t amp_bytes() const;
@@ -59,6 +71,10 @@ extern thread_local std::string g_last_error;
 
 }  // namespace qs
 
+namespace qs {
+uint64_t new_plan_uid();
+}
+
 struct qs_plan {
   qs::PlanIR ir;
   std::vector<double> params;
@@ -66,6 +82,7 @@ struct qs_plan {
   qs::PlanDev dev[2];
   std::vector<qs::Gf2Args> gf2;  // host-side kernel arguments per GF(2) layer
   uint64_t version = 0;          // bumped whenever the parameters change
+  uint64_t uid = qs::new_plan_uid();  // unique per plan object (keys recorded graphs)
   qs_plan* inv = nullptr;        // inverse plan (adjoint sweeps), built on demand
   uint64_t inv_version = 0;
 
@@ -82,6 +99,12 @@ void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last);
 // layer is a tile pass or a gather, its kernel sums |psi|^2 over what it
 // writes (no separate read of the state); otherwise a reduction follows.
 double apply_norm2(qs_state& s, qs_plan& p);
+// Apply every layer through a HIP graph recorded on first use for this state,
+// plan and parameter version, replayed afterwards (one launch for the whole
+// plan).  Plans with host-staged gates (plain gates on 3 or more qubits) run
+// eagerly instead.
+void apply_graph(qs_state& s, qs_plan& p);
+void free_graphs(qs_state& s);
 void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params, bool inverse = false);
 double state_norm2(qs_state& s);
 std::complex<double> state_overlap(qs_state& a, qs_state& b);
