@@ -20,9 +20,10 @@ import numpy as np
 
 from . import _lib
 from ._lib import QsError, QsGate, QsPauli, QsPlanOpts, check, lib
+from . import qasm  # noqa: E402  (OpenQASM 2.0 import; host only)
 
 __all__ = ["State", "StateView", "Batch", "Plan", "apply", "apply_graph", "apply_norm2", "apply_gates", "expect", "norm2", "overlap", "infidelity",
-           "amplitudes", "to_c_gates", "to_c_terms", "profile", "QsError", "version", "adjoint_grad",
+           "amplitudes", "qasm", "to_c_gates", "to_c_terms", "profile", "QsError", "version", "adjoint_grad",
            "energy_function"]
 
 
