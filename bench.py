@@ -489,6 +489,26 @@ def bench_graphs(qs, torch, steps=40, reps=10):
     return out
 
 
+def manifest(qs, torch):
+    """Run manifest: library, runtime and device identification, seeds."""
+    import platform
+    p = torch.cuda.get_device_properties(0)
+    rev = None
+    head = os.path.join(ROOT, ".git", "HEAD")
+    if os.path.exists(head):
+        ref = open(head).read().strip()
+        if ref.startswith("ref: "):
+            f = os.path.join(ROOT, ".git", ref[5:])
+            rev = open(f).read().strip() if os.path.exists(f) else None
+        else:
+            rev = ref
+    return {"library": qs.version(), "git_rev": rev, "torch": torch.__version__, "hip": torch.version.hip,
+            "device": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "device_memory_GiB": round(p.total_memory / 2 ** 30, 1), "host": platform.node(),
+            "host_cpus": os.cpu_count(), "state_seed": STATE_SEED, "block_seed": BLOCK_SEED,
+            "timing": "HIP events on the library stream + host wall clock around K steps, synchronised"}
+
+
 SECTIONS = {
     "batched_qaoa": lambda qs, torch: bench_batched_qaoa(qs, torch),
     "adjoint": lambda qs, torch: bench_adjoint(qs, torch),
@@ -609,6 +629,7 @@ def main():
         "plan_ms": round(1e3 * t_plan, 2),
         "roofline": roof,
         "kernels": kernels,
+        "manifest": manifest(qs, torch),
     }
     if not args.no_extra:
         del st
