@@ -162,11 +162,90 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
   }
 }
 
+// complex128 k = 6: the 64 x 64 matrix (64 KB) does not fit the register
+// file, so it is staged in LDS next to the tile and each wave reads its A
+// fragments from there; otherwise as dense_kernel (f64 MFMA, D[i][j] in lane
+// j + 16 (i % 4), register i / 4).
+__global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<double>* __restrict__ psi,
+                                                                      const cplx<double>* U_, DenseGeom G) {
+  constexpr int K = 64, RT = K / 16, KS = K / 4;
+  typedef f64x4 acc_t;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t M = 1u << G.m;
+  cplx<double>* T = reinterpret_cast<cplx<double>*>(smem_raw);
+  cplx<double>* Us = T + dense_lds_off(M);
+  uint32_t* hi_tab = reinterpret_cast<uint32_t*>(Us + K * K);
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t li = lane & 15u, lk = lane >> 4;
+  for (uint32_t h = threadIdx.x; h < (1u << G.n_hi); h += kDenseThreads) {
+    uint32_t off = 0;
+    for (uint32_t j = 0; j < G.n_hi; ++j)
+      if ((h >> j) & 1u) off |= 1u << G.hi_bit[j];
+    hi_tab[h] = off;
+  }
+  for (uint32_t e = threadIdx.x; e < (uint32_t)(K * K); e += kDenseThreads) Us[e] = U_[e];
+  const uint32_t colmask = (M - 1u) & ~G.rowmask;
+  uint32_t brow[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) brow[ks] = deposit(4u * ks + lk, G.rowmask);
+  uint32_t drow[RT][4];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) drow[rt][v] = deposit(16u * rt + lk + 4u * v, G.rowmask);
+  const uint32_t ncb = (1u << G.c) >> 4;
+  const uint32_t Lmask = (1u << G.L) - 1u;
+  __syncthreads();
+
+  for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
+    uint32_t base = 0;
+    for (uint32_t j = 0; j < G.n_free; ++j)
+      if ((t >> j) & 1u) base |= 1u << G.free_bit[j];
+    for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
+      const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
+      *reinterpret_cast<cplx2<double>*>(T + dense_lds_off(p)) = ld_nt(reinterpret_cast<const cplx2<double>*>(psi + g));
+    }
+    __syncthreads();
+    for (uint32_t cb = wave; cb < ncb; cb += kDenseThreads / 64) {
+      const uint32_t colp = deposit(16u * cb + li, colmask);
+      acc_t yr[RT], yi[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        yr[rt] = acc_t{0, 0, 0, 0};
+        yi[rt] = acc_t{0, 0, 0, 0};
+      }
+#pragma unroll 4
+      for (int ks = 0; ks < KS; ++ks) {
+        const cplx<double> x = T[dense_lds_off(brow[ks] | colp)];
+        const double nxi = -x.im;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const cplx<double> u = Us[(16u * rt + li) * K + 4u * ks + lk];
+          yr[rt] = mfma16(u.re, x.re, yr[rt]);
+          yr[rt] = mfma16(u.im, nxi, yr[rt]);
+          yi[rt] = mfma16(u.re, x.im, yi[rt]);
+          yi[rt] = mfma16(u.im, x.re, yi[rt]);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[dense_lds_off(drow[rt][v] | colp)] = cplx<double>{yr[rt][v], yi[rt][v]};
+    }
+    __syncthreads();
+    for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
+      const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
+      st_nt(reinterpret_cast<cplx2<double>*>(psi + g), *reinterpret_cast<const cplx2<double>*>(T + dense_lds_off(p)));
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 bool dense_supported(int n, int k, bool complex128) {
-  if (k < 4 || k > 6 || n - k < 4 || n > 32) return false;
-  return !(complex128 && k == 6);  // 128 double-precision U fragments exceed the register file
+  (void)complex128;  // complex128 k = 6 stages its matrix in LDS
+  return k >= 4 && k <= 6 && n - k >= 4 && n <= 32;
 }
 
 DenseGeom dense_geometry(int n, int k, const int* bits_sorted) {
@@ -214,6 +293,15 @@ bool launch_dense(cplx<R>* psi, int n, int k, const int* bits_sorted, const cplx
     QS_LAUNCH("dense_k5", s, (dense_kernel<R, 32>), dim3(grid), dim3(kDenseThreads), lds, s, psi, U_dev, G);
   } else if constexpr (sizeof(R) == 4) {
     QS_LAUNCH("dense_k6", s, (dense_kernel<R, 64>), dim3(grid), dim3(kDenseThreads), lds, s, psi, U_dev, G);
+  } else {
+    // the tile, the 64 x 64 complex128 matrix and the offset table: ~132 KB
+    const size_t lds6 = lds + sizeof(cplx<double>) * 64 * 64;
+    static bool attr_set = false;
+    if (!attr_set) {
+      allow_dynamic_lds((const void*)dense_kernel_k6_c128, (int)lds6, "dense_k6");
+      attr_set = true;
+    }
+    QS_LAUNCH("dense_k6", s, dense_kernel_k6_c128, dim3(grid), dim3(kDenseThreads), lds6, s, psi, U_dev, G);
   }
   return true;
 }

@@ -2,8 +2,8 @@
 
 Wire sets cover targets among the lowest state bits (the tile's column bits
 then start above them), among the highest bits, interleaved, and random;
-sizes span many tiles.  complex128 six-qubit blocks take the per-gate k-qubit
-kernel and are checked the same way.  Bars as in the other parity tests.
+sizes span many tiles.  complex128 six-qubit blocks (matrix staged in LDS) are
+checked the same way.  Bars as in the other parity tests.
 """
 import math
 
