@@ -1436,8 +1436,9 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
 
 }  // namespace
 
-PlanIR build_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOptions& opt,
-                  int tile_bits, int low_bits) {
+// A structured plan of a gate list (no window fusion).
+static PlanIR structured_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOptions& opt,
+                              int tile_bits, int low_bits, int windows) {
   PlanIR P;
   P.n = n;
   P.n_params = n_params;
@@ -1445,36 +1446,72 @@ PlanIR build_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOp
   P.gates = std::move(gates);
   P.tile_bits = tile_bits;
   P.low_bits = low_bits;
-  if (opt.mode == QS_PLAIN || n < kRoundBits) {
-    for (size_t i = 0; i < P.gates.size(); ++i) P.layers.push_back({L_PLAIN, (int32_t)i});
-    return P;
-  }
+  P.windows = windows;
   Builder B(P, tile_bits, low_bits);
   B.run();
   for (auto& T : P.passes) finalize_pass(P, T);
+  return P;
+}
+
+PlanIR build_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOptions& opt,
+                  int tile_bits, int low_bits) {
+  if (opt.mode == QS_PLAIN || n < kRoundBits) {
+    PlanIR P;
+    P.n = n;
+    P.n_params = n_params;
+    P.opt = opt;
+    P.gates = std::move(gates);
+    P.tile_bits = tile_bits;
+    P.low_bits = low_bits;
+    for (size_t i = 0; i < P.gates.size(); ++i) P.layers.push_back({L_PLAIN, (int32_t)i});
+    return P;
+  }
+  PlanIR best = structured_plan(n, gates, n_params, opt, tile_bits, low_bits, 0);
   // Generic matrix fusion of decomposed blocks (Section "Limitations and
-  // Future Work"): the same stream with dense windows, kept when it needs
-  // fewer passes than the structured plan.
+  // Future Work"): candidates with dense windows over the whole stream and
+  // chunk by chunk (each chunk of consecutive gates keeps its windows only
+  // when they need fewer passes there), kept when cheaper than the
+  // structured plan.
   const int kw = std::min(std::min(opt.window_k, opt.dense_k_max), std::min(n - 4, QS_MAX_GATE_WIRES));
-  if (kw >= 4) {
-    std::vector<NGate> fused;
-    const int formed = fuse_windows(n, P.gates, kw, fused);
-    if (formed > 0) {
-      PlanIR Q;
-      Q.n = n;
-      Q.n_params = n_params;
-      Q.opt = opt;
-      Q.gates = std::move(fused);
-      Q.tile_bits = tile_bits;
-      Q.low_bits = low_bits;
-      Q.windows = formed;
-      Builder BQ(Q, tile_bits, low_bits);
-      BQ.run();
-      for (auto& T : Q.passes) finalize_pass(Q, T);
-      if (plan_cost(Q) < plan_cost(P)) return Q;
+  if (kw < 4) return best;
+  double best_cost = plan_cost(best);
+  std::vector<NGate> fused;
+  const int formed = fuse_windows(n, gates, kw, fused);
+  if (formed == 0) return best;
+  PlanIR W = structured_plan(n, std::move(fused), n_params, opt, tile_bits, low_bits, formed);
+  const double w_cost = plan_cost(W);
+  constexpr size_t kChunk = 96;
+  if (gates.size() > kChunk) {
+    std::vector<NGate> mixed;
+    int mixed_windows = 0;
+    bool any_struct = false, any_win = false;
+    for (size_t c0 = 0; c0 < gates.size(); c0 += kChunk) {
+      std::vector<NGate> chunk(gates.begin() + c0, gates.begin() + std::min(gates.size(), c0 + kChunk));
+      std::vector<NGate> fc;
+      const int f = fuse_windows(n, chunk, kw, fc);
+      bool use_win = false;
+      if (f > 0) {
+        const double cs = plan_cost(structured_plan(n, chunk, n_params, opt, tile_bits, low_bits, 0));
+        const double cw = plan_cost(structured_plan(n, fc, n_params, opt, tile_bits, low_bits, f));
+        use_win = cw < cs;
+      }
+      if (use_win) {
+        mixed.insert(mixed.end(), fc.begin(), fc.end());
+        mixed_windows += f;
+        any_win = true;
+      } else {
+        mixed.insert(mixed.end(), chunk.begin(), chunk.end());
+        any_struct = true;
+      }
+    }
+    if (any_win && any_struct) {
+      PlanIR M = structured_plan(n, std::move(mixed), n_params, opt, tile_bits, low_bits, mixed_windows);
+      const double m_cost = plan_cost(M);
+      if (m_cost < best_cost && m_cost < w_cost) return M;
     }
   }
-  return P;
+  if (w_cost < best_cost) return W;
+  return best;
 }
 
 // ---------------------------------------------------------------- numerics

@@ -390,3 +390,19 @@ def test_trivial_qft_stage_and_hadamard_cancel(n):
     blocked = W.qft_stream(n) + [W.G("T", n - 1)] + W.wht_stream(n)
     d2 = check_plan(n, blocked, tol=1e-11)
     assert sum(1 for L in d2["layers"] if L["kind"] == "tile" for op in L["ops"]) > 2 * n - 2
+
+
+def test_mixed_streams_choose_windows_per_chunk():
+    """A structured transform, a decomposed ladder and a structured transform
+    again: the ladder's chunks take dense windows, the transforms keep their
+    tile passes, and the whole plan is exact and shorter than the structured one."""
+    n = 12
+    stream = W.qft_stream(n) + W.ladder_stream(6, 1.0, 0.5, 0.05, 2) + W.wht_stream(n) + W.qft_stream(n)
+    d = check_plan(n, stream, tol=1e-11)
+    assert d["windows"] > 0
+    k = kinds(d)
+    assert "dense" in k and "tile" in k
+    d0 = qs.Plan(n, stream, window_k=-1).describe()
+    assert len(d["layers"]) < len(d0["layers"])
+    # the structured head stays a tile pass: no window swallows the transform
+    assert k[0] == "tile"
