@@ -8,6 +8,7 @@ namespace qs {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr unsigned kGf2Batch = 2;  // cosets whose loads a gather workgroup issues together
 constexpr int kDiagPairsPerThread = 8;
 constexpr int kDiagAngleGroups = 4;  // from this many groups: total angle, one sincos per amplitude
 
@@ -110,7 +111,7 @@ __device__ __forceinline__ void gf2_coset_rep(const Gf2Args& A, uint32_t c, uint
     if ((y0 >> j) & 1u) x0 ^= A.acol[j];
 }
 
-template <class R>
+template <class R, int kB>
 __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                        Gf2Args A, double* __restrict__ norm_part, uint32_t per) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -131,44 +132,62 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
   const uint32_t lomask = nlo - 1u;
   if (D == kThreads * 4) {
     // full tiles, `per` consecutive cosets per workgroup (the tables above are
-    // loaded once): two 16-byte loads in flight per thread, then two stores
-    for (uint32_t q = 0; q < per; ++q) {
-      const uint32_t coset = blockIdx.x * per + q;
-      uint32_t y0, x0;
-      gf2_coset_rep(A, coset, y0, x0);
+    // loaded once), kB of them at a time in kB tiles of LDS: 2 kB 16-byte
+    // loads in flight per thread, then 2 kB stores
+    for (uint32_t q = 0; q < per; q += kB) {
+      uint32_t y0[kB];
+      cplx2<R> w[kB][2];
+      uint32_t xa[kB][2];
+#pragma unroll
+      for (int b = 0; b < kB; ++b) {
+        uint32_t x0;
+        gf2_coset_rep(A, blockIdx.x * per + q + b, y0[b], x0);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t s = 2u * (threadIdx.x + kThreads * k);
+          xa[b][k] = x0 ^ (s & lomask) ^ au[s >> A.c];
+          w[b][k] = ld_nt(reinterpret_cast<const cplx2<R>*>(in + (xa[b][k] & ~1u)));
+        }
+      }
       // 16-byte accesses: source and destination runs are aligned blocks of
       // 2^c elements (c >= 1) XOR-permuted, so elements 2i, 2i + 1 of a run
       // share one aligned pair; `f` says whether the pair is swapped
-      cplx<R> v[4];
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const uint32_t s = 2u * (threadIdx.x + kThreads * k);
-        const uint32_t slo = s & lomask, shi = s >> A.c;
-        const uint32_t xa = x0 ^ slo ^ au[shi];
-        const cplx2<R> w = ld_nt(reinterpret_cast<const cplx2<R>*>(in + (xa & ~1u)));
-        const uint32_t f = xa & 1u;  // w.a holds source coordinate slo ^ f
-        const uint32_t ta = tl[slo ^ f] ^ th[shi], tb = tl[slo ^ f ^ 1u] ^ th[shi];
-        T[ta ^ hx[ta >> A.c]] = w.a;
-        T[tb ^ hx[tb >> A.c]] = w.b;
+      for (int b = 0; b < kB; ++b) {
+        cplx<R>* Tb = T + b * D;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t s = 2u * (threadIdx.x + kThreads * k);
+          const uint32_t slo = s & lomask, shi = s >> A.c;
+          const uint32_t f = xa[b][k] & 1u;  // w.a holds source coordinate slo ^ f
+          const uint32_t ta = tl[slo ^ f] ^ th[shi], tb = tl[slo ^ f ^ 1u] ^ th[shi];
+          Tb[ta ^ hx[ta >> A.c]] = w[b][k].a;
+          Tb[tb ^ hx[tb >> A.c]] = w[b][k].b;
+        }
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const uint32_t tt = 2u * (threadIdx.x + kThreads * k);
-        const uint32_t ya = y0 ^ (tt & lomask) ^ vh[tt >> A.c];
-        const uint32_t f = ya & 1u;  // the even destination takes tile coordinate tt ^ f
-        const uint32_t te = tt ^ f, to = tt ^ f ^ 1u;
-        v[2 * k] = T[te ^ hx[te >> A.c]];
-        v[2 * k + 1] = T[to ^ hx[to >> A.c]];
-        st_nt(reinterpret_cast<cplx2<R>*>(out + (ya & ~1u)), cplx2<R>{v[2 * k], v[2 * k + 1]});
+      for (int b = 0; b < kB; ++b) {
+        const cplx<R>* Tb = T + b * D;
+        cplx<R> v[4];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t tt = 2u * (threadIdx.x + kThreads * k);
+          const uint32_t ya = y0[b] ^ (tt & lomask) ^ vh[tt >> A.c];
+          const uint32_t f = ya & 1u;  // the even destination takes tile coordinate tt ^ f
+          const uint32_t te = tt ^ f, to = tt ^ f ^ 1u;
+          v[2 * k] = Tb[te ^ hx[te >> A.c]];
+          v[2 * k + 1] = Tb[to ^ hx[to >> A.c]];
+          st_nt(reinterpret_cast<cplx2<R>*>(out + (ya & ~1u)), cplx2<R>{v[2 * k], v[2 * k + 1]});
+        }
+        if (norm_part != nullptr) {
+          // the layer's norm, fused: each wavefront's FP64 sum of |psi|^2 over
+          // what it stored (no workgroup barrier)
+          const double tn = wave_sum_fixed(abs2_d(v[0]) + abs2_d(v[1]) + abs2_d(v[2]) + abs2_d(v[3]));
+          if ((threadIdx.x & 63u) == 0) norm_part[4 * (size_t)(blockIdx.x * per + q + b) + (threadIdx.x >> 6)] = tn;
+        }
       }
-      if (norm_part != nullptr) {
-        // the layer's norm, fused: each wavefront's FP64 sum of |psi|^2 over
-        // what it stored (no workgroup barrier)
-        const double tn = wave_sum_fixed(abs2_d(v[0]) + abs2_d(v[1]) + abs2_d(v[2]) + abs2_d(v[3]));
-        if ((threadIdx.x & 63u) == 0) norm_part[4 * (size_t)coset + (threadIdx.x >> 6)] = tn;
-      }
-      __syncthreads();  // the next coset rewrites the tile
+      __syncthreads();  // the next cosets rewrite the tiles
     }
     return;
   }
@@ -275,11 +294,17 @@ void launch_diag(cplx<R>* psi, int n, const DiagDev& D, hipStream_t s) {
 template <class R>
 void launch_gf2(const cplx<R>* in, cplx<R>* out, const Gf2Args& A, hipStream_t s, double* norm_part) {
   const unsigned n_cosets = 1u << (A.n - A.d);
-  const size_t lds = sizeof(cplx<R>) << A.d;
-  // full tiles: four cosets per workgroup once there are plenty of them
-  const unsigned per = ((1u << A.d) == kThreads * 4u && n_cosets >= 8192u) ? 4u : 1u;
-  QS_LAUNCH("gf2_gather", s, gf2_kernel<R>, dim3(n_cosets / per), dim3(kThreads), lds, s, in, out, A, norm_part,
-            per);
+  // full tiles: four cosets per workgroup once there are plenty of them, the
+  // loads of kGf2Batch of them issued together
+  const bool full = (1u << A.d) == kThreads * 4u;
+  const unsigned per = (full && n_cosets >= 8192u) ? 4u : 1u;
+  if (per % kGf2Batch == 0) {
+    QS_LAUNCH("gf2_gather", s, (gf2_kernel<R, kGf2Batch>), dim3(n_cosets / per), dim3(kThreads),
+              (sizeof(cplx<R>) << A.d) * kGf2Batch, s, in, out, A, norm_part, per);
+  } else {
+    QS_LAUNCH("gf2_gather", s, (gf2_kernel<R, 1>), dim3(n_cosets / per), dim3(kThreads), sizeof(cplx<R>) << A.d, s, in,
+              out, A, norm_part, per);
+  }
 }
 
 #define INST(R)                                                                              \
