@@ -132,14 +132,22 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
     bool tiled = false;
     if (FL.kind == L_TILE && bits.size() <= 32) {
       const TilePassIR& T = p.ir.passes[FL.index];
+      // the pass's tile bits, with the low run [0, L) cut to the requested low
+      // bits (at least 5: 256-byte runs, and a tile of at least 2^7): smaller
+      // tiles let several workgroups share a CU
+      int lo_needed = 0;
+      for (int b : bits)
+        if (b < T.L) lo_needed = std::max(lo_needed, b + 1);
+      int Lr = std::min(T.L, std::max(lo_needed, 5));
+      while (Lr < T.L && Lr + T.h < 7) ++Lr;
       RhoTileArgs A{};
-      A.L = (uint32_t)T.L;
+      A.L = (uint32_t)Lr;
       A.a = (uint32_t)T.a;
       A.h = (uint32_t)T.h;
-      A.m = (uint32_t)(T.L + T.h);
-      tiled = T.L >= 1 && rho_tile_fits(A.m, sizeof(R));
+      A.m = (uint32_t)(Lr + T.h);
+      tiled = Lr >= 1 && rho_tile_fits(A.m, sizeof(R));
       for (int b : bits) {
-        const int pos = b < T.L ? b : (b >= T.a && b < T.a + T.h ? T.L + b - T.a : -1);
+        const int pos = b < Lr ? b : (b >= T.a && b < T.a + T.h ? Lr + b - T.a : -1);
         if (pos < 0) tiled = false;
         else A.tbit[A.nbits++] = (uint32_t)pos;
       }

@@ -385,80 +385,243 @@ template void launch_diag_grad<double>(const cplx<double>*, const cplx<double>*,
 // ---- cross densities of several bits at once (adjoint sweep) ---------------
 namespace {
 
-constexpr int kRhoThreads = 1024;
-constexpr int kRhoWaves = kRhoThreads / 64;
+constexpr int kRhoMaxThreads = 512;
+constexpr int kRhoMaxWaves = kRhoMaxThreads / 64;
 
 __device__ __forceinline__ uint32_t rho_lds_off(uint32_t pos) { return pos + ((pos >> 5) << 1); }
 
-// One workgroup per coset of the tile bits [0, L) U [a, a + h): phi and lambda
-// tiles staged in LDS; then wave w takes the requested tile bits w, w + 16, ...
-// and, over all of the tile's pairs along its bit, the eight sums
-// rho_b[r][c] = sum conj(lam_r) phi_c.  Each lane sums its share of pairs in the
-// state's precision; the folds across the wave (fixed order) and across tiles
-// (compensated, rho_finalize) are FP64.
+inline uint32_t rho_threads(uint32_t m) {
+  const uint32_t t = (1u << m) >> 4;
+  return t < 64 ? 64 : (t > (uint32_t)kRhoMaxThreads ? (uint32_t)kRhoMaxThreads : t);
+}
+
+// Register bits of a chunk: 2^4 complex64 or 2^3 complex128 amplitudes of
+// each state per group.
 template <class R>
-__global__ void __launch_bounds__(kRhoThreads) rho_tile_kernel(const cplx<R>* __restrict__ phi,
-                                                               const cplx<R>* __restrict__ lam, RhoTileArgs A,
-                                                               double* __restrict__ partials) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const uint32_t M = 1u << A.m;
-  cplx<R>* P = reinterpret_cast<cplx<R>*>(smem_raw);
-  cplx<R>* Q = P + rho_lds_off(M);
-  const uint32_t coset = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t nlo = A.a - A.L, top = A.a + A.h;
-  const uint32_t base = ((coset & ((1u << nlo) - 1u)) << A.L) | (top >= 32 ? 0u : ((coset >> nlo) << top));
-  const uint32_t lmask = (1u << A.L) - 1u;
-  for (uint32_t pos = 2u * threadIdx.x; pos < M; pos += 2u * kRhoThreads) {
-    const uint32_t g = base | (pos & lmask) | ((pos >> A.L) << A.a);
-    *reinterpret_cast<cplx2<R>*>(P + rho_lds_off(pos)) = ld_nt(reinterpret_cast<const cplx2<R>*>(phi + g));
-    *reinterpret_cast<cplx2<R>*>(Q + rho_lds_off(pos)) = ld_nt(reinterpret_cast<const cplx2<R>*>(lam + g));
+constexpr int rho_chunk_bits() { return sizeof(R) == 4 ? 4 : 3; }
+
+// The sums of one chunk of up to kB requested tile bits.  Register index bit
+// k holds tile bit t[k] (the kReq requested bits first, then spare tile bits
+// that only enumerate amplitudes); a thread takes whole groups of 2^kB
+// amplitudes of both tiles into registers and adds, per requested bit, the
+// eight sums over the group's pairs along that bit.
+template <class R, int kReq>
+__device__ __forceinline__ void rho_chunk(const cplx<R>* P, const cplx<R>* Q, uint32_t M, const uint32_t* t,
+                                          double* out32) {
+  constexpr int kB = rho_chunk_bits<R>(), kN = 1 << kB;
+  static_assert(kReq >= 1 && kReq <= kB, "a chunk holds at most kB requested bits");
+  uint32_t ts[kB];
+#pragma unroll
+  for (int k = 0; k < kB; ++k) ts[k] = t[k];
+  // ascending, for inserting the zero bits of a group's base position
+#pragma unroll
+  for (int i = 1; i < kB; ++i)
+#pragma unroll
+    for (int j = kB - 1; j >= i; --j)
+      if (ts[j - 1] > ts[j]) {
+        const uint32_t x = ts[j - 1];
+        ts[j - 1] = ts[j];
+        ts[j] = x;
+      }
+  uint32_t loff[kN];
+#pragma unroll
+  for (int j = 0; j < kN; ++j) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int k = 0; k < kB; ++k)
+      if ((j >> k) & 1) o |= 1u << t[k];
+    loff[j] = rho_lds_off(o);
   }
-  __syncthreads();
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  for (uint32_t bi = wave; bi < A.nbits; bi += kRhoWaves) {
-    const uint32_t b = A.tbit[bi];
-    // a lane's sum over its <= 2^(m-7) pairs in the state's precision, the
-    // folds across lanes and tiles in FP64
-    R a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (uint32_t j = lane; j < M / 2; j += 64) {
-      const uint32_t p0 = insert0(j, b), p1 = p0 | (1u << b);
-      const cplx<R> f0 = P[rho_lds_off(p0)], f1 = P[rho_lds_off(p1)];
-      const cplx<R> l0 = Q[rho_lds_off(p0)], l1 = Q[rho_lds_off(p1)];
-      const R f0r = f0.re, f0i = f0.im, f1r = f1.re, f1i = f1.im;
-      const R l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
-      R* acc = a8;
-      acc[0] += l0r * f0r + l0i * f0i;
-      acc[1] += l0r * f0i - l0i * f0r;
-      acc[2] += l0r * f1r + l0i * f1i;
-      acc[3] += l0r * f1i - l0i * f1r;
-      acc[4] += l1r * f0r + l1i * f0i;
-      acc[5] += l1r * f0i - l1i * f0r;
-      acc[6] += l1r * f1r + l1i * f1i;
-      acc[7] += l1r * f1i - l1i * f1r;
+  R acc[kReq][8];
+#pragma unroll
+  for (int k = 0; k < kReq; ++k)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[k][v] = R(0);
+  for (uint32_t g = threadIdx.x; g < (M >> kB); g += blockDim.x) {
+    uint32_t gpos = g;
+#pragma unroll
+    for (int k = 0; k < kB; ++k) gpos = insert0(gpos, ts[k]);
+    const cplx<R>* Pg = P + rho_lds_off(gpos);
+    const cplx<R>* Qg = Q + rho_lds_off(gpos);
+    cplx<R> f[kN], l[kN];
+#pragma unroll
+    for (int j = 0; j < kN; ++j) {
+      f[j] = Pg[loff[j]];
+      l[j] = Qg[loff[j]];
     }
-    double acc[8];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      double x = a8[v];
+    for (int k = 0; k < kReq; ++k)
 #pragma unroll
-      for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
-      acc[v] = x;
+      for (int j = 0; j < kN; ++j) {
+        if ((j >> k) & 1) continue;
+        const int j1 = j | (1 << k);
+        const cplx<R> f0 = f[j], f1 = f[j1], l0 = l[j], l1 = l[j1];
+        acc[k][0] += l0.re * f0.re + l0.im * f0.im;
+        acc[k][1] += l0.re * f0.im - l0.im * f0.re;
+        acc[k][2] += l0.re * f1.re + l0.im * f1.im;
+        acc[k][3] += l0.re * f1.im - l0.im * f1.re;
+        acc[k][4] += l1.re * f0.re + l1.im * f0.im;
+        acc[k][5] += l1.re * f0.im - l1.im * f0.re;
+        acc[k][6] += l1.re * f1.re + l1.im * f1.im;
+        acc[k][7] += l1.re * f1.im - l1.im * f1.re;
+      }
+  }
+  // sums over the wavefront by recursive halving (fixed order): each exchange
+  // at lane distance d hands half of a lane's values to its partner, so the
+  // exchanges of one step are independent of each other
+  const uint32_t lane = threadIdx.x & 63u;
+  if constexpr (sizeof(R) == 4) {
+    // all 8 kReq values together (padded to 32): three steps in FP32 (sums
+    // of 8 lanes), then FP64; lane pair (2v, 2v + 1) ends with value v
+    float y[32];
+#pragma unroll
+    for (int v = 0; v < 32; ++v) y[v] = v < 8 * kReq ? acc[v >> 3][v & 7] : 0.0f;
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+      const int d = 32 >> st, half = 16 >> st;
+      const bool up = (lane & (uint32_t)d) != 0;
+#pragma unroll
+      for (int i = 0; i < half; ++i) {
+        const float send = up ? y[i] : y[i + half];
+        const float keep = up ? y[i + half] : y[i];
+        y[i] = keep + __shfl_xor(send, d, 64);
+      }
     }
-    if (lane < 8) {
-      double x = acc[0];
+    double x[4];
 #pragma unroll
-      for (int v = 1; v < 8; ++v) x = lane == (uint32_t)v ? acc[v] : x;
-      partials[((size_t)blockIdx.x * A.nbits + bi) * 8 + lane] = x;
+    for (int i = 0; i < 4; ++i) x[i] = (double)y[i];
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int d = 4 >> st, half = 2 >> st;
+      const bool up = (lane & (uint32_t)d) != 0;
+#pragma unroll
+      for (int i = 0; i < half; ++i) {
+        const double send = up ? x[i] : x[i + half];
+        const double keep = up ? x[i + half] : x[i];
+        x[i] = keep + __shfl_xor(send, d, 64);
+      }
+    }
+    x[0] += __shfl_xor(x[0], 1, 64);
+    if ((lane & 1u) == 0 && (lane >> 1) < 8u * kReq) out32[lane >> 1] = x[0];
+  } else {
+    // per bit in FP64: after three exchanges lane l holds value l >> 3 summed
+    // over the lanes that differ in bits 3..5, three more add the rest
+#pragma unroll
+    for (int k = 0; k < kReq; ++k) {
+      double x[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) x[v] = (double)acc[k][v];
+#pragma unroll
+      for (int st = 0; st < 3; ++st) {
+        const int d = 32 >> st, half = 4 >> st;
+        const bool up = (lane & (uint32_t)d) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+          const double send = up ? x[i] : x[i + half];
+          const double keep = up ? x[i + half] : x[i];
+          x[i] = keep + __shfl_xor(send, d, 64);
+        }
+      }
+#pragma unroll
+      for (int d = 4; d > 0; d >>= 1) x[0] += __shfl_xor(x[0], d, 64);
+      if ((lane & 7u) == 0) out32[8 * k + (lane >> 3)] = x[0];
     }
   }
 }
 
-// out[o] = sum over tiles t of partials[t * nv + o], compensated, fixed order.
+// One workgroup per coset of the tile bits [0, L) U [a, a + h): phi and lambda
+// tiles staged in LDS, then the requested tile bits in chunks of four
+// (complex64) or three (complex128), each
+// giving per bit the eight sums rho_b[r][c] = sum conj(lam_r) phi_c over the
+// tile's pairs along b.  Sums inside a thread run in the state's precision
+// (eight pair terms per group), the folds across lanes, wavefronts (fixed
+// order) and tiles (compensated, rho_finalize) in FP64.  Partials are stored
+// value-major: partials[(8 bi + v) ntiles + tile].
+template <class R>
+__global__ void __launch_bounds__(kRhoMaxThreads) rho_tile_kernel(const cplx<R>* __restrict__ phi,
+                                                                  const cplx<R>* __restrict__ lam, RhoTileArgs A,
+                                                                  double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[kRhoMaxWaves][32];
+  const uint32_t M = 1u << A.m;
+  cplx<R>* P = reinterpret_cast<cplx<R>*>(smem_raw);
+  cplx<R>* Q = P + rho_lds_off(M);
+  const uint32_t ntiles = gridDim.x;
+  const uint32_t tile = xcd_block(blockIdx.x, ntiles);
+  const uint32_t nlo = A.a - A.L, top = A.a + A.h;
+  const uint32_t base = ((tile & ((1u << nlo) - 1u)) << A.L) | (top >= 32 ? 0u : ((tile >> nlo) << top));
+  const uint32_t lmask = (1u << A.L) - 1u;
+  const uint32_t stride = 2u * blockDim.x;
+  // every thread's 16-byte accesses of both tiles in flight at once (up to
+  // eight per state: 2^13 complex64 amplitudes over 512 threads)
+  constexpr int kLd = 8;
+  for (uint32_t p0 = 2u * threadIdx.x; p0 < M; p0 += kLd * stride) {
+    cplx2<R> vf[kLd], vl[kLd];
+#pragma unroll
+    for (int k = 0; k < kLd; ++k) {
+      const uint32_t pos = p0 + k * stride;
+      if (pos < M) {
+        const uint32_t g = base | (pos & lmask) | ((pos >> A.L) << A.a);
+        vf[k] = ld_nt(reinterpret_cast<const cplx2<R>*>(phi + g));
+        vl[k] = ld_nt(reinterpret_cast<const cplx2<R>*>(lam + g));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kLd; ++k) {
+      const uint32_t pos = p0 + k * stride;
+      if (pos < M) {
+        *reinterpret_cast<cplx2<R>*>(P + rho_lds_off(pos)) = vf[k];
+        *reinterpret_cast<cplx2<R>*>(Q + rho_lds_off(pos)) = vl[k];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  constexpr uint32_t kB = rho_chunk_bits<R>();
+  for (uint32_t c0 = 0; c0 < A.nbits; c0 += kB) {
+    const int req = (int)min(kB, A.nbits - c0);
+    uint32_t t[4];
+    for (int k = 0; k < req; ++k) t[k] = A.tbit[c0 + k];
+    // spare bits: the lowest tile bits not requested in this chunk
+    for (uint32_t b = 0, k = (uint32_t)req; k < kB; ++b) {
+      bool used = false;
+      for (int i = 0; i < req; ++i) used |= t[i] == b;
+      if (!used) t[k++] = b;
+    }
+    switch (req) {
+      case 1: rho_chunk<R, 1>(P, Q, M, t, red[wave]); break;
+      case 2: rho_chunk<R, 2>(P, Q, M, t, red[wave]); break;
+      case 3: rho_chunk<R, 3>(P, Q, M, t, red[wave]); break;
+      default: rho_chunk<R, kB>(P, Q, M, t, red[wave]); break;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8u * (uint32_t)req) {
+      double sum = 0.0;
+      for (uint32_t w = 0; w < nwaves; ++w) sum += red[w][threadIdx.x];
+      partials[((size_t)(8 * c0) + threadIdx.x) * ntiles + tile] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// out[o] = sum over tiles t of partials[o * ntiles + t], compensated, fixed order.
 __global__ void __launch_bounds__(kThreads) rho_finalize(const double* __restrict__ partials, uint32_t ntiles,
-                                                         uint32_t nv, double* __restrict__ out) {
+                                                         double* __restrict__ out) {
   const uint32_t o = blockIdx.x;
+  const double* row = partials + (size_t)o * ntiles;
   Acc a = {0.0, 0.0};
-  for (uint32_t t = threadIdx.x; t < ntiles; t += kThreads) nadd(a, partials[(size_t)t * nv + o]);
+  // eight loads in flight, added in the same order as one at a time (the
+  // zeros past the end add nothing)
+  for (uint32_t t0 = threadIdx.x; t0 < ntiles; t0 += 8 * kThreads) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t t = t0 + k * kThreads;
+      v[k] = t < ntiles ? row[t] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nadd(a, v[k]);
+  }
   __shared__ Acc red[kThreads];
   a = block_fold(a, red);
   if (threadIdx.x == 0) out[o] = a.s + a.c;
@@ -470,13 +633,14 @@ size_t rho_tile_partials(int n, const RhoTileArgs& A) { return ((size_t)1 << (n 
 
 bool rho_tile_fits(uint32_t m, size_t amp_bytes) {
   const uint32_t M = 1u << m;
-  return m >= 7 && 2 * amp_bytes * (M + ((M >> 5) << 1)) <= 160 * 1024;
+  // both tiles plus the kernel's 2 KiB of static LDS within the CU's 160 KiB
+  return m >= 7 && 2 * amp_bytes * (M + ((M >> 5) << 1)) + 2048 <= 160 * 1024;
 }
 
 template <class R>
 bool launch_rho_tile(const cplx<R>* phi, const cplx<R>* lam, int n, const RhoTileArgs& A, double* partials,
                      double* out, hipStream_t s) {
-  constexpr size_t kMaxDynamic = 160 * 1024;
+  constexpr size_t kMaxDynamic = 158 * 1024;
   const uint32_t M = 1u << A.m;
   const size_t lds = 2 * sizeof(cplx<R>) * (M + ((M >> 5) << 1));
   if (!rho_tile_fits(A.m, sizeof(cplx<R>)) || A.nbits == 0 || A.nbits > 32) return false;
@@ -490,10 +654,9 @@ bool launch_rho_tile(const cplx<R>* phi, const cplx<R>* lam, int n, const RhoTil
     attr_set = true;
   }
   const uint32_t ntiles = 1u << (n - A.m);
-  QS_LAUNCH("reduce_rho_tile", s, rho_tile_kernel<R>, dim3(ntiles), dim3(kRhoThreads), lds, s, phi, lam, A,
+  QS_LAUNCH("reduce_rho_tile", s, rho_tile_kernel<R>, dim3(ntiles), dim3(rho_threads(A.m)), lds, s, phi, lam, A,
             partials);
-  QS_LAUNCH("reduce_rho_finalize", s, rho_finalize, dim3(A.nbits * 8), dim3(kThreads), 0, s, partials, ntiles,
-            A.nbits * 8, out);
+  QS_LAUNCH("reduce_rho_finalize", s, rho_finalize, dim3(A.nbits * 8), dim3(kThreads), 0, s, partials, ntiles, out);
   return true;
 }
 template bool launch_rho_tile<float>(const cplx<float>*, const cplx<float>*, int, const RhoTileArgs&, double*, double*,

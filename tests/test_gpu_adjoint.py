@@ -97,3 +97,32 @@ def test_inverse_plan_on_device(qs):
     qs.apply(st, plan)
     qs.apply(st, plan.inverse())
     assert metrics.infidelity(st.download(), psi0) < 1e-24
+
+
+@pytest.mark.parametrize("dtype,tol,tile_bits", [("c64", 1e-5, 13), ("c64", 1e-5, 11), ("c128", 1e-11, 12),
+                                                 ("c128", 1e-11, 9)])
+def test_tiled_cross_densities_on_partial_bit_sets(qs, dtype, tol, tile_bits):
+    """Parametrised rotations on uneven subsets of the wires, so that a tile
+    pass asks for 1 .. 13 bits' cross densities (whole register chunks, part
+    chunks and spare bits), at 14 qubits against parameter shift."""
+    n = 14
+    rng = np.random.default_rng(5)
+    subsets = [list(range(13)), [0, 5, 13], [2, 3, 4, 6, 7, 8, 9, 10, 11], [12], [1, 13, 7, 4, 9]]
+    stream, k = [], 0
+    for sub in subsets:
+        for q in range(n):
+            if q in sub:
+                stream.append(W.G("RY" if k % 2 == 0 else "RX", q, param=k))
+                k += 1
+            else:
+                stream.append(W.G("RZ", q, theta=float(rng.uniform(-1, 1))))
+        stream += [W.G("CNOT", q, q + 1) for q in range(0, n - 1, 2)]
+        stream += [W.G("CNOT", q, q + 1) for q in range(1, n - 1, 2)]
+    params = rng.uniform(-3, 3, size=k)
+    terms = W.xxz_terms(n, 0.5) + W.z_terms(n)
+    plan = qs.Plan(n, stream, n_params=k, params=params, max_tile_bits=tile_bits)
+    assert "tile" in [L["kind"] for L in plan.describe()["layers"]]
+    e, g = qs.adjoint_grad(qs.State(n, dtype), plan, terms)
+    assert abs(e - gradients.energy(n, stream, params, terms)) < tol
+    g_ref = gradients.parameter_shift(n, stream, params, terms)
+    assert np.max(np.abs(g - g_ref)) < tol, np.max(np.abs(g - g_ref))
