@@ -259,7 +259,11 @@ qs_status qs_marginal(qs_state* s, uint64_t qubit_mask, double* out);
  * lambda together, accumulating 2 Re <lambda| dU psi> per parameter in FP64.
  * grad has n_params entries (must equal the plan's).  Parameters may appear in
  * RX, RY, RZ and P gates of single-qubit windows and in diagonal gates (RZ, P,
- * CPHASE, RZZ, MCP); a parameter on any other kind gives QS_EUNSUPPORTED. */
+ * CPHASE, RZZ, MCP); a parameter on any other kind gives QS_EUNSUPPORTED.
+ * Memory: the first call allocates two work states of psi's size (each with
+ * its own gather scratch when the plan has permutation layers) and a small
+ * device scratch area; they stay with psi for later calls and are released
+ * by qs_free(psi).  QS_ENOMEM when they do not fit. */
 qs_status qs_adjoint_grad(qs_state* psi, const qs_plan* p, const qs_pauli* terms,
                           size_t n_terms, double* energy, double* grad, size_t n_params);
 

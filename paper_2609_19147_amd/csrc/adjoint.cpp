@@ -20,21 +20,27 @@ using namespace qs;
 
 namespace {
 
-struct TempState {
-  qs_state s;
-  TempState(const qs_state& like) {
-    s.n = like.n;
-    s.dtype = like.dtype;
-    s.device = like.device;
-    s.stream = like.stream;
-    const size_t bytes = s.state_bytes();
+// Work state k of psi (same n, dtype, device and stream), made on first use
+// and kept with psi; its contents are overwritten by each sweep.
+qs_state& work_state(qs_state& psi, int k) {
+  std::unique_ptr<qs_state>& w = psi.work[k];
+  if (!w) {
+    auto s = std::make_unique<qs_state>();
+    s->n = psi.n;
+    s->dtype = psi.dtype;
+    s->device = psi.device;
+    s->stream = psi.stream;
+    const size_t bytes = s->state_bytes();
     size_t fr = 0, tot = 0;
     check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
     if (bytes > fr) fail(QS_ENOMEM, "no device memory for the adjoint states");
-    if (hipMalloc(&s.buf[0], bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of an adjoint state failed");
-    s.owned[0] = true;
+    if (hipMalloc(&s->buf[0], bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of an adjoint state failed");
+    s->owned[0] = true;
+    w = std::move(s);
   }
-};
+  w->stream = psi.stream;
+  return *w;
+}
 
 template <class R>
 void copy_state(qs_state& dst, qs_state& src) {
@@ -72,7 +78,9 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
 
   // forward
   apply_layers(psi, p, 0, L);
-  TempState phi(psi), lam(psi);
+  struct Work {
+    qs_state& s;
+  } phi{work_state(psi, 0)}, lam{work_state(psi, 1)};
   copy_state<R>(phi.s, psi);
   {
     std::vector<uint32_t> xs, zs;
@@ -84,12 +92,7 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
       cs.push_back(t.ci);
     }
     const size_t nt = std::max<size_t>(ts.size(), 1);
-    void* dterms = nullptr;
-    check_hip(hipMalloc(&dterms, nt * 16 + nt * 8), "hipMalloc");
-    struct Guard {
-      void* p;
-      ~Guard() { hipFree(p); }
-    } g{dterms};
+    void* dterms = psi.ensure_work_buf(nt * 16 + nt * 8);
     uint32_t* dx = (uint32_t*)dterms;
     uint32_t* dz = dx + nt;
     double* dc = (double*)(dz + nt);  // byte offset 8 nt: aligned for doubles
@@ -167,14 +170,8 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
       single_bits[fl] = bits;
     }
   }
-  void* buf = nullptr;
-  if (n_res) check_hip(hipMalloc(&buf, (rho_partials + n_res) * sizeof(double)), "hipMalloc");
-  struct BufGuard {
-    void* p;
-    ~BufGuard() {
-      if (p) hipFree(p);
-    }
-  } buf_guard{buf};
+  // (the forward sweep has finished with the scratch area: psi was synchronised)
+  void* buf = n_res ? psi.ensure_work_buf((rho_partials + n_res) * sizeof(double)) : nullptr;
   double* part = (double*)buf;
   double* res = part + rho_partials;
   for (size_t j = 0; j < L; ++j) {

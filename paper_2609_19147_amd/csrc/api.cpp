@@ -149,6 +149,19 @@ void qs_state::ensure_norm(uint64_t tiles) {
   norm_cap = tiles;
 }
 
+void* qs_state::ensure_work_buf(size_t bytes) {
+  if (work_cap >= bytes) return work_buf;
+  if (work_buf) {
+    check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    check_hip(hipFree(work_buf), "hipFree");
+    work_buf = nullptr;
+    work_cap = 0;
+  }
+  if (hipMalloc(&work_buf, bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of the adjoint scratch failed");
+  work_cap = bytes;
+  return work_buf;
+}
+
 void qs_state::sync() { check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
 
 static qs_state* check_state(qs_state* s) {
@@ -194,6 +207,7 @@ qs_state::~qs_state() {
   if (norm_part) hipFree(norm_part);
   free_graphs(*this);
   if (matbuf) hipFree(matbuf);
+  if (work_buf) hipFree(work_buf);
 }
 
 extern "C" qs_status qs_free(qs_state* s) {

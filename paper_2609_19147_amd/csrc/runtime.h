@@ -5,6 +5,7 @@
 
 #include <complex>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "kernels.h"
@@ -37,6 +38,11 @@ struct qs_state {
   std::vector<PlanGraphEntry> graphs;  // recorded plans, most recent last
   hipStream_t capture_stream = nullptr;  // private stream graphs are recorded on
   void* matbuf = nullptr;  // device staging for dense plain gates
+  // adjoint sweeps: the two work states (phi, lambda) and a device scratch
+  // area, made by the first call and kept until the state is freed
+  std::unique_ptr<qs_state> work[2];
+  void* work_buf = nullptr;
+  size_t work_cap = 0;
 
   size_t amp_bytes() const;
   size_t state_bytes() const;
@@ -44,6 +50,7 @@ struct qs_state {
   void ensure_other();
   void ensure_red();
   void ensure_norm(uint64_t tiles);
+  void* ensure_work_buf(size_t bytes);  // at least `bytes` of device scratch (waits for the stream to grow it)
   void sync();
   ~qs_state();
 };
