@@ -78,10 +78,9 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
 
   // forward
   apply_layers(psi, p, 0, L);
-  struct Work {
-    qs_state& s;
-  } phi{work_state(psi, 0)}, lam{work_state(psi, 1)};
-  copy_state<R>(phi.s, psi);
+  qs_state& phi = work_state(psi, 0);
+  qs_state& lam = work_state(psi, 1);
+  copy_state<R>(phi, psi);
   {
     std::vector<uint32_t> xs, zs;
     std::vector<double> cs;
@@ -101,16 +100,16 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
       check_hip(hipMemcpyAsync(dz, zs.data(), ts.size() * 4, hipMemcpyHostToDevice, psi.stream), "hipMemcpyAsync");
       check_hip(hipMemcpyAsync(dc, cs.data(), ts.size() * 16, hipMemcpyHostToDevice, psi.stream), "hipMemcpyAsync");
     }
-    launch_pauli_apply<R>((const cplx<R>*)phi.s.cur_ptr(), (cplx<R>*)lam.s.cur_ptr(), n, dx, dz, dc, (int)ts.size(),
+    launch_pauli_apply<R>((const cplx<R>*)phi.cur_ptr(), (cplx<R>*)lam.cur_ptr(), n, dx, dz, dc, (int)ts.size(),
                           psi.stream);
     psi.sync();
   }
-  *energy = state_overlap(phi.s, lam.s).real();
+  *energy = state_overlap(phi, lam).real();
 
   // backward: every reduction writes its own slot of one device array, read
   // back once after the sweep (no host round trip per layer)
   std::vector<double> g(p.ir.n_params, 0.0);
-  phi.s.ensure_red();
+  phi.ensure_red();
   const PlanDev& d = p.device_for(psi.dtype);
   // per forward layer: the cross densities of all of a tile layer's parameter
   // bits in one read of phi and lambda (the layer's tile geometry), else one
@@ -176,13 +175,13 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
   double* res = part + rho_partials;
   for (size_t j = 0; j < L; ++j) {
     const size_t fl = L - 1 - j;  // forward layer being undone
-    apply_layers(phi.s, inv, j, j + 1);
-    apply_layers(lam.s, inv, j, j + 1);
-    const cplx<R>* ph = (const cplx<R>*)phi.s.cur_ptr();
-    const cplx<R>* la = (const cplx<R>*)lam.s.cur_ptr();
+    apply_layers(phi, inv, j, j + 1);
+    apply_layers(lam, inv, j, j + 1);
+    const cplx<R>* ph = (const cplx<R>*)phi.cur_ptr();
+    const cplx<R>* la = (const cplx<R>*)lam.cur_ptr();
     if (tile_rho[fl].nbits) launch_rho_tile<R>(ph, la, n, tile_rho[fl], part, res + tile_slot[fl], psi.stream);
     for (int b : single_bits[fl])
-      launch_pair_rho<R>(ph, la, n, b, phi.s.red_partials, res + rho_slot[fl][b], psi.stream);
+      launch_pair_rho<R>(ph, la, n, b, phi.red_partials, res + rho_slot[fl][b], psi.stream);
     for (const auto& kv : diag_slot[fl]) {
       const char* base = (const char*)d.blob;
       const int di = kv.first.first;
@@ -192,7 +191,7 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
       D.lut = base + d.diag_lut[di];
       D.n_groups = d.diag_ngroups[di];
       D.conj = 0;
-      launch_diag_grad<R>(ph, la, n, D, kv.first.second, 1, phi.s.red_partials, res + kv.second, psi.stream);
+      launch_diag_grad<R>(ph, la, n, D, kv.first.second, 1, phi.red_partials, res + kv.second, psi.stream);
     }
   }
   std::vector<double> r(n_res);

@@ -126,3 +126,29 @@ def test_tiled_cross_densities_on_partial_bit_sets(qs, dtype, tol, tile_bits):
     assert abs(e - gradients.energy(n, stream, params, terms)) < tol
     g_ref = gradients.parameter_shift(n, stream, params, terms)
     assert np.max(np.abs(g - g_ref)) < tol, np.max(np.abs(g - g_ref))
+
+
+def test_work_states_are_reused_across_calls_and_plans(qs):
+    """The adjoint's work states stay with the state: repeated calls give the
+    same bits, and a second plan (other structure, other parameter count) on
+    the same state still matches parameter shift."""
+    n = 10
+    st = qs.State(n, "c64")
+    s1 = W.hea_stream(n, 2)
+    p1 = W.hea_params(n, 2, 3)
+    plan1 = qs.Plan(n, s1, n_params=len(p1), params=p1)
+    terms = W.xxz_terms(n, 0.5)
+    e_a, g_a = qs.adjoint_grad(st, plan1, terms)
+    st.set_basis(0)
+    e_b, g_b = qs.adjoint_grad(st, plan1, terms)
+    assert e_a == e_b and np.array_equal(g_a, g_b)
+    s2 = ([W.G("RX", q, param=q) for q in range(n)] + [W.G("CNOT", q, (q + 3) % n) for q in range(n)]
+          + [W.G("RY", q, param=n + q) for q in range(n - 1)])
+    p2 = np.linspace(-1.0, 1.2, 2 * n - 1)
+    plan2 = qs.Plan(n, s2, n_params=len(p2), params=p2)
+    st.set_basis(3)
+    e2, g2 = qs.adjoint_grad(st, plan2, W.z_terms(n))
+    psi0 = sv.basis(n, 3)
+    assert abs(e2 - gradients.energy(n, s2, p2, W.z_terms(n), psi0=psi0)) < 1e-5
+    g_ref = gradients.parameter_shift(n, s2, p2, W.z_terms(n), psi0=psi0)
+    assert np.max(np.abs(g2 - g_ref)) < 1e-5
