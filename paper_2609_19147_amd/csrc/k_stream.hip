@@ -272,7 +272,10 @@ template <class Rd, class Rs>
 void launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, uint64_t N, hipStream_t s) {
   if (sizeof(Rd) == sizeof(Rs) && N >= 2) {
     const uint64_t npairs = N / 2;
-    QS_LAUNCH("copy", s, copy_kernel<Rd>, dim3(grid_for(npairs, kThreads * 4)), dim3(kThreads), 0, s,
+    // one block per 4 kThreads pairs (no grid cap): every thread issues its
+    // four loads once, which streams faster than a grid-stride loop here
+    const uint64_t blocks = (npairs + kThreads * 4 - 1) / (kThreads * 4);
+    QS_LAUNCH("copy", s, copy_kernel<Rd>, dim3((unsigned)(blocks < (1u << 30) ? blocks : (1u << 30))), dim3(kThreads), 0, s,
               reinterpret_cast<cplx2<Rd>*>(dst), reinterpret_cast<const cplx2<Rd>*>(src), npairs);
     return;
   }
