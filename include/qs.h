@@ -284,6 +284,15 @@ qs_status qs_batch_run(qs_batch* b);
  * only): obs[i] has n_terms[i] terms; out receives n_inst values (sync). */
 qs_status qs_batch_expect_diag(qs_batch* b, const qs_pauli* const* obs,
                                const size_t* n_terms, double* out);
+/* Stores diagonal observables (as for qs_batch_expect_diag) on the device
+ * once, for loops that re-run the batch with new parameters and read the
+ * same observables each time; replaces any stored before.  Terms are read
+ * during the call only.  (Section "Algorithm Implementations": the QAOA
+ * cost expectation per instance.) */
+qs_status qs_batch_set_observables(qs_batch* b, const qs_pauli* const* obs, const size_t* n_terms);
+/* Expectation of the stored observables per instance, as qs_batch_expect_diag
+ * (sync); QS_EINVAL when none are stored. */
+qs_status qs_batch_expect_stored(qs_batch* b, double* out);
 /* Expectation of any Pauli sum per instance (sync): Z-type terms of all
  * instances in one batched FP64 reduction, terms with X or Y factors per
  * instance with pair reads.  obs[i] has n_terms[i] terms; out receives n_inst

@@ -217,6 +217,19 @@ class Batch:
         """Per-instance expectation of any Pauli sums (X / Y terms per instance)."""
         return self._expect(lib().qs_batch_expect, observables)
 
+    def set_observables(self, observables) -> None:
+        """Store Z-type Pauli sums (one per instance) on the device once."""
+        arrs = [to_c_terms(o) for o in observables]
+        ptrs = (C.POINTER(QsPauli) * len(arrs))(*[C.cast(a, C.POINTER(QsPauli)) for a in arrs])
+        cnt = (C.c_size_t * len(arrs))(*[len(o) for o in observables])
+        check(lib().qs_batch_set_observables(self.h, ptrs, cnt))
+
+    def expect_stored(self) -> np.ndarray:
+        """Per-instance expectation of the stored observables (one batched reduction)."""
+        out = np.zeros(len(self.n))
+        check(lib().qs_batch_expect_stored(self.h, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
     def state(self, i: int) -> StateView:
         v = C.c_void_p()
         check(lib().qs_batch_state(self.h, i, C.byref(v)))

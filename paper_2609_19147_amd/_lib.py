@@ -83,6 +83,8 @@ _SIGS = {
     "qs_batch_run": ([P], C.c_int),
     "qs_batch_expect_diag": ([P, C.POINTER(C.POINTER(QsPauli)), C.POINTER(SZ), C.POINTER(C.c_double)], C.c_int),
     "qs_batch_expect": ([P, C.POINTER(C.POINTER(QsPauli)), C.POINTER(SZ), C.POINTER(C.c_double)], C.c_int),
+    "qs_batch_set_observables": ([P, C.POINTER(C.POINTER(QsPauli)), C.POINTER(SZ)], C.c_int),
+    "qs_batch_expect_stored": ([P, C.POINTER(C.c_double)], C.c_int),
     "qs_batch_state": ([P, SZ, C.POINTER(P)], C.c_int),
     "qs_batch_free": ([P], C.c_int),
     "qs_profile_enable": ([C.c_int], C.c_int),

@@ -42,6 +42,11 @@ struct qs_batch {
   size_t red_doubles = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // observables stored by qs_batch_set_observables: device tables, results
+  // and partials in one allocation, descriptors in group order
+  void* obs_dev = nullptr;
+  size_t obs_out_off = 0, obs_part_off = 0, obs_desc_off = 0;
+  std::vector<size_t> obs_pos;
 
   size_t amp_bytes() const { return dtype == QS_C64 ? 8 : 16; }
   ~qs_batch();
@@ -54,6 +59,7 @@ qs_batch::~qs_batch() {
   if (desc) hipFree(desc);
   if (red) hipFree(red);
   if (arena) hipFree(arena);
+  if (obs_dev) hipFree(obs_dev);
   if (own_stream && stream) hipStreamDestroy(stream);
 }
 
@@ -301,83 +307,156 @@ extern "C" qs_status qs_batch_run(qs_batch* b) {
   }
 }
 
+namespace {
+
+// Device image of per-instance Z-type observables: count tables and
+// descriptors (host bytes, uploaded as one block), then room for the results
+// (256-byte aligned) and the batched reduction's partial sums.
+struct ObsImage {
+  std::vector<unsigned char> host;
+  size_t desc_off = 0, out_off = 0, part_off = 0, bytes = 0;
+  std::vector<size_t> pos;  // instance -> position in group order
+  std::vector<size_t> t_off, g_off, w_off;
+  std::vector<double> c0;
+  std::vector<int> ng;
+};
+
+ObsImage build_obs(const qs_batch* b, const qs_pauli* const* obs, const size_t* n_terms) {
+  ObsImage I;
+  I.t_off.resize(b->n_inst);
+  I.g_off.resize(b->n_inst);
+  I.w_off.resize(b->n_inst);
+  I.c0.resize(b->n_inst);
+  I.ng.resize(b->n_inst);
+  auto put = [&](const void* src, size_t bytes) {
+    size_t off = (I.host.size() + 15) & ~size_t(15);
+    I.host.resize(off + bytes + 16);
+    if (bytes) std::memcpy(I.host.data() + off, src, bytes);
+    return off;
+  };
+  for (size_t i = 0; i < b->n_inst; ++i) {
+    if (n_terms[i] && !obs[i]) fail(QS_EINVAL, "NULL observable");
+    DiagIR D = diag_observable(b->nq[i], obs[i], n_terms[i]);
+    DiagNumeric num = diag_numeric(D, {});
+    std::vector<double> w;
+    for (auto& G : D.groups) w.push_back(G.angle.c0);
+    // diag_numeric's first group has lut entries; only terms/groups are used here
+    I.t_off[i] = put(num.terms.data(), num.terms.size() * sizeof(DiagTerm));
+    I.g_off[i] = put(num.groups.data(), num.groups.size() * sizeof(DiagGroup));
+    I.w_off[i] = put(w.data(), w.size() * sizeof(double));
+    I.c0[i] = D.global.c0;
+    I.ng[i] = (int)D.groups.size();
+  }
+  I.desc_off = (I.host.size() + 255) & ~size_t(255);
+  I.host.resize(I.desc_off + b->n_inst * sizeof(ObsDev));
+  size_t need_red = 0;
+  for (auto& G : b->groups) need_red = std::max(need_red, batch_observable_partials((uint32_t)G.inst.size(), G.n));
+  I.out_off = (I.host.size() + 255) & ~size_t(255);
+  I.part_off = I.out_off + sizeof(double) * (b->n_inst + 8);
+  I.bytes = I.part_off + sizeof(double) * need_red;
+  I.pos.resize(b->n_inst);
+  size_t k = 0;
+  for (auto& G : b->groups)
+    for (size_t i : G.inst) I.pos[i] = k++;
+  return I;
+}
+
+// Fills the descriptors for device base `dev` and uploads the tables.
+void upload_obs(const qs_batch* b, ObsImage& I, void* dev) {
+  char* base = (char*)dev;
+  for (size_t i = 0; i < b->n_inst; ++i) {
+    ObsDev o;
+    std::memset(&o, 0, sizeof o);
+    o.psi = b->views[i]->buf[0];
+    o.terms = (const DiagTerm*)(base + I.t_off[i]);
+    o.groups = (const DiagGroup*)(base + I.g_off[i]);
+    o.w = (const double*)(base + I.w_off[i]);
+    o.n_groups = I.ng[i];
+    o.c0 = I.c0[i];
+    std::memcpy(I.host.data() + I.desc_off + I.pos[i] * sizeof(ObsDev), &o, sizeof o);
+  }
+  check_hip(hipMemcpyAsync(dev, I.host.data(), I.host.size(), hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync");
+}
+
+// One batched reduction per qubit-count group over uploaded observables, the
+// per-instance results copied back (waits for the stream).
+void run_obs(const qs_batch* b, void* dev, size_t desc_off, size_t out_off, size_t part_off,
+             const std::vector<size_t>& pos, double* out) {
+  char* base = (char*)dev;
+  double* dout = (double*)(base + out_off);
+  double* partials = (double*)(base + part_off);
+  size_t first = 0;
+  for (auto& G : b->groups) {
+    const ObsDev* od_dev = (const ObsDev*)(base + desc_off) + first;
+    if (b->dtype == QS_C64)
+      launch_batch_observable<float>(od_dev, (uint32_t)G.inst.size(), G.n, partials, dout + first, b->stream);
+    else
+      launch_batch_observable<double>(od_dev, (uint32_t)G.inst.size(), G.n, partials, dout + first, b->stream);
+    first += G.inst.size();
+  }
+  std::vector<double> res(b->n_inst);
+  check_hip(hipMemcpyAsync(res.data(), dout, b->n_inst * sizeof(double), hipMemcpyDeviceToHost, b->stream),
+            "hipMemcpyAsync");
+  check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  for (size_t i = 0; i < b->n_inst; ++i) out[i] = res[pos[i]];
+}
+
+}  // namespace
+
 extern "C" qs_status qs_batch_expect_diag(qs_batch* b, const qs_pauli* const* obs, const size_t* n_terms,
                                           double* out) {
   try {
     if (!b || !obs || !n_terms || !out) fail(QS_EINVAL, "NULL argument");
-    // observables -> count tables (host), then one batched reduction per group
-    std::vector<unsigned char> host;
-    std::vector<ObsDev> od(b->n_inst);
-    std::vector<size_t> t_off(b->n_inst), g_off(b->n_inst), w_off(b->n_inst);
-    auto put = [&](const void* src, size_t bytes) {
-      size_t off = (host.size() + 15) & ~size_t(15);
-      host.resize(off + bytes + 16);
-      if (bytes) std::memcpy(host.data() + off, src, bytes);
-      return off;
-    };
-    std::vector<double> c0(b->n_inst);
-    std::vector<int> ng(b->n_inst);
-    for (size_t i = 0; i < b->n_inst; ++i) {
-      if (n_terms[i] && !obs[i]) fail(QS_EINVAL, "NULL observable");
-      DiagIR D = diag_observable(b->nq[i], obs[i], n_terms[i]);
-      DiagNumeric num = diag_numeric(D, {});
-      std::vector<double> w;
-      for (auto& G : D.groups) w.push_back(G.angle.c0);
-      // diag_numeric's first group has lut entries; only terms/groups are used here
-      t_off[i] = put(num.terms.data(), num.terms.size() * sizeof(DiagTerm));
-      g_off[i] = put(num.groups.data(), num.groups.size() * sizeof(DiagGroup));
-      w_off[i] = put(w.data(), w.size() * sizeof(double));
-      c0[i] = D.global.c0;
-      ng[i] = (int)D.groups.size();
-    }
-    size_t obs_off = (host.size() + 255) & ~size_t(255);
-    host.resize(obs_off + b->n_inst * sizeof(ObsDev));
-    size_t need_red = 0;
-    for (auto& G : b->groups) need_red = std::max(need_red, batch_observable_partials((uint32_t)G.inst.size(), G.n));
-    // device layout: tables and descriptors, then the results (256-byte
-    // aligned), then the partial sums
-    const size_t out_off = (host.size() + 255) & ~size_t(255);
-    const size_t part_off = out_off + sizeof(double) * (b->n_inst + 8);
+    ObsImage I = build_obs(b, obs, n_terms);
     void* dev = nullptr;
-    check_hip(hipMalloc(&dev, part_off + sizeof(double) * need_red), "hipMalloc");
+    check_hip(hipMalloc(&dev, I.bytes), "hipMalloc");
     struct Guard {
       void* p;
       ~Guard() { hipFree(p); }
     } guard{dev};
-    char* base = (char*)dev;
-    double* dout = (double*)(base + out_off);
-    double* partials = (double*)(base + part_off);
-    // descriptors in group order
-    std::vector<size_t> pos(b->n_inst);
-    size_t k = 0;
-    for (auto& G : b->groups)
-      for (size_t i : G.inst) pos[i] = k++;
-    for (size_t i = 0; i < b->n_inst; ++i) {
-      ObsDev o;
-      std::memset(&o, 0, sizeof o);
-      o.psi = b->views[i]->buf[0];
-      o.terms = (const DiagTerm*)(base + t_off[i]);
-      o.groups = (const DiagGroup*)(base + g_off[i]);
-      o.w = (const double*)(base + w_off[i]);
-      o.n_groups = ng[i];
-      o.c0 = c0[i];
-      std::memcpy(host.data() + obs_off + pos[i] * sizeof(ObsDev), &o, sizeof o);
+    upload_obs(b, I, dev);
+    run_obs(b, dev, I.desc_off, I.out_off, I.part_off, I.pos, out);
+    return QS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+}
+
+extern "C" qs_status qs_batch_set_observables(qs_batch* b, const qs_pauli* const* obs, const size_t* n_terms) {
+  try {
+    if (!b || !obs || !n_terms) fail(QS_EINVAL, "NULL argument");
+    ObsImage I = build_obs(b, obs, n_terms);
+    void* dev = nullptr;
+    check_hip(hipMalloc(&dev, I.bytes), "hipMalloc");
+    try {
+      upload_obs(b, I, dev);
+      check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    } catch (...) {
+      hipFree(dev);
+      throw;
     }
-    check_hip(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync");
-    size_t first = 0;
-    for (auto& G : b->groups) {
-      const ObsDev* od_dev = (const ObsDev*)(base + obs_off) + first;
-      if (b->dtype == QS_C64)
-        launch_batch_observable<float>(od_dev, (uint32_t)G.inst.size(), G.n, partials, dout + first, b->stream);
-      else
-        launch_batch_observable<double>(od_dev, (uint32_t)G.inst.size(), G.n, partials, dout + first, b->stream);
-      first += G.inst.size();
+    if (b->obs_dev) {
+      check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+      hipFree(b->obs_dev);
     }
-    std::vector<double> res(b->n_inst);
-    check_hip(hipMemcpyAsync(res.data(), dout, b->n_inst * sizeof(double), hipMemcpyDeviceToHost, b->stream),
-              "hipMemcpyAsync");
-    check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-    for (size_t i = 0; i < b->n_inst; ++i) out[i] = res[pos[i]];
+    b->obs_dev = dev;
+    b->obs_desc_off = I.desc_off;
+    b->obs_out_off = I.out_off;
+    b->obs_part_off = I.part_off;
+    b->obs_pos = I.pos;
+    return QS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+}
+
+extern "C" qs_status qs_batch_expect_stored(qs_batch* b, double* out) {
+  try {
+    if (!b || !out) fail(QS_EINVAL, "NULL argument");
+    if (!b->obs_dev) fail(QS_EINVAL, "no observables stored: call qs_batch_set_observables first");
+    run_obs(b, b->obs_dev, b->obs_desc_off, b->obs_out_off, b->obs_part_off, b->obs_pos, out);
     return QS_OK;
   } catch (const Error& e) {
     g_last_error = e.msg;

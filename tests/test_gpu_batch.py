@@ -117,3 +117,32 @@ def test_batch_expect_general_pauli_sums(qs, dtype):
     # Z-only observables give the same value as the diagonal entry point
     zobs = [W.maxcut_terms(i.edges) for i in insts]
     assert np.allclose(B.expect(zobs), B.expect_diag(zobs), rtol=0, atol=1e-12)
+
+
+def test_stored_observables_match_per_call_expectations(qs):
+    """Observables stored once on the device give the per-call reduction's
+    numbers bit for bit, across replays and a parameter refresh; storing a
+    second set replaces the first; reading before any is stored is an error."""
+    insts, plans, B = qaoa_batch(qs, 10, 11, 2, (8, 10, 12, 14))
+    obs = [W.maxcut_terms(i.edges) for i in insts]
+    fresh = qs.Batch(plans, init="plus")
+    with pytest.raises(qs.QsError) as e:
+        fresh.expect_stored()
+    assert e.value.code == -1
+    B.set_observables(obs)
+    for _ in range(2):
+        B.run()
+        assert np.array_equal(B.expect_stored(), B.expect_diag(obs))
+    params = np.linspace(-0.4, 0.9, 4)
+    for p in plans:
+        p.set_params(params)
+    B.refresh()
+    B.run()
+    stored = B.expect_stored()
+    assert np.array_equal(stored, B.expect_diag(obs))
+    for k, inst in enumerate(insts):
+        ref = sv.run(sv.basis(inst.n, 0), inst.n, W.qaoa_stream(inst, param_offset=0), params)
+        assert abs(stored[k] - sv.expect(ref, inst.n, obs[k])) < 1e-5
+    z = [W.z_terms(i.n) for i in insts]
+    B.set_observables(z)
+    assert np.array_equal(B.expect_stored(), B.expect_diag(z))
