@@ -243,7 +243,32 @@ __global__ void __launch_bounds__(kThreads) batch_obs_kernel(const ObsDev* __res
       for (int g = 0; g < O.n_groups; ++g) {
         const DiagGroup G = O.groups[g];
         int cnt[2 * K];
-        diag_counts<2 * K>(i0, off, O.terms, G.term_begin, G.term_end, cnt);
+        const int32_t* nb = O.nbr + g * kObsNbrStride;
+        if (nb[64]) {
+          // a sum of distinct pair mismatches, quadratic in the flipped bits
+          // 0, 9, 10 of the eight points (zero in i0): the count at i0, then
+          // per flipped bit deg - 2 popcount(N & i0), and -2 per flipped pair
+          int c0 = 0;
+          for (int t = G.term_begin; t < G.term_end; ++t) {
+            const uint32_t m = (uint32_t)O.terms[t].mask;
+            const int s = O.terms[t].shift;
+            c0 += popc((i0 ^ (i0 >> s)) & m);
+          }
+          static_assert(2 * kThreads == 512, "the eight points flip state bits 0, 9 and 10");
+          constexpr int kb[3] = {0, 9, 10};
+          int d[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) d[k] = nb[32 + kb[k]] - 2 * popc(i0 & (uint32_t)nb[kb[k]]);
+          const int q01 = -2 * (int)(((uint32_t)nb[0] >> 9) & 1u), q02 = -2 * (int)(((uint32_t)nb[0] >> 10) & 1u);
+          const int q12 = -2 * (int)(((uint32_t)nb[9] >> 10) & 1u);
+#pragma unroll
+          for (int j = 0; j < 2 * K; ++j) {
+            const int f0 = j & 1, f1 = (j >> 1) & 1, f2 = (j >> 2) & 1;
+            cnt[j] = c0 + f0 * d[0] + f1 * d[1] + f2 * d[2] + f0 * f1 * q01 + f0 * f2 * q02 + f1 * f2 * q12;
+          }
+        } else {
+          diag_counts<2 * K>(i0, off, O.terms, G.term_begin, G.term_end, cnt);
+        }
         const double w = O.w[g];
 #pragma unroll
         for (int j = 0; j < 2 * K; ++j) v[j] += w * (double)cnt[j];

@@ -80,7 +80,13 @@ struct ObsDev {
   int32_t n_groups;
   int32_t pad;
   double c0;
+  // per group g, kObsNbrStride int32: [0, 32) neighbour masks N_p, [32, 64)
+  // degrees deg_p, [64] = 1 when the group is a set of distinct bit pairs
+  // (every term DT_SHIFT_XOR), so that flipping a zero bit p changes the
+  // count by deg_p - 2 popcount(N_p & i); 0 otherwise
+  const int32_t* nbr;
 };
+constexpr int kObsNbrStride = 65;
 template <class R>
 void launch_batch_observable(const ObsDev* obs_dev, uint32_t count, uint32_t n, double* partials, double* out,
                              hipStream_t s);
