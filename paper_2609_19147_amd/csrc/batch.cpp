@@ -321,43 +321,17 @@ struct ObsImage {
   std::vector<int> ng;
 };
 
-// Per group, the neighbour masks and degrees of a count that is a sum of
-// distinct bit-pair mismatches (all terms DT_SHIFT_XOR: bit j of a term's mask
-// pairs state bits j and j + shift; a partner at or above bit n is a constant
-// zero and adds to the degree only), else the group's flag stays 0.
-std::vector<int32_t> pair_neighbours(const DiagNumeric& num, int n) {
-  std::vector<int32_t> nb(num.groups.size() * kObsNbrStride, 0);
-  for (size_t g = 0; g < num.groups.size(); ++g) {
+// The neighbour tables of the batched observable kernel (layout of ObsDev::nbr).
+std::vector<int32_t> obs_neighbours(const DiagNumeric& num, int n) {
+  const std::vector<PairNeighbours> pn = pair_neighbours(num, n);
+  std::vector<int32_t> nb(pn.size() * kObsNbrStride, 0);
+  for (size_t g = 0; g < pn.size(); ++g) {
     int32_t* T = nb.data() + g * kObsNbrStride;
-    bool ok = true;
-    std::vector<uint64_t> seen;  // pairs (lo, hi) as lo * 64 + hi, hi = 63 for a constant partner
-    for (int t = num.groups[g].term_begin; t < num.groups[g].term_end && ok; ++t) {
-      const DiagTerm& D = num.terms[t];
-      if (D.form != DT_SHIFT_XOR || D.shift <= 0) {
-        ok = false;
-        break;
-      }
-      for (int j = 0; j < 32; ++j) {
-        if (!((D.mask >> j) & 1u)) continue;
-        if (j >= n) continue;  // both bits are constant zeros: no contribution
-        const int q = j + D.shift;
-        const bool real = q < n;
-        const uint64_t key = (uint64_t)j * 64 + (real ? q : 63);
-        if (std::find(seen.begin(), seen.end(), key) != seen.end()) {
-          ok = false;
-          break;
-        }
-        seen.push_back(key);
-        T[32 + j] += 1;
-        if (real) {
-          T[32 + q] += 1;
-          T[j] |= (int32_t)(1u << q);
-          T[q] |= (int32_t)(1u << j);
-        }
-      }
+    for (int p = 0; p < 32; ++p) {
+      T[p] = (int32_t)pn[g].mask[p];
+      T[32 + p] = pn[g].deg[p];
     }
-    if (!ok) std::fill(T, T + kObsNbrStride, 0);
-    T[64] = ok ? 1 : 0;
+    T[64] = pn[g].ok ? 1 : 0;
   }
   return nb;
 }
@@ -386,7 +360,7 @@ ObsImage build_obs(const qs_batch* b, const qs_pauli* const* obs, const size_t* 
     I.t_off[i] = put(num.terms.data(), num.terms.size() * sizeof(DiagTerm));
     I.g_off[i] = put(num.groups.data(), num.groups.size() * sizeof(DiagGroup));
     I.w_off[i] = put(w.data(), w.size() * sizeof(double));
-    const std::vector<int32_t> nb = pair_neighbours(num, b->nq[i]);
+    const std::vector<int32_t> nb = obs_neighbours(num, b->nq[i]);
     I.nb_off[i] = put(nb.data(), nb.size() * sizeof(int32_t));
     I.c0[i] = D.global.c0;
     I.ng[i] = (int)D.groups.size();

@@ -353,16 +353,36 @@ __device__ __forceinline__ void diag_apply_round(cplx<R>* a, uint32_t i0, uint32
   for (int g = 0; g < D.n_groups; ++g) {
     const int lb = groups[g].lut_begin;
     int cnt[16];
-    if (qt[8 * g]) {
-      const uint32_t off5[5] = {0u, b0, b1, b2, b3};
-      int c5[5];
-      diag_counts<5>(i0, off5, D.terms, groups[g].term_begin, groups[g].term_end, c5);
-      const int d[4] = {c5[1] - c5[0], c5[2] - c5[0], c5[3] - c5[0], c5[4] - c5[0]};
-      const int q01 = qt[8 * g + 1], q02 = qt[8 * g + 2], q03 = qt[8 * g + 3];
-      const int q12 = qt[8 * g + 4], q13 = qt[8 * g + 5], q23 = qt[8 * g + 6];
+    const cptr<int8_t> row = qt + kPairRowBytes * g;
+    if (row[0]) {
+      int d[4];
+      int c0;
+      if (row[7]) {
+        // distinct bit-pair mismatches: the count at the base index (register
+        // bits zero), then deg_k - 2 popcount(N_k & base) per register bit
+        const cptr<DiagTerm> terms = to_const(D.terms);
+        c0 = 0;
+        for (int t = groups[g].term_begin; t < groups[g].term_end; ++t) {
+          const uint32_t m = terms[t].mask;
+          c0 += popc((i0 ^ (i0 >> terms[t].shift)) & m);
+        }
+        const cptr<uint32_t> nmask = reinterpret_cast<cptr<uint32_t>>(row + 16);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = (int)row[8 + k] - 2 * popc(i0 & nmask[k]);
+      } else {
+        const uint32_t off5[5] = {0u, b0, b1, b2, b3};
+        int c5[5];
+        diag_counts<5>(i0, off5, D.terms, groups[g].term_begin, groups[g].term_end, c5);
+        c0 = c5[0];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = c5[k + 1] - c5[0];
+      }
+      const int c5_0 = c0;
+      const int q01 = row[1], q02 = row[2], q03 = row[3];
+      const int q12 = row[4], q13 = row[5], q23 = row[6];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        int c = c5[0];
+        int c = c5_0;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           if ((j >> k) & 1) c += d[k];

@@ -101,6 +101,9 @@ struct DiagTerm {
   int32_t pad;
 };
 
+// Bytes per group in a diagonal round's pair table (see the round builder).
+constexpr int kPairRowBytes = 32;
+
 struct DiagGroup {
   int32_t term_begin, term_end;  // into the layer's term array
   int32_t lut_begin;             // into the layer's LUT (count + 1 entries)

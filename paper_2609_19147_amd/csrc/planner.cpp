@@ -1436,6 +1436,42 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
 
 }  // namespace
 
+std::vector<PairNeighbours> pair_neighbours(const DiagNumeric& num, int n) {
+  std::vector<PairNeighbours> out(num.groups.size());
+  for (size_t g = 0; g < num.groups.size(); ++g) {
+    PairNeighbours& P = out[g];
+    bool ok = true;
+    std::vector<uint64_t> seen;  // pair (lo, hi) as lo * 64 + hi, hi = 63 for a constant partner
+    for (int t = num.groups[g].term_begin; t < num.groups[g].term_end && ok; ++t) {
+      const DiagTerm& D = num.terms[t];
+      if (D.form != DT_SHIFT_XOR || D.shift <= 0) {
+        ok = false;
+        break;
+      }
+      for (int j = 0; j < 32 && j < n; ++j) {
+        if (!((D.mask >> j) & 1u)) continue;
+        const int q = j + D.shift;
+        const bool real = q < n;
+        const uint64_t key = (uint64_t)j * 64 + (real ? q : 63);
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) {
+          ok = false;
+          break;
+        }
+        seen.push_back(key);
+        P.deg[j] += 1;
+        if (real) {
+          P.deg[q] += 1;
+          P.mask[j] |= 1u << q;
+          P.mask[q] |= 1u << j;
+        }
+      }
+    }
+    if (!ok) P = PairNeighbours{};
+    P.ok = ok;
+  }
+  return out;
+}
+
 // A structured plan of a gate list (no window fusion).
 static PlanIR structured_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOptions& opt,
                               int tile_bits, int low_bits, int windows) {

@@ -178,6 +178,17 @@ struct DiagNumeric {
 // x mod 2 pi in [-pi, pi], against 2 pi carried in two doubles.
 double reduce_2pi(double x);
 DiagNumeric diag_numeric(const DiagIR& d, const std::vector<double>& params, bool conj = false);
+// A group whose count is a sum of distinct bit-pair mismatches (every term
+// DT_SHIFT_XOR; bit j of a term's mask pairs state bits j and j + shift, a
+// partner at or above bit n being a constant zero): per state bit p its real
+// partners N_p and its number of pairs deg_p, so that setting a zero bit p of
+// i changes the count by deg_p - 2 popcount(N_p & i).  ok = false otherwise.
+struct PairNeighbours {
+  bool ok = false;
+  uint32_t mask[32] = {0};
+  int32_t deg[32] = {0};
+};
+std::vector<PairNeighbours> pair_neighbours(const DiagNumeric& num, int n);
 // Diagonal observable sum_t c_t Z-string_t as value(i) = global + sum_g angle_g
 // count_g(i) (the groups' "angles" are the real weights -2 c).
 DiagIR diag_observable(int n, const qs_pauli* terms, size_t n_terms);

@@ -39,11 +39,17 @@ constexpr int kAngleModeGroups = 3;
 // x AND y = xy for a bond on two register bits, linear or constant otherwise.
 // The kernel then evaluates the count at the group's base index and at the
 // four single-bit flips, and adds q_kl for every pair of set register bits.
-// Table per group: {quadratic flag, q01, q02, q03, q12, q13, q23, 0}.
-void round_pair_table(const DiagNumeric& num, const int g[4], std::vector<int8_t>& out) {
+// Row per group (kPairRowBytes): {quadratic flag, q01, q02, q03, q12, q13,
+// q23, pair flag, deg_0..deg_3, 0, 0, 0, 0, N_0..N_3 as uint32}.  With the pair
+// flag set (a sum of distinct bit-pair mismatches) the kernel obtains the four
+// flipped counts from the base count as base + deg_k - 2 popcount(N_k & base)
+// instead of evaluating every term four more times.
+void round_pair_table(const DiagNumeric& num, const std::vector<PairNeighbours>& pn, const int g[4],
+                      std::vector<int8_t>& out) {
   static const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
-  for (const DiagGroup& G : num.groups) {
-    int8_t row[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+  for (size_t gi = 0; gi < num.groups.size(); ++gi) {
+    const DiagGroup& G = num.groups[gi];
+    int8_t row[kPairRowBytes] = {1, 0};
     int q[6] = {0, 0, 0, 0, 0, 0};
     for (int t = G.term_begin; t < G.term_end; ++t) {
       const DiagTerm& T = num.terms[t];
@@ -61,7 +67,16 @@ void round_pair_table(const DiagNumeric& num, const int g[4], std::vector<int8_t
       if (q[e] < -127 || q[e] > 127) row[0] = 0;
       row[1 + e] = (int8_t)q[e];
     }
-    out.insert(out.end(), row, row + 8);
+    bool pairs = row[0] != 0 && pn[gi].ok;
+    for (int k = 0; k < 4 && pairs; ++k) pairs = pn[gi].deg[g[k]] <= 127;
+    if (pairs) {
+      row[7] = 1;
+      for (int k = 0; k < 4; ++k) {
+        row[8 + k] = (int8_t)pn[gi].deg[g[k]];
+        std::memcpy(row + 16 + 4 * k, &pn[gi].mask[g[k]], 4);
+      }
+    }
+    out.insert(out.end(), row, row + kPairRowBytes);
   }
 }
 
@@ -75,8 +90,10 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
   d.diag_theta.assign(P.diags.size(), 0);
   d.diag_global.assign(P.diags.size(), 0.0);
   std::vector<DiagNumeric> nums;
+  std::vector<std::vector<PairNeighbours>> pns;
   for (size_t i = 0; i < P.diags.size(); ++i) {
     DiagNumeric num = diag_numeric(P.diags[i], p.params);
+    pns.push_back(pair_neighbours(num, P.n));
     d.diag_terms[i] = b.put(num.terms);
     d.diag_groups[i] = b.put(num.groups);
     d.diag_lut[i] = b.put(cast<R>(num.lut));
@@ -103,16 +120,16 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
       for (int k = 0; k < 4; ++k) g[k] = r.tbit[k] < T.L ? r.tbit[k] : r.tbit[k] - T.L + T.a;
       r.qoff = (int32_t)qtab.size();
       const DiagNumeric& num = nums[T.diag_slots[r.diag]];
-      round_pair_table(num, g, qtab);
+      round_pair_table(num, pns[T.diag_slots[r.diag]], g, qtab);
       // angle mode for layers with many groups, all quadratic: the six pair
       // phases exp(i sum_g theta_g q_g,kl) join the pass's coefficients
       bool all_quad = num.groups.size() >= (size_t)kAngleModeGroups;
-      for (size_t gi = 0; gi < num.groups.size(); ++gi) all_quad = all_quad && qtab[r.qoff + 8 * gi] != 0;
+      for (size_t gi = 0; gi < num.groups.size(); ++gi) all_quad = all_quad && qtab[r.qoff + kPairRowBytes * gi] != 0;
       if (all_quad) {
         r.qcoef = (int32_t)coef.size();
         for (int e = 0; e < 6; ++e) {
           double Q = 0.0;
-          for (size_t gi = 0; gi < num.groups.size(); ++gi) Q += num.theta[gi] * qtab[r.qoff + 8 * gi + 1 + e];
+          for (size_t gi = 0; gi < num.groups.size(); ++gi) Q += num.theta[gi] * qtab[r.qoff + kPairRowBytes * gi + 1 + e];
           coef.push_back(std::polar(1.0, Q));
         }
       }
