@@ -20,7 +20,7 @@ static std::vector<double> rand_unitary_flat(std::mt19937_64& r, int d) {
 int main(int argc, char** argv) {
   int iters = argc > 1 ? atoi(argv[1]) : 300;
   std::mt19937_64 rng(12345);
-  size_t ok = 0, errs = 0;
+  size_t ok = 0, errs = 0, nbr_checks = 0;
   for (int it = 0; it < iters; ++it) {
     const int n = 1 + (int)(rng() % 32);
     const int ng = (int)(rng() % 120);
@@ -82,7 +82,37 @@ int main(int argc, char** argv) {
           (void)coef;
         }
         for (auto& g2 : P.gf2s) { Gf2Args a = gf2_args(n, g2, 5); (void)a; }
-        for (auto& d : P.diags) { auto num = diag_numeric(d, params); (void)num; }
+        for (auto& d : P.diags) {
+          auto num = diag_numeric(d, params);
+          // neighbour masks of pair-mismatch groups against direct counts:
+          // setting zero bits p (and q) of i moves the count by deg - 2|N & i|
+          // (and -2 more when p, q are a pair)
+          auto pn = pair_neighbours(num, n);
+          for (size_t g = 0; g < pn.size(); ++g) {
+            if (!pn[g].ok) continue;
+            auto count = [&](uint32_t i) {
+              int c = 0;
+              for (int t = num.groups[g].term_begin; t < num.groups[g].term_end; ++t)
+                c += __builtin_popcount((i ^ (i >> num.terms[t].shift)) & num.terms[t].mask);
+              return c;
+            };
+            const uint32_t full = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+            for (int trial = 0; trial < 8; ++trial) {
+              const int bp = (int)(rng() % n), bq = (int)(rng() % n);
+              const uint32_t i = (uint32_t)rng() & full & ~(1u << bp) & ~(1u << bq);
+              const int dp = pn[g].deg[bp] - 2 * __builtin_popcount(pn[g].mask[bp] & i);
+              const int dq = pn[g].deg[bq] - 2 * __builtin_popcount(pn[g].mask[bq] & i);
+              const int pair = bp != bq && ((pn[g].mask[bp] >> bq) & 1u) ? -2 : 0;
+              const int want1 = count(i | (1u << bp)) - count(i);
+              const int want2 = bp != bq ? count(i | (1u << bp) | (1u << bq)) - count(i) : want1;
+              if (want1 != dp || want2 != (bp != bq ? dp + dq + pair : dp)) {
+                std::printf("pair neighbours disagree: n=%d group=%zu bits %d %d\n", n, g, bp, bq);
+                return 1;
+              }
+              ++nbr_checks;
+            }
+          }
+        }
         if (n_params) { try { auto ge = grad_entries(P, params); (void)ge; } catch (const Error&) {} }
         ok += js.size() > 0 && js2.size() > 0;
       }
@@ -90,6 +120,6 @@ int main(int argc, char** argv) {
       ++errs;
     }
   }
-  std::printf("plans ok: %zu, rejected streams: %zu\n", ok, errs);
+  std::printf("plans ok: %zu, rejected streams: %zu, pair-neighbour checks: %zu\n", ok, errs, nbr_checks);
   return 0;
 }

@@ -6,6 +6,7 @@ parameters go through normalisation, planning with four option sets
 sizes), description, inversion, gradient bookkeeping, GF(2) kernel arguments
 and numeric tables.  Any sanitizer report fails the test."""
 import os
+import re
 import shutil
 import subprocess
 import tempfile
@@ -31,3 +32,7 @@ def test_planner_fuzz_under_asan_ubsan():
         r = subprocess.run([exe, "150"], capture_output=True, text=True, env=env, timeout=600)
         assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
         assert "plans ok: 600" in r.stdout and "runtime error" not in r.stderr, r.stdout + r.stderr[-2000:]
+        # the neighbour masks of pair-mismatch diagonal groups were checked
+        # against direct counts on some of the random streams
+        m = re.search(r"pair-neighbour checks: (\d+)", r.stdout)
+        assert m and int(m.group(1)) > 0, r.stdout
