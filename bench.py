@@ -199,11 +199,22 @@ def bench_adjoint(qs, torch, n=24, layers=8, seed=24, ps_sample=16):
     """24-qubit hardware-efficient ansatz (384 parameters), XXZ energy: one
     adjoint forward + backward against GPU parameter shift (769 circuits; the
     plain and fused per-circuit paths are timed on a sample of circuits)."""
+    from paper_2609_19147_amd.tune import TileTuner
     stream = W.hea_stream(n, layers)
     params = W.hea_params(n, layers, seed)
     terms = W.xxz_terms(n, 0.5)
-    plan = qs.Plan(n, stream, n_params=len(params), params=params)
     st = qs.State(n, "c64")
+    # tile limit of the plan: measured once per device (untimed), like the
+    # batched section's
+    plans = {}
+
+    def run(tb):
+        if tb not in plans:
+            plans[tb] = qs.Plan(n, stream, n_params=len(params), params=params, max_tile_bits=tb)
+        st.set_basis(0)
+        qs.adjoint_grad(st, plans[tb], terms)
+    tile_bits = TileTuner().best(f"adjoint-hea{layers}-xxz", n, "c64", run, (11, 12, 13))
+    plan = plans.get(tile_bits) or qs.Plan(n, stream, n_params=len(params), params=params, max_tile_bits=tile_bits)
     qs.adjoint_grad(st, plan, terms)  # warm-up (builds the inverse plan)
     ts = []
     for _ in range(3):
@@ -245,7 +256,7 @@ def bench_adjoint(qs, torch, n=24, layers=8, seed=24, ps_sample=16):
     t_plain = (time.perf_counter() - t0) / (2 * max(1, len(idx) // 2))
     diff = max(abs(g[j] - v) for j, v in g_ps.items())
     return {"n_qubits": n, "params": len(params), "terms": len(terms), "energy": e,
-            "ms_adjoint": round(1e3 * t_adj, 2),
+            "max_tile_bits": tile_bits, "ms_adjoint": round(1e3 * t_adj, 2),
             "equiv_circuits_per_s": round(n_circ / t_adj, 1),
             "plain_circuits_per_s": round(1.0 / t_plain, 2),
             "fused_circuits_per_s": round(1.0 / t_fused, 2),
