@@ -596,17 +596,22 @@ def main():
         step()
     torch.cuda.synchronize()
     with qs.profile() as prof:
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ev0.record()
-        for _ in range(args.steps):
+        evs[0].record()
+        for k in range(args.steps):
             nrm = step()
-        ev1.record()
+            evs[k + 1].record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     wall = t1 - t0
+    # per-step device times: mean and the t-based 95% confidence half-width
+    per_step = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    ci95 = None
+    if args.steps > 1:
+        from scipy.stats import t as student_t
+        ci95 = float(student_t.ppf(0.975, args.steps - 1) * per_step.std(ddof=1) / math.sqrt(args.steps))
     ms_step = 1e3 * wall / args.steps
     alg_bytes = n_pass * 2 * S + S
     value = alg_bytes / (wall / args.steps) / 1e9
@@ -653,6 +658,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
+        "ms_per_step_events": {"mean": round(float(per_step.mean()), 4),
+                               "ci95": round(ci95, 4) if ci95 is not None else None, "steps": args.steps},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
