@@ -80,6 +80,9 @@ std::string shape_signature(const PlanIR& P) {
   return sig;
 }
 
+// Every amplitude of |+>^n: 2^(-n/2).
+double plus_amplitude(int n) { return std::ldexp(1.0, -n / 2) * ((n & 1) ? std::sqrt(0.5) : 1.0); }
+
 template <class R>
 void build_descs(qs_batch& B) {
   // one TileKArgs per (group, tile layer, instance), laid out contiguously per launch
@@ -115,6 +118,8 @@ void build_descs(qs_batch& B) {
         A.n_rounds = (uint32_t)T.rounds.size();
         A.n = p.ir.n;
         A.scale = T.scale;
+        // |+>^n made by the first layer's tile loads (no separate fill)
+        if (li == 0 && B.init == 1) A.init_amp = plus_amplitude(G.n);
         std::memcpy(host.data() + off + k * sizeof A, &A, sizeof A);
       }
       B.slot_desc[gi][li] = off;
@@ -138,8 +143,9 @@ void record(qs_batch& B) {
     cplx<R>* base = (cplx<R>*)((char*)B.arena + B.offset[first] * B.amp_bytes());
     const uint64_t N = (uint64_t)G.inst.size() << G.n;  // instances of a group are contiguous
     if (B.init == 1) {
-      const double v = std::ldexp(1.0, -G.n / 2) * ((G.n & 1) ? std::sqrt(0.5) : 1.0);
-      launch_fill_uniform<R>(base, N, v, B.stream);
+      // a group whose first layer is a tile pass makes |+>^n in that pass's loads
+      const PlanIR& P0 = B.plans[first]->ir;
+      if (P0.layers.empty() || P0.layers[0].kind != L_TILE) launch_fill_uniform<R>(base, N, plus_amplitude(G.n), B.stream);
     } else {
       // |0...0> for each instance
       launch_fill_uniform<R>(base, N, 0.0, B.stream);

@@ -303,6 +303,12 @@ __device__ __forceinline__ Ctx coset_ctx(const TileKArgs<R>& A, uint32_t coset) 
 template <class R>
 __device__ __forceinline__ void tile_load(const TileKArgs<R>& A, const Ctx& C, cplx<R>* T) {
   const uint32_t M = 1u << A.m, stride = 2 * blockDim.x;
+  if (A.init_amp != 0.0) {
+    // the uniform initial state, made here instead of read from HBM
+    const cplx2<R> v{cplx<R>{(R)A.init_amp, R(0)}, cplx<R>{(R)A.init_amp, R(0)}};
+    for (uint32_t pos = 2 * threadIdx.x; pos < M; pos += stride) *reinterpret_cast<cplx2<R>*>(T + lds_off(pos)) = v;
+    return;
+  }
   const cplx<R>* __restrict__ psi = A.psi;
   if (M >= stride * kChunk) {
     for (uint32_t p0 = 2 * threadIdx.x; p0 < M; p0 += stride * kChunk) {
@@ -497,6 +503,7 @@ __device__ __forceinline__ TileKArgs<R> load_args(const TileKArgs<R>* descs, uin
   A.n = P->n;
   A.scale = P->scale;
   A.norm_part = nullptr;  // batched passes never report a norm
+  A.init_amp = P->init_amp;
   return A;
 }
 

@@ -61,6 +61,8 @@ struct TileKArgs {
   uint32_t n;
   double scale;       // 2^(-k/2) for the pass's k unscaled butterflies
   double* norm_part;  // null, or one FP64 sum of |psi|^2 as stored per tile
+  double init_amp;    // 0: load the tile; else the tile starts as this real
+                      // amplitude everywhere (a uniform state made on load)
 };
 template <class R> void launch_tile(const TileKArgs<R>& A, hipStream_t s);
 // count instances of one geometry (n qubits, m tile bits), descriptors in device
