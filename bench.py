@@ -266,6 +266,49 @@ def bench_adjoint(qs, torch, n=24, layers=8, seed=24, ps_sample=16):
             "param_shift_sample": f"{len(idx)} parameters (fused), {max(1, len(idx) // 2)} (plain)"}
 
 
+def bench_precision(qs, torch, n=N_QUBITS, reps=3):
+    """The composed 30-qubit circuit in complex128 on the GPU beside complex64
+    from the same input (the complex128 Gaussian state rounded once): time and
+    effective GB/s of each, the complex64 result's infidelity against the
+    complex128 one, and its norm drift (FP64 reductions)."""
+    from paper_2609_19147_amd.tune import TileTuner
+    stream = circuit(n)
+    plans = {13: qs.Plan(n, stream)}
+    s128 = qs.State(n, "c128", init=None)
+    W.gaussian_state_torch(n, STATE_SEED, "c128", out=s128.tensor())
+    s64 = qs.State(n, "c64", init=None)
+    src = qs.State(n, "c128", init=None, lazy_scratch=True)
+    src.copy_from(s128)
+
+    # complex128 tiles of 2^13 amplitudes fill a CU's LDS (one workgroup per
+    # CU): the tile limit for complex128 is measured (untimed), as elsewhere
+    def run128(tb):
+        if tb not in plans:
+            plans[tb] = qs.Plan(n, stream, max_tile_bits=tb)
+        qs.apply(s128, plans[tb])
+    tb128 = TileTuner().best("composed-circuit", n, "c128", run128, (11, 12, 13))
+    out = {"max_tile_bits_c64": 13, "max_tile_bits_c128": tb128}
+    for name, st, amp, plan in (("c64", s64, 8, plans[13]), ("c128", s128, 16, plans[tb128])):
+        ts = []
+        for _ in range(reps):
+            st.copy_from(src)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            qs.apply(st, plan)
+            st.sync()
+            ts.append(time.perf_counter() - t0)
+        t = min(ts)
+        out[f"ms_{name}"] = round(1e3 * t, 3)
+        out[f"passes_{name}"] = plan.num_layers()
+        out[f"GBs_{name}"] = round(plan.num_layers() * 2 * amp * (1 << n) / t / 1e9, 1)
+    del src
+    torch.cuda.empty_cache()
+    out["infidelity_c64_vs_c128"] = qs.infidelity(s64, s128)
+    out["norm2_drift_c64"] = abs(qs.norm2(s64) - 1.0)
+    out["norm2_drift_c128"] = abs(qs.norm2(s128) - 1.0)
+    return out
+
+
 def bench_tfim(qs, torch, n=25, steps=40):
     """25-qubit open-chain TFIM, J = 1, h = 0.8, dt = 0.05, 40 Strang steps
     after an H layer, complex64: fused plan vs the plain per-gate path."""
@@ -534,6 +577,7 @@ SECTIONS = {
     "batched_qaoa": lambda qs, torch: bench_batched_qaoa(qs, torch),
     "adjoint": lambda qs, torch: bench_adjoint(qs, torch),
     "tfim25": lambda qs, torch: bench_tfim(qs, torch),
+    "precision_30q": lambda qs, torch: bench_precision(qs, torch),
     "dense_blocks": lambda qs, torch: bench_dense(qs, torch),
     "layers_30q": lambda qs, torch: bench_layers(qs, torch),
     "diag_families_25q": lambda qs, torch: bench_families(qs, torch),
@@ -686,6 +730,8 @@ def main():
         out["adjoint"] = bench_adjoint(qs, torch)
         log("TFIM: 25 qubits, 40 Strang steps")
         out["tfim25"] = bench_tfim(qs, torch)
+        log("precision: the 30-qubit circuit in complex64 and complex128")
+        out["precision_30q"] = bench_precision(qs, torch)
         log("dense k-qubit blocks: 30 qubits, k = 4, 5, 6")
         out["dense_blocks"] = bench_dense(qs, torch)
         log("single layers: 30 qubits")
