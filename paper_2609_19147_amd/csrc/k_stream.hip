@@ -111,6 +111,28 @@ __device__ __forceinline__ void gf2_coset_rep(const Gf2Args& A, uint32_t c, uint
     if ((y0 >> j) & 1u) x0 ^= A.acol[j];
 }
 
+// LDS tile of a gather: complex64 elements interleaved (one 8-byte word
+// each, the swizzle keeps 2^c lanes on distinct words); complex128 elements
+// as a real and an imaginary plane of 8-byte words, so the same swizzle
+// applies to each plane.
+template <class R>
+struct GfTile {
+  R* base;
+  uint32_t D;
+  __device__ __forceinline__ void put(uint32_t i, const cplx<R>& v) const {
+    if constexpr (sizeof(R) == 4) {
+      reinterpret_cast<cplx<R>*>(base)[i] = v;
+    } else {
+      base[i] = v.re;
+      base[D + i] = v.im;
+    }
+  }
+  __device__ __forceinline__ cplx<R> get(uint32_t i) const {
+    if constexpr (sizeof(R) == 4) return reinterpret_cast<const cplx<R>*>(base)[i];
+    else return cplx<R>{base[i], base[D + i]};
+  }
+};
+
 template <class R, int kB>
 __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                        Gf2Args A, double* __restrict__ norm_part, uint32_t per) {
@@ -154,21 +176,21 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
       // share one aligned pair; `f` says whether the pair is swapped
 #pragma unroll
       for (int b = 0; b < kB; ++b) {
-        cplx<R>* Tb = T + b * D;
+        const GfTile<R> Tb{reinterpret_cast<R*>(T + b * D), D};
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const uint32_t s = 2u * (threadIdx.x + kThreads * k);
           const uint32_t slo = s & lomask, shi = s >> A.c;
           const uint32_t f = xa[b][k] & 1u;  // w.a holds source coordinate slo ^ f
           const uint32_t ta = tl[slo ^ f] ^ th[shi], tb = tl[slo ^ f ^ 1u] ^ th[shi];
-          Tb[ta ^ hx[ta >> A.c]] = w[b][k].a;
-          Tb[tb ^ hx[tb >> A.c]] = w[b][k].b;
+          Tb.put(ta ^ hx[ta >> A.c], w[b][k].a);
+          Tb.put(tb ^ hx[tb >> A.c], w[b][k].b);
         }
       }
       __syncthreads();
 #pragma unroll
       for (int b = 0; b < kB; ++b) {
-        const cplx<R>* Tb = T + b * D;
+        const GfTile<R> Tb{reinterpret_cast<R*>(T + b * D), D};
         cplx<R> v[4];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -176,8 +198,8 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
           const uint32_t ya = y0[b] ^ (tt & lomask) ^ vh[tt >> A.c];
           const uint32_t f = ya & 1u;  // the even destination takes tile coordinate tt ^ f
           const uint32_t te = tt ^ f, to = tt ^ f ^ 1u;
-          v[2 * k] = Tb[te ^ hx[te >> A.c]];
-          v[2 * k + 1] = Tb[to ^ hx[to >> A.c]];
+          v[2 * k] = Tb.get(te ^ hx[te >> A.c]);
+          v[2 * k + 1] = Tb.get(to ^ hx[to >> A.c]);
           st_nt(reinterpret_cast<cplx2<R>*>(out + (ya & ~1u)), cplx2<R>{v[2 * k], v[2 * k + 1]});
         }
         if (norm_part != nullptr) {
@@ -199,13 +221,13 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
     const uint32_t slo = s & lomask, shi = s >> A.c;
     const uint32_t x = x0 ^ slo ^ au[shi];
     const uint32_t tk = tl[slo] ^ th[shi];
-    T[tk ^ hx[tk >> A.c]] = in[x];
+    GfTile<R>{reinterpret_cast<R*>(T), D}.put(tk ^ hx[tk >> A.c], in[x]);
   }
   __syncthreads();
   double nacc = 0.0;
   for (uint32_t t = threadIdx.x; t < D; t += kThreads) {
     const uint32_t y = y0 ^ (t & lomask) ^ vh[t >> A.c];
-    const cplx<R> v = T[t ^ hx[t >> A.c]];
+    const cplx<R> v = GfTile<R>{reinterpret_cast<R*>(T), D}.get(t ^ hx[t >> A.c]);
     out[y] = v;
     nacc += abs2_d(v);
   }
