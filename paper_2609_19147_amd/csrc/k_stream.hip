@@ -53,6 +53,21 @@ __global__ void __launch_bounds__(kThreads) copy_kernel(cplx2<R>* __restrict__ d
   for (; i < npairs; i += step) dst[i] = src[i];
 }
 
+__global__ void __launch_bounds__(kThreads) copy1_kernel(cplx<double>* __restrict__ dst,
+                                                         const cplx<double>* __restrict__ src, uint64_t n) {
+  const uint64_t step = (uint64_t)gridDim.x * kThreads;
+  uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x;
+  for (; i + 3 * step < n; i += 4 * step) {
+    const cplx<double> v0 = ld_nt(src + i), v1 = ld_nt(src + i + step), v2 = ld_nt(src + i + 2 * step),
+                       v3 = ld_nt(src + i + 3 * step);
+    st_nt(dst + i, v0);
+    st_nt(dst + i + step, v1);
+    st_nt(dst + i + 2 * step, v2);
+    st_nt(dst + i + 3 * step, v3);
+  }
+  for (; i < n; i += step) dst[i] = src[i];
+}
+
 template <class R>
 __global__ void gather_kernel(const cplx<R>* psi, const uint64_t* idx, cplx<R>* out, uint64_t count) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
@@ -152,6 +167,56 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
   __syncthreads();
   const uint32_t D = 1u << A.d;
   const uint32_t lomask = nlo - 1u;
+  if constexpr (sizeof(R) == 8) {
+    if (D == kThreads * 4) {
+      // complex128 full tiles: one 16-byte element per lane and access
+      // (source and destination runs are XOR-permuted aligned blocks of 2^c
+      // elements, so consecutive lanes stay inside aligned blocks); kB cosets'
+      // loads in flight, as below
+      for (uint32_t q = 0; q < per; q += kB) {
+        uint32_t y0[kB];
+        cplx<R> w[kB][4];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+          uint32_t x0;
+          gf2_coset_rep(A, blockIdx.x * per + q + b, y0[b], x0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t s = threadIdx.x + kThreads * k;
+            w[b][k] = ld_nt(in + (x0 ^ (s & lomask) ^ au[s >> A.c]));
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+          const GfTile<R> Tb{reinterpret_cast<R*>(T + b * D), D};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t s = threadIdx.x + kThreads * k;
+            const uint32_t t = tl[s & lomask] ^ th[s >> A.c];
+            Tb.put(t ^ hx[t >> A.c], w[b][k]);
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+          const GfTile<R> Tb{reinterpret_cast<R*>(T + b * D), D};
+          cplx<R> v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t t = threadIdx.x + kThreads * k;
+            v[k] = Tb.get(t ^ hx[t >> A.c]);
+            st_nt(out + (y0[b] ^ (t & lomask) ^ vh[t >> A.c]), v[k]);
+          }
+          if (norm_part != nullptr) {
+            const double tn = wave_sum_fixed(abs2_d(v[0]) + abs2_d(v[1]) + abs2_d(v[2]) + abs2_d(v[3]));
+            if ((threadIdx.x & 63u) == 0) norm_part[4 * (size_t)(blockIdx.x * per + q + b) + (threadIdx.x >> 6)] = tn;
+          }
+        }
+        __syncthreads();  // the next cosets rewrite the tiles
+      }
+      return;
+    }
+  }
   if (D == kThreads * 4) {
     // full tiles, `per` consecutive cosets per workgroup (the tables above are
     // loaded once), kB of them at a time in kB tiles of LDS: 2 kB 16-byte
@@ -292,6 +357,12 @@ void launch_fill_uniform(cplx<R>* psi, uint64_t N, double v, hipStream_t s) {
 }
 template <class Rd, class Rs>
 void launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, uint64_t N, hipStream_t s) {
+  if (sizeof(Rd) == 8 && sizeof(Rs) == 8) {
+    // complex128: one 16-byte amplitude per lane and access
+    QS_LAUNCH("copy", s, copy1_kernel, dim3((unsigned)std::min<uint64_t>((N + kThreads * 4 - 1) / (kThreads * 4), 1u << 30)),
+              dim3(kThreads), 0, s, reinterpret_cast<cplx<double>*>(dst), reinterpret_cast<const cplx<double>*>(src), N);
+    return;
+  }
   if (sizeof(Rd) == sizeof(Rs) && N >= 2) {
     const uint64_t npairs = N / 2;
     // one block per 4 kThreads pairs (no grid cap): every thread issues its

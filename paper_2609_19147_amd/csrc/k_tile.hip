@@ -300,6 +300,28 @@ __device__ __forceinline__ Ctx coset_ctx(const TileKArgs<R>& A, uint32_t coset) 
 // ---- load: pairs (pos, pos+1) are adjacent in memory (tile bit 0 = state bit 0).
 // Tiles of >= 1024 amplitudes give every thread a multiple of kChunk pairs,
 // so the batch of loads is issued without per-element guards.
+// complex128: one 16-byte amplitude per lane and access, consecutive lanes on
+// consecutive amplitudes (a pair per lane would be two 16-byte accesses at a
+// 32-byte lane stride, each half-filling its requests)
+__device__ __forceinline__ void tile_load_c128(const TileKArgs<double>& A, const Ctx& C, cplx<double>* T) {
+  const uint32_t M = 1u << A.m, nthr = blockDim.x;
+  const cplx<double>* __restrict__ psi = A.psi;
+  constexpr int K = 2 * kChunk;
+  for (uint32_t p0 = threadIdx.x; p0 < M; p0 += nthr * K) {
+    cplx<double> v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t pos = p0 + nthr * k;
+      if (pos < M) v[k] = ld_nt(psi + (C.base | C.dep(pos)));
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t pos = p0 + nthr * k;
+      if (pos < M) T[lds_off(pos)] = v[k];
+    }
+  }
+}
+
 template <class R>
 __device__ __forceinline__ void tile_load(const TileKArgs<R>& A, const Ctx& C, cplx<R>* T) {
   const uint32_t M = 1u << A.m, stride = 2 * blockDim.x;
@@ -307,6 +329,10 @@ __device__ __forceinline__ void tile_load(const TileKArgs<R>& A, const Ctx& C, c
     // the uniform initial state, made here instead of read from HBM
     const cplx2<R> v{cplx<R>{(R)A.init_amp, R(0)}, cplx<R>{(R)A.init_amp, R(0)}};
     for (uint32_t pos = 2 * threadIdx.x; pos < M; pos += stride) *reinterpret_cast<cplx2<R>*>(T + lds_off(pos)) = v;
+    return;
+  }
+  if constexpr (sizeof(R) == 8) {
+    tile_load_c128(A, C, T);
     return;
   }
   const cplx<R>* __restrict__ psi = A.psi;
@@ -422,6 +448,29 @@ __device__ __forceinline__ double tile_store(const TileKArgs<R>& A, const Ctx& C
   // with the pass's butterfly normalisation
   const R sc = (R)A.scale;
   const bool do_scale = A.scale != 1.0;
+  if constexpr (sizeof(R) == 8) {
+    // complex128: one amplitude per lane and access (as in the load)
+    const uint32_t nthr = blockDim.x;
+    constexpr int K = 2 * kChunk;
+    for (uint32_t p0 = threadIdx.x; p0 < M; p0 += nthr * K) {
+      cplx<R> v[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t pos = p0 + nthr * k;
+        if (pos < M) v[k] = T[lds_off(pos)];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t pos = p0 + nthr * k;
+        if (pos < M) {
+          if (do_scale) v[k] = cscale(v[k], sc);
+          st_nt(psi + (C.base | C.dep(pos)), v[k]);
+          if (A.norm_part != nullptr) nacc += abs2_d(v[k]);
+        }
+      }
+    }
+    return nacc;
+  }
   if (M >= stride * kChunk) {
     for (uint32_t p0 = 2 * threadIdx.x; p0 < M; p0 += stride * kChunk) {
       cplx2<R> v[kChunk];
