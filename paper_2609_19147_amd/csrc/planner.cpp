@@ -1304,7 +1304,6 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
     }
     r.op_begin = (int32_t)T.ops.size();
     int prev_qft_bit = -1;
-    bool prev_fresh = false;
     for (int oi : ops) {
       const OpIR& o = P.ops[oi];
       TileOp op;
@@ -1321,9 +1320,10 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
       else if (o.kind == OP_QFT || o.kind == OP_QFT_INV) T.n_coef += 1 << op.rbit;
       if (o.kind == OP_QFT) {
         // exp(i pi low_p / 2^p) = (exp(i pi low_{p+1} / 2^{p+1}))^2 when bit p is a
-        // round bit (zero in the group base); square at most once in a row
-        op.square = (prev_qft_bit == o.bit + 1 && prev_fresh) ? 1 : 0;
-        prev_fresh = !op.square;
+        // round bit (zero in the group base): the round evaluates its first
+        // stage's twiddle and squares it for the next (at most three squarings
+        // in a row, each doubling the phase's relative rounding error)
+        op.square = (prev_qft_bit == o.bit + 1) ? 1 : 0;
         prev_qft_bit = o.bit;
       }
       if (o.kind == OP_H || o.kind == OP_QFT || o.kind == OP_QFT_INV) T.n_butterfly += 1;
