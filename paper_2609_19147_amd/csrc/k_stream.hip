@@ -81,6 +81,26 @@ __global__ void __launch_bounds__(kThreads) diag_kernel(cplx<R>* psi, uint64_t n
   cplx2<R>* __restrict__ p2 = reinterpret_cast<cplx2<R>*>(psi);
   constexpr int K = kDiagPairsPerThread;
   const uint64_t nchunks = npairs / (kThreads * K);
+  if constexpr (sizeof(R) == 8) {
+    if (nchunks > 0) {
+      // complex128: one 16-byte amplitude per lane and access; thread x owns
+      // amplitudes x + j kThreads of each chunk of 2 K kThreads
+      uint32_t off[2 * K];
+#pragma unroll
+      for (int j = 0; j < 2 * K; ++j) off[j] = (uint32_t)j * kThreads;
+      for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint64_t a0 = c * (uint64_t)(2 * K * kThreads) + threadIdx.x;
+        cplx<R> a[2 * K];
+#pragma unroll
+        for (int j = 0; j < 2 * K; ++j) a[j] = ld_nt(psi + a0 + (uint64_t)j * kThreads);
+        if (D.n_groups >= kDiagAngleGroups) diag_apply_total_angle<R, 2 * K>(a, (uint32_t)a0, off, D);
+        else diag_apply<R, 2 * K>(a, (uint32_t)a0, off, D);
+#pragma unroll
+        for (int j = 0; j < 2 * K; ++j) st_nt(psi + a0 + (uint64_t)j * kThreads, a[j]);
+      }
+      return;
+    }
+  }
   if (nchunks > 0) {
     // chunks of K * kThreads pairs: thread x owns pairs x + k kThreads, i.e.
     // amplitudes 2x | (j & 1) | (j >> 1) 2 kThreads of the chunk
