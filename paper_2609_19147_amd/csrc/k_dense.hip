@@ -122,9 +122,16 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
     for (uint32_t j = 0; j < G.n_free; ++j)
       if ((t >> j) & 1u) base |= 1u << G.free_bit[j];
     // load: tile bit 0 is state bit 0, so pairs (p, p + 1) are adjacent
-    for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
-      const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
-      *reinterpret_cast<cplx2<R>*>(T + dense_lds_off(p)) = ld_nt(reinterpret_cast<const cplx2<R>*>(psi + g));
+    if constexpr (sizeof(R) == 8 && K == 16) {
+      // complex128, k = 4 (K = 16, memory-bound): one 16-byte amplitude per lane and
+      // access (for k = 5 the extra address work costs more than it saves)
+      for (uint32_t p = threadIdx.x; p < M; p += kDenseThreads)
+        T[dense_lds_off(p)] = ld_nt(psi + (base | (p & Lmask) | hi_tab[p >> G.L]));
+    } else {
+      for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
+        const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
+        *reinterpret_cast<cplx2<R>*>(T + dense_lds_off(p)) = ld_nt(reinterpret_cast<const cplx2<R>*>(psi + g));
+      }
     }
     __syncthreads();
 
@@ -154,9 +161,14 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
         for (int v = 0; v < 4; ++v) T[dense_lds_off(drow[rt][v] | colp)] = cplx<R>{yr[rt][v], yi[rt][v]};
     }
     __syncthreads();
-    for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
-      const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
-      st_nt(reinterpret_cast<cplx2<R>*>(psi + g), *reinterpret_cast<const cplx2<R>*>(T + dense_lds_off(p)));
+    if constexpr (sizeof(R) == 8 && K == 16) {
+      for (uint32_t p = threadIdx.x; p < M; p += kDenseThreads)
+        st_nt(psi + (base | (p & Lmask) | hi_tab[p >> G.L]), T[dense_lds_off(p)]);
+    } else {
+      for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
+        const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
+        st_nt(reinterpret_cast<cplx2<R>*>(psi + g), *reinterpret_cast<const cplx2<R>*>(T + dense_lds_off(p)));
+      }
     }
     __syncthreads();
   }
