@@ -1303,7 +1303,7 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
       r.loff[j] = lds_off(o);
     }
     r.op_begin = (int32_t)T.ops.size();
-    int prev_qft_bit = -1;
+    int prev_qft_bit = -1, prev_qft_base = -1;
     for (int oi : ops) {
       const OpIR& o = P.ops[oi];
       TileOp op;
@@ -1320,11 +1320,15 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
       else if (o.kind == OP_QFT || o.kind == OP_QFT_INV) T.n_coef += 1 << op.rbit;
       if (o.kind == OP_QFT) {
         // exp(i pi low_p / 2^p) = (exp(i pi low_{p+1} / 2^{p+1}))^2 when bit p is a
-        // round bit (zero in the group base): the round evaluates its first
-        // stage's twiddle and squares it for the next (at most three squarings
-        // in a row, each doubling the phase's relative rounding error)
-        op.square = (prev_qft_bit == o.bit + 1) ? 1 : 0;
+        // round bit (zero in the group base) and both stages read the bits from
+        // the same base (low_q = the group bits in [base, q)): the round then
+        // evaluates its first stage's twiddle and squares it for the next (at
+        // most three squarings in a row, each doubling the phase's relative
+        // rounding error).  Stages with different bases (an approximate QFT,
+        // two QFTs on adjacent registers) evaluate their own.
+        op.square = (prev_qft_bit == o.bit + 1 && prev_qft_base == o.base) ? 1 : 0;
         prev_qft_bit = o.bit;
+        prev_qft_base = o.base;
       }
       if (o.kind == OP_H || o.kind == OP_QFT || o.kind == OP_QFT_INV) T.n_butterfly += 1;
       T.ops.push_back(op);

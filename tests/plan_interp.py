@@ -3,10 +3,16 @@
 Applies the layers exactly as the plan states them -- tile passes round by
 round, diagonal layers from their FP64 lookup tables, GF(2) gathers from
 their row masks -- so the planner's rewrite can be checked against the
-one-gate-at-a-time oracle on the CPU, without a GPU.  QFT stages use the
-plain stage definition (butterfly on bit p, then exp(i pi low / 2^p) on the
-bit-p = 1 half, low = the index bits in [base, p)).  Dense layers apply the matrix the plan carries;
-plain layers call the oracle's gate application.
+one-gate-at-a-time oracle on the CPU, without a GPU.  A QFT stage is a
+butterfly on bit p, then a twiddle on the bit-p = 1 half; the twiddle is
+formed the way the tile kernel forms it: a group factor (the index with the
+round's four bits cleared) times the plan's in-round coefficient E[k] (k =
+the round bits below the stage's register bit).  The group factor is
+exp(i pi low / 2^p), low = the group index bits in [base, p), or, where the
+plan flags the stage ``square``, the square of the previous stage's group
+factor -- so a wrong flag, or a wrong E table, shows up here as a wrong
+state.  Dense layers apply the matrix the plan carries; plain layers call the
+oracle's gate application.
 """
 from __future__ import annotations
 
@@ -94,10 +100,14 @@ def apply_layer(psi, n, L, stream, params):
     assert k == "tile"
     psi = psi.copy()
     r2 = 1 / math.sqrt(2)
+    i = np.arange(1 << n, dtype=np.int64)
     for R in L["rounds"]:
         if R["diag"] >= 0:
             ph = diag_phase(L["diags"][R["diag"]], n)
             psi *= np.conj(ph) if L.get("inverse") else ph
+        sbits = [tb if tb < L["L"] else L["a"] + (tb - L["L"]) for tb in R["tbits"]]
+        g = i & ~sum(1 << sb for sb in sbits)
+        w_prev = None
         for op in L["ops"][R["ops"][0]:R["ops"][1]]:
             b = op["bit"]
             c = [complex(a, bb) for a, bb in op.get("coef", [])]
@@ -107,20 +117,28 @@ def apply_layer(psi, n, L, stream, params):
                 apply_bit_2x2(psi, n, b, [[c[0], 0], [0, c[1]]])
             elif op["kind"] == 1:
                 apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
-            elif op["kind"] == 2:
-                apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
-                i = np.arange(1 << n, dtype=np.int64)
-                low = i & ((1 << b) - 1) & ~((1 << op.get("base", 0)) - 1)
-                tw = np.exp(1j * math.pi * low / (1 << b))
+            elif op["kind"] in (2, 4):
+                base = op.get("base", 0)
                 sel = ((i >> b) & 1) == 1
-                psi[sel] *= tw[sel]
-            elif op["kind"] == 4:  # inverse QFT stage: undo the twiddle, then the butterfly
-                i = np.arange(1 << n, dtype=np.int64)
-                low = i & ((1 << b) - 1) & ~((1 << op.get("base", 0)) - 1)
-                tw = np.exp(-1j * math.pi * low / (1 << b))
-                sel = ((i >> b) & 1) == 1
-                psi[sel] *= tw[sel]
-                apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
+                if c:
+                    if op["square"]:
+                        assert w_prev is not None, "square flag on a round's first stage"
+                        w = w_prev * w_prev
+                    else:
+                        w = np.exp(1j * math.pi * (g & ((1 << b) - 1) & ~((1 << base) - 1)) / (1 << b))
+                    w_prev = w
+                    kk = np.zeros_like(i)
+                    for r in range(op["rbit"]):
+                        kk |= ((i >> sbits[r]) & 1) << r
+                    tw = w * np.array(c)[kk]
+                else:  # unbound plan: the plain stage definition
+                    tw = np.exp(1j * math.pi * (i & ((1 << b) - 1) & ~((1 << base) - 1)) / (1 << b))
+                if op["kind"] == 2:
+                    apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
+                    psi[sel] *= tw[sel]
+                else:  # inverse QFT stage: undo the twiddle, then the butterfly
+                    psi[sel] *= np.conj(tw[sel])
+                    apply_bit_2x2(psi, n, b, [[r2, r2], [r2, -r2]])
             else:
                 raise AssertionError(f"unexpected op kind {op['kind']}")
     return psi

@@ -94,6 +94,24 @@ def test_tile_geometries(qs, tile_bits):
     compare(qs, st, sv.run(psi0, n, stream), "c64", n)
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("case", ["approx2", "approx5", "adjacent", "adjacent_then_full"])
+def test_approximate_and_register_qfts(qs, dtype, case):
+    # stages whose bases differ (approximate QFT: stage p reads bits [p - d, p);
+    # QFTs on neighbouring registers) share tile rounds; each computes its own
+    # group twiddle
+    n = 16
+    if case.startswith("approx"):
+        stream = W.qft_register_stream(range(n), int(case[-1]))
+    else:
+        hi, lo = W.qft_register_stream(range(7)), W.qft_register_stream(range(7, n))
+        stream = lo + hi + (W.qft_stream(n) if case == "adjacent_then_full" else [])
+    for tile_bits in (13, 7):
+        st, psi0 = start(qs, n, dtype, 8)
+        qs.apply(st, qs.Plan(n, stream, max_tile_bits=tile_bits))
+        compare(qs, st, sv.run(psi0, n, stream), dtype, n)
+
+
 def test_multi_qubit_and_controlled(qs):
     n = 11
     rng = np.random.default_rng(4)

@@ -236,7 +236,7 @@ def test_twiddle_squaring_stays_inside_a_round(tile_bits):
                 if op["square"]:
                     prev = [o for o in ops[:k] if o["kind"] == 2]
                     assert R["type"] in (1, 2), R
-                    assert prev and prev[-1]["bit"] == op["bit"] + 1 and not prev[-1]["square"]
+                    assert prev and prev[-1]["bit"] == op["bit"] + 1 and prev[-1]["base"] == op["base"]
 
 
 @pytest.mark.parametrize("case", ["qft", "mixed", "tfim", "hea", "perm", "xxyy"])
@@ -297,6 +297,33 @@ def test_qft_and_inverse_qft_on_an_upper_register(offset):
         stages = [o for o in ops if o["kind"] == kind]
         assert len(stages) >= t - 1 and all(o["base"] == offset for o in stages)
         assert "diag" not in kinds(d)
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("tile_bits", [6, 13])
+def test_approximate_qft(degree, tile_bits):
+    # stage p of an approximate QFT reads the bits [p - degree, p), so
+    # consecutive stages have different bases: a round may not square one
+    # stage's group twiddle into the next
+    n = 12
+    d = check_plan(n, W.qft_register_stream(range(n), degree), tol=1e-12, max_tile_bits=tile_bits)
+    stages = [o for L in d["layers"] for o in L.get("ops", []) if o["kind"] == 2]
+    if degree > 1:
+        assert len(stages) >= n - 1
+        assert any(o["base"] > 0 for o in stages)
+
+
+@pytest.mark.parametrize("split", [4, 6, 8])
+def test_qfts_on_adjacent_registers(split):
+    # a QFT on the upper qubits (bits [n - split, n)), then one on the lower
+    # qubits, then the lower register's QFT again before the upper one's:
+    # stages on neighbouring bits with different bases share rounds
+    n = 12
+    hi = W.qft_register_stream(range(split))
+    lo = W.qft_register_stream(range(split, n))
+    for stream in (hi + lo, lo + hi, lo + hi + W.qft_stream(n)):
+        check_plan(n, stream, tol=1e-12)
+        check_plan(n, stream, tol=1e-12, max_tile_bits=7)
 
 
 # ---------------------------------------------------------------- dense-window fusion

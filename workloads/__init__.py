@@ -126,6 +126,25 @@ def qft_stream(n: int) -> List[Gate]:
     return out
 
 
+def qft_register_stream(qubits: Sequence[int], degree: Optional[int] = None) -> List[Gate]:
+    """QFT stream on the listed qubits (most significant first), no swaps.
+
+    Same gate order as :func:`qft_stream`, with register position ``j``
+    standing for ``qubits[j]``.  ``degree`` keeps only the controlled phases
+    whose register distance ``k - j`` is at most ``degree`` (the approximate
+    QFT); ``None`` keeps them all.
+    """
+    out: List[Gate] = []
+    m = len(qubits)
+    for j in range(m):
+        out.append(G("H", qubits[j]))
+        for k in range(j + 1, m):
+            if degree is not None and k - j > degree:
+                break
+            out.append(G("CPHASE", qubits[k], qubits[j], theta=math.pi / (1 << (k - j))))
+    return out
+
+
 def wht_stream(n: int) -> List[Gate]:
     return [G("H", q) for q in range(n)]
 
