@@ -569,7 +569,7 @@ def manifest(qs, torch):
     return {"library": qs.version(), "git_rev": rev, "torch": torch.__version__, "hip": torch.version.hip,
             "device": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
             "device_memory_GiB": round(p.total_memory / 2 ** 30, 1), "host": platform.node(),
-            "host_cpus": os.cpu_count(), "state_seed": STATE_SEED, "block_seed": BLOCK_SEED,
+            "host_cpus": len(os.sched_getaffinity(0)), "state_seed": STATE_SEED, "block_seed": BLOCK_SEED,
             "timing": "HIP events on the library stream + host wall clock around K steps, synchronised"}
 
 
@@ -657,8 +657,12 @@ def main():
         from scipy.stats import t as student_t
         ci95 = float(student_t.ppf(0.975, args.steps - 1) * per_step.std(ddof=1) / math.sqrt(args.steps))
     ms_step = 1e3 * wall / args.steps
-    alg_bytes = n_pass * 2 * S + S
+    # effective bandwidth: passes used x 2S per step (the norm is summed by
+    # the last pass as it writes, so it moves no bytes of its own)
+    alg_bytes = n_pass * 2 * S
     value = alg_bytes / (wall / args.steps) / 1e9
+    # the same step counted as if the norm were a separate S-byte read
+    norm_inclusive = (alg_bytes + S) / (wall / args.steps) / 1e9
 
     # the achievable streaming ceiling: the library's own device copy of the
     # same state (2 S bytes per launch), timed with HIP events like the step
@@ -714,6 +718,7 @@ def main():
                                f"then FP64 norm", "n_qubits": n, "layers": kinds,
                    "gates": len(stream), "state_seed": STATE_SEED, "block_seed": BLOCK_SEED},
         "gate_stream_equiv_GBs": round(len(stream) * 2 * S / (wall / args.steps) / 1e9, 1),
+        "norm_inclusive_equiv_GBs": round(norm_inclusive, 1),
         "norm_after": nrm,
         "hbm_bytes_per_step": n_pass * 2 * S,
         "plan_ms": round(1e3 * t_plan, 2),

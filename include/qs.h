@@ -198,7 +198,12 @@ qs_status qs_plan_free(qs_plan* p);
 qs_status qs_plan_inverse(const qs_plan* p, qs_plan** out);
 
 /* Apply layers [first, first + count) of a plan to a state (asynchronous, on
- * the state's stream).  count = (size_t)-1 applies through the last layer. */
+ * the state's stream).  count = (size_t)-1 applies through the last layer.
+ * (Section "Hand-Tuned Metal Shaders": each fused layer is one kernel of the
+ * "Kernel Taxonomy"; the rewrite is the "Semantics-Preserving Fusion" one, so
+ * the result equals the gate-by-gate product up to rounding.)  QS_EINVAL when
+ * the plan's and the state's qubit counts differ or a parametrised plan has
+ * no bound parameters; nothing is applied then. */
 qs_status qs_apply_layer(qs_state* s, const qs_plan* p, size_t first, size_t count);
 /* Apply every layer of a plan through one HIP graph launch (asynchronous, on
  * the state's stream).  The plan's layer sequence is recorded as a graph on
@@ -217,13 +222,28 @@ qs_status qs_apply_graph(qs_state* s, const qs_plan* p);
  * first use (8 bytes per tile, or per wavefront of a gather, of the last
  * layer). */
 qs_status qs_apply_norm2(qs_state* s, const qs_plan* p, double* norm2);
-/* Plain per-gate path: one kernel per gate, no fusion (the baseline). */
+/* Plain per-gate path: one kernel per gate, no fusion (the baseline).  This
+ * is the paper's structured per-gate tier (Section "Same-Machine External
+ * Baselines": diagonal gates as broadcast phase multiplies, controlled
+ * single-qubit gates as half-state updates, SWAP as a permutation; Appendix
+ * "Pure MLX versus a Hand-Written Kernel", "The pure-MLX path": a single-qubit
+ * gate as the (A, 2, B) pair update).  gates / params: host arrays read during
+ * the call; every gate is validated before the first launch (QS_EINVAL). */
 qs_status qs_apply_gates(qs_state* s, const qs_gate* gates, size_t n_gates,
                          const double* params, size_t n_params);
 
 /* ---- reductions (FP64, compensated, deterministic) --------------------- */
+/* Section "State Management" (normalisation, probabilities and expectation
+ * values of Pauli observables) and Section "Independent complex128
+ * validation" (norm drift and infidelity against a reference).  Each
+ * amplitude is widened to FP64 and summed with Neumaier compensation per
+ * thread, then in a fixed order over threads and workgroups, so the results
+ * are bitwise repeatable.  They synchronise the state's stream. */
 
-/* sum_t coeff_t <psi|P_t|psi>; per_term (nullable) receives each term. */
+/* sum_t coeff_t <psi|P_t|psi> (host terms[n_terms], read during the call);
+ * per_term (nullable, host, n_terms doubles) receives each term's
+ * <psi|P_t|psi> times coeff_t, total (host) the sum.  Not normalised by
+ * ||psi||^2. */
 qs_status qs_expect(qs_state* s, const qs_pauli* terms, size_t n_terms,
                     double* per_term, double* total);
 qs_status qs_norm2(qs_state* s, double* out);
@@ -252,6 +272,13 @@ qs_status qs_sample(qs_state* s, const double* u, size_t count, uint64_t* out);
 qs_status qs_marginal(qs_state* s, uint64_t qubit_mask, double* out);
 
 /* ---- adjoint gradients -------------------------------------------------- */
+/* The adjoint method is this library's addition.  The paper differentiates
+ * its variational ansatz by parameter shift (Section "Algorithm
+ * Implementations": parameter-shift gradients with Adam), which costs two
+ * circuits per parameter (Section "Detailed Algorithm Performance", the
+ * ansatz scaling table, which names automatic differentiation as the way to
+ * extend that range).  This call returns the same gradient, exact up to
+ * rounding, from one forward and one backward sweep. */
 
 /* Energy E = <psi_L|H|psi_L> and dE/dparams of the plan applied to the given
  * state (in: initial state; out: the final state psi_L).  Uses the adjoint
@@ -268,6 +295,14 @@ qs_status qs_adjoint_grad(qs_state* psi, const qs_plan* p, const qs_pauli* terms
                           size_t n_terms, double* energy, double* grad, size_t n_params);
 
 /* ---- batches of circuits (many states, one graph launch) ---------------- */
+/* Batching is this library's addition for the launch-bound regime the paper
+ * reports (Section "Background", "GPU Acceleration Paradigms": gate batching
+ * to amortise overhead; Section "Limitations and Future Work" and the
+ * QASM sweep of Appendix "Complete Per-Workload Speedups": below ~15 qubits
+ * a circuit sits at kernel-launch overhead).  The instances are typically the
+ * QAOA ansatz of Section "Algorithm Implementations" (cost layer
+ * e^{-i gamma H_C}, mixer e^{-i beta H_M}, from |+>^n) on different graphs,
+ * sizes and angles. */
 
 /* A batch owns n_inst states (qubit counts n_qubits[i], one device arena) and
  * one plan per instance (plans[i], borrowed, must outlive the batch, all with

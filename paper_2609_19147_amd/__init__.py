@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes as C
 import json
+import weakref
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -386,25 +387,47 @@ def adjoint_grad(state: State, plan: Plan, terms):
     return e.value, g
 
 
+# One state per (plan, dtype) for energy_function: made on the first forward
+# and reset to |0...0> on every later one, so that repeated evaluations (an
+# optimisation loop) allocate no device memory; it lives as long as the plan.
+_energy_states = weakref.WeakKeyDictionary()
+
+
+def _energy_state(plan: Plan, dtype: str) -> State:
+    per = _energy_states.get(plan)
+    if per is None:
+        per = _energy_states[plan] = {}
+    st = per.get(dtype)
+    if st is None:
+        st = per[dtype] = State(plan.n, dtype, init=None)
+    return st.set_basis(0)
+
+
 def energy_function():
     """torch.autograd.Function computing E(params) = <psi(params)|H|psi(params)>
-    from |0...0> with the adjoint backward of the library."""
+    from |0...0> with the adjoint backward of the library.  The gradient is
+    computed in the forward call only when ``params`` requires one; it has the
+    shape of ``params``."""
     import torch
 
     class QsEnergy(torch.autograd.Function):
         @staticmethod
         def forward(ctx, params, plan, terms, dtype="c64"):
-            p = params.detach().to("cpu", torch.float64).numpy()
+            p = params.detach().to("cpu", torch.float64).numpy().ravel()
             plan.set_params(p)
-            st = State(plan.n, dtype, init="zero")
-            e, g = adjoint_grad(st, plan, terms)
-            ctx.save_for_backward(torch.as_tensor(g, dtype=params.dtype, device=params.device))
+            st = _energy_state(plan, dtype)
+            if ctx.needs_input_grad[0]:
+                e, g = adjoint_grad(st, plan, terms)
+                ctx.grad = torch.as_tensor(g.reshape(params.shape), dtype=params.dtype, device=params.device)
+            else:
+                apply(st, plan)
+                e = expect(st, terms)
+                ctx.grad = None
             return torch.tensor(e, dtype=params.dtype, device=params.device)
 
         @staticmethod
         def backward(ctx, grad_out):
-            (g,) = ctx.saved_tensors
-            return grad_out * g, None, None, None
+            return grad_out * ctx.grad, None, None, None
 
     return QsEnergy
 

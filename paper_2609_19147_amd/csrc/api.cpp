@@ -426,6 +426,7 @@ extern "C" qs_status qs_apply_gates(qs_state* s, const qs_gate* gates, size_t n_
     auto g = normalise_gates(s->n, gates, n_gates, n_params);
     if (n_params && !params) fail(QS_EINVAL, "params is NULL");
     std::vector<double> pv(params, params + n_params);
+    s->plain_acc = NormAcc{};  // the rounding compensation restarts with every call
     for (auto& ng : g) apply_plain_gate(*s, ng, pv);
   });
 }

@@ -80,9 +80,47 @@ void round_pair_table(const DiagNumeric& num, const std::vector<PairNeighbours>&
   }
 }
 
+// The rotations and 2x2 unitaries a tile pass applies, rounded to float in
+// round order with the plan's running norm compensation (fround.h); the
+// entries were first rounded one by one (phases to unit modulus).
+template <class R>
+void round_pass_unitaries(const TilePassIR& T, const std::vector<TileRound>& rounds, const std::vector<cd>& coef,
+                          std::vector<cplx<R>>& cr, NormAcc& acc) {
+  auto mat2 = [&](int off) {
+    if (off < 0 || (size_t)off + 4 > coef.size()) return;
+    cplx<float> f[4];
+    fround_unitary2(&coef[off], f, acc);
+    for (int e = 0; e < 4; ++e) cr[off + e] = {(R)f[e].re, (R)f[e].im};
+  };
+  for (const TileRound& r : rounds) {
+    if (r.type == RT_MAT4) {
+      for (int bb = 0; bb < 4; ++bb) mat2(r.coef4 + 4 * bb);
+    } else if (r.type == RT_MAT4_RX || r.type == RT_MAT4_RY) {
+      for (int bb = 0; bb < 4; ++bb) {
+        const cplx<float> f = fround_pair(coef[r.coef4 + bb], acc);
+        cr[r.coef4 + bb] = {(R)f.re, (R)f.im};
+      }
+    } else {
+      for (int k = r.op_begin; k < r.op_end; ++k) {
+        const TileOp& op = T.ops[k];
+        if (op.kind == OP_MAT) {
+          mat2(op.coef);
+        } else if (op.kind == OP_DIAG) {
+          const cd D[4] = {coef[op.coef], 0.0, 0.0, coef[op.coef + 1]};
+          cplx<float> f[4];
+          fround_unitary2(D, f, acc);
+          cr[op.coef] = {(R)f[0].re, (R)f[0].im};
+          cr[op.coef + 1] = {(R)f[3].re, (R)f[3].im};
+        }
+      }
+    }
+  }
+}
+
 template <class R>
 void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
   const PlanIR& P = p.ir;
+  NormAcc acc;
   d.diag_terms.assign(P.diags.size(), 0);
   d.diag_groups.assign(P.diags.size(), 0);
   d.diag_lut.assign(P.diags.size(), 0);
@@ -96,7 +134,7 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
     pns.push_back(pair_neighbours(num, P.n));
     d.diag_terms[i] = b.put(num.terms);
     d.diag_groups[i] = b.put(num.groups);
-    d.diag_lut[i] = b.put(cast<R>(num.lut));
+    d.diag_lut[i] = b.put(round_entries<R>(num.lut));
     d.diag_ngroups[i] = (int)num.groups.size();
     d.diag_theta[i] = b.put(num.theta);
     d.diag_global[i] = num.global;
@@ -137,7 +175,9 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
     if (!qtab.empty()) d.pass_qtab[i] = b.put(qtab);
     d.pass_rounds[i] = b.put(rounds);
     d.pass_ops[i] = b.put(T.ops);
-    d.pass_coef[i] = b.put(cast<R>(coef));
+    std::vector<cplx<R>> cr = round_entries<R>(coef);
+    if (sizeof(R) == sizeof(float)) round_pass_unitaries(T, rounds, coef, cr, acc);
+    d.pass_coef[i] = b.put(cr);
     // slot descriptors hold device addresses: filled in once the blob has one
     if (!T.diag_slots.empty()) d.pass_diag[i] = b.put(std::vector<DiagDev>(T.diag_slots.size()));
   }
@@ -299,7 +339,7 @@ void plain_t(qs_state& s, const NGate& g, const std::vector<double>& params, boo
   const int n = s.n;
   std::vector<cd> M = gate_matrix(g, params);
   if (inverse) M = dagger(M, 1 << (int)g.bits.size());
-  std::vector<cplx<R>> m = cast<R>(M);
+  std::vector<cplx<R>> m = round_gate<R>(M, 1 << (int)g.bits.size(), s.plain_acc);
   const auto& b = g.bits;
   switch (g.kind) {
     case QS_GATE_I:
@@ -374,6 +414,7 @@ double distance_t(qs_state& a, qs_state& b, double ar, double ai, double bs) {
 }  // namespace
 
 void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last) {
+  s.plain_acc = NormAcc{};  // plain layers' rounding compensation restarts with every call
   if (s.dtype == QS_C64) apply_layers_t<float>(s, p, first, last);
   else apply_layers_t<double>(s, p, first, last);
 }

@@ -8,6 +8,7 @@
 #include <memory>
 #include <vector>
 
+#include "fround.h"
 #include "kernels.h"
 #include "planner.h"
 #include "qs.h"
@@ -38,6 +39,7 @@ struct qs_state {
   std::vector<PlanGraphEntry> graphs;  // recorded plans, most recent last
   hipStream_t capture_stream = nullptr;  // private stream graphs are recorded on
   void* matbuf = nullptr;  // device staging for dense plain gates
+  qs::NormAcc plain_acc;   // norm compensation of the per-gate path's complex64 rounding
   // adjoint sweeps: the two work states (phi, lambda) and a device scratch
   // area, made by the first call and kept until the state is freed
   std::unique_ptr<qs_state> work[2];

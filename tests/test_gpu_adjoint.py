@@ -1,5 +1,7 @@
 """Adjoint-method gradients on the GPU against the oracle's parameter-shift
-gradients (tolerances: complex64 1e-5, complex128 1e-11 on every component)."""
+gradients (tolerances: complex64 1e-5, complex128 1e-11 on every component)
+and against the oracle's central finite differences (h = 1e-5: complex64
+1e-5, complex128 1e-8, the finite-difference error bar)."""
 import math
 
 import numpy as np
@@ -47,6 +49,36 @@ def test_hea_xxz_gradients_match_parameter_shift(qs, dtype, tol):
     assert metrics.infidelity(st.download(), ref) < (1e-10 if dtype == "c64" else 1e-24)
 
 
+@pytest.fixture(scope="module")
+def hea12_reference():
+    """The 24-qubit adjoint configuration's ansatz at 12 qubits (8 layers of
+    RY, RZ on every qubit and the CNOT ladder, 192 parameters U[-pi, pi],
+    seed 24, XXZ with Jz = 0.5): the oracle's energy, parameter-shift and
+    central finite-difference gradients (385 + 384 circuits)."""
+    n, layers = 12, 8
+    stream = W.hea_stream(n, layers)
+    params = W.hea_params(n, layers, 24)
+    terms = W.xxz_terms(n, 0.5)
+    e = gradients.energy(n, stream, params, terms)
+    ps = gradients.parameter_shift(n, stream, params, terms)
+    fd = gradients.finite_differences(n, stream, params, terms, h=1e-5)
+    return n, stream, params, terms, e, ps, fd
+
+
+@pytest.mark.parametrize("dtype,tol_ps,tol_fd", [("c64", 1e-5, 1e-5), ("c128", 1e-11, 1e-8)])
+def test_config_ansatz_at_12_qubits_against_parameter_shift_and_finite_differences(
+        qs, hea12_reference, dtype, tol_ps, tol_fd):
+    n, stream, params, terms, e_ref, ps, fd = hea12_reference
+    assert np.max(np.abs(ps - fd)) < 1e-8  # the two oracle gradients agree first
+    for tile_bits in (0, 9):
+        plan = qs.Plan(n, stream, n_params=len(params), params=params, max_tile_bits=tile_bits)
+        st = qs.State(n, dtype)
+        e, g = qs.adjoint_grad(st, plan, terms)
+        assert abs(e - e_ref) < tol_ps
+        assert np.max(np.abs(g - ps)) < tol_ps, np.max(np.abs(g - ps))
+        assert np.max(np.abs(g - fd)) < tol_fd, np.max(np.abs(g - fd))
+
+
 def test_small_tiles_and_rx_windows(qs):
     n, layers = 9, 3
     stream = []
@@ -85,6 +117,19 @@ def test_torch_autograd_function(qs):
     g_ref = gradients.parameter_shift(n, stream, params.detach().numpy(), terms)
     assert abs(E.item() - gradients.energy(n, stream, params.detach().numpy(), terms)) < 1e-12
     assert np.max(np.abs(params.grad.numpy() - g_ref)) < 1e-11
+    # parameters of any shape (the gradient takes it); the state is reused by
+    # later calls, which start from |0...0> again; no gradient under no_grad
+    shaped = params.detach().reshape(layers, n, 2).clone().requires_grad_(True)
+    for _ in range(2):
+        E2 = qs.energy_function().apply(shaped, plan, terms, "c128")
+        E2.backward()
+        assert E2.item() == E.item()
+        assert shaped.grad.shape == shaped.shape
+        assert np.max(np.abs(shaped.grad.numpy().ravel() - g_ref)) < 1e-11
+        shaped.grad = None
+    with torch.no_grad():
+        E3 = qs.energy_function().apply(shaped, plan, terms, "c128")
+    assert abs(E3.item() - E.item()) < 1e-13 and not E3.requires_grad
 
 
 def test_inverse_plan_on_device(qs):

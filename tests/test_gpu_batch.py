@@ -89,6 +89,114 @@ def test_p1_closed_form_whole_batch(qs):
         assert abs(got[k] - ref) < 2e-5, (k, got[k], ref)
 
 
+def tuner_candidates(n):
+    """The tile limits the benchmark's autotuner chooses among for an
+    n-qubit QAOA instance (two equal tile groups per instance, +-3 bits)."""
+    mid = max(6, min(14, (n + 4) // 2))
+    return list(range(max(8, mid - 3), min(14, n - 2) + 1))
+
+
+def test_p1_closed_form_all_512_config_instances(qs):
+    # every instance of the 512-instance configuration (16-24 qubits), cut to
+    # its first layer, in one batch; the instances of each size cycle through
+    # every tile limit the autotuner may pick for that size (13- and 14-bit
+    # batched tiles with the cut diagonal at 22 and 24 qubits among them)
+    from tests.test_oracle_pins import qaoa_p1_edge
+    insts = W.qaoa_instances(512, 512, depth=4)
+    seen = {}
+    plans, tiles = [], set()
+    for inst in insts:
+        cands = tuner_candidates(inst.n)
+        tb = cands[seen.get(inst.n, 0) % len(cands)]
+        seen[inst.n] = seen.get(inst.n, 0) + 1
+        tiles.add((inst.n, tb))
+        p1 = W.QaoaInstance(inst.n, inst.edges, inst.gammas[:1], inst.betas[:1])
+        plans.append(qs.Plan(inst.n, W.qaoa_stream(p1, param_offset=0, h_layer=False), n_params=2,
+                             max_tile_bits=tb, params=[inst.gammas[0], inst.betas[0]]))
+    assert (22, 13) in tiles and (24, 13) in tiles and (24, 14) in tiles
+    B = qs.Batch(plans, init="plus")
+    B.set_observables([W.maxcut_terms(i.edges) for i in insts])
+    B.run()
+    got = B.expect_stored()
+    norms = B.expect_diag([[(1.0, 0, 0)]] * len(insts))
+    err = np.empty(len(insts))
+    err_n = np.empty(len(insts))
+    for k, inst in enumerate(insts):
+        adj = {q: set() for q in range(inst.n)}
+        for u, v in inst.edges:
+            adj[u].add(v)
+            adj[v].add(u)
+        ref = sum(qaoa_p1_edge(adj, u, v, inst.gammas[0], inst.betas[0]) for u, v in inst.edges)
+        err[k] = got[k] - ref
+        err_n[k] = got[k] / norms[k] - ref
+    k = int(np.argmax(np.abs(err)))
+    print(f"p=1 closed form, 512 instances: max |<C> - closed form| = {abs(err[k]):.3e} "
+          f"(instance {k}, n = {insts[k].n}); normalised {np.max(np.abs(err_n)):.3e}; "
+          f"max |norm - 1| = {np.max(np.abs(norms - 1)):.3e}")
+    assert np.max(np.abs(err)) < 2e-5
+    assert np.max(np.abs(err_n)) < 2e-5
+
+
+@pytest.fixture(scope="module")
+def qaoa_p4_golden():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "qaoa_p4_22q_24q.json")) as fh:
+        rec = json.load(fh)
+    insts = W.qaoa_instances(rec["workload"]["instances"], rec["workload"]["seed"], rec["workload"]["depth"])
+    out = []
+    for r in rec["instances"]:
+        inst = insts[r["position"]]
+        assert inst.n == r["n"] and [list(e) for e in inst.edges] == r["edges"]
+        assert np.array_equal(inst.gammas, r["gammas"]) and np.array_equal(inst.betas, r["betas"])
+        amp = np.array(r["sample_re"]) + 1j * np.array(r["sample_im"])
+        out.append((inst, r["cut"], np.array(r["sample_idx"], dtype=np.int64), amp))
+    return out
+
+
+def test_p4_config_instances_22q_24q_against_stored_oracle_runs(qs, qaoa_p4_golden):
+    """Two 22-qubit and two 24-qubit instances of the 512-instance p = 4
+    configuration, through the batched graph (every autotuner tile limit),
+    the per-instance fused plan and the plain per-gate path, against the
+    oracle's stored <C> and sampled amplitudes.  Every path is held to
+    |<C> - <C>_ref| < 2e-5 both as computed and normalised, and to a norm
+    drift below 1e-6: the complex64 rotations are rounded so that their norm
+    deviations cancel along the plan (or the call, on the per-gate path)
+    instead of adding up over the 96 equal-angle mixer rotations."""
+    report = []
+    for inst, cut_ref, idx, amp_ref in qaoa_p4_golden:
+        prm = np.empty(8)
+        prm[0::2] = inst.gammas
+        prm[1::2] = inst.betas
+        stream = W.qaoa_stream(inst, param_offset=0, h_layer=False)
+        obs = W.maxcut_terms(inst.edges)
+        runs = []
+        plans = [qs.Plan(inst.n, stream, n_params=8, max_tile_bits=tb, params=prm)
+                 for tb in tuner_candidates(inst.n)]
+        B = qs.Batch(plans, init="plus")
+        B.run()
+        for k, c in enumerate(B.expect_diag([obs] * len(plans))):
+            runs.append((f"batched tb={tuner_candidates(inst.n)[k]}", c, B.state(k)))
+        st = qs.State(inst.n, "c64", init="plus")
+        qs.apply(st, plans[-1])
+        runs.append(("fused", qs.expect(st, obs), st))
+        sp = qs.State(inst.n, "c64", init="plus")
+        qs.apply_gates(sp, W.qaoa_stream(inst, h_layer=False))
+        runs.append(("plain", qs.expect(sp, obs), sp))
+        for name, c, state in runs:
+            nrm = qs.norm2(state)
+            got = qs.amplitudes(state, idx)
+            rel = np.linalg.norm(got / math.sqrt(nrm) - amp_ref) / np.linalg.norm(amp_ref)
+            report.append((inst.n, name, c - cut_ref, c / nrm - cut_ref, nrm - 1.0, rel))
+            assert abs(c / nrm - cut_ref) < 2e-5, report[-1]
+            assert abs(c - cut_ref) < 2e-5, report[-1]
+            assert abs(nrm - 1.0) < 1e-6, report[-1]
+            assert rel < 1e-5, report[-1]
+        del B
+    for r in report:
+        print("n=%d %-14s d<C>=%+.3e  d<C>/norm=%+.3e  norm-1=%+.3e  rel L2=%.2e" % r)
+
+
 def test_batch_rejects_permutation_layers(qs):
     p = qs.Plan(6, W.ghz_stream(6))
     with pytest.raises(qs.QsError) as e:
