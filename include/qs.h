@@ -265,6 +265,18 @@ qs_status qs_amplitudes(qs_state* s, const uint64_t* idx, size_t count, void* ho
  * so equal inputs give equal draws.  A drawn index always has p_i > 0.
  * QS_EINVAL for u outside [0, 1) or a state without mass (nothing is drawn). */
 qs_status qs_sample(qs_state* s, const double* u, size_t count, uint64_t* out);
+/* qs_sample without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same draws, bit for bit, with the norm reduction's partials,
+ * the cumulative sums and the staged uniforms and indices held in a static
+ * device array of the library (about 9.6 MB per GPU, kept until the process
+ * ends; looked up once per device on the first call there).  u and out are
+ * host arrays of count entries, as for qs_sample.  Limits: at most 26 qubits
+ * and at most 65536 draws per call; larger requests give QS_EINVAL before any
+ * device work.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (concurrent threads or streams) race and must be
+ * serialised by the caller. */
+qs_status qs_sample_noalloc(qs_state* s, const double* u, size_t count, uint64_t* out);
 /* Marginal distribution (unnormalised: sums of |psi_i|^2, FP64) over the
  * qubits set in qubit_mask (bit q = qubit q, at most 16 of them) into out
  * (host, 2^k doubles).  Bin index: the selected qubits read as a sub-register,

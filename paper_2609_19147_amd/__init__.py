@@ -364,6 +364,17 @@ def sample(state: State, u) -> np.ndarray:
     return out
 
 
+def sample_noalloc(state: State, u) -> np.ndarray:
+    """As sample(), through the allocation-free entry point (static device
+    scratch; at most 26 qubits and 65536 draws per call)."""
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).ravel())
+    out = np.empty(uu.size, dtype=np.uint64)
+    if uu.size:
+        check(lib().qs_sample_noalloc(state.h, uu.ctypes.data_as(C.POINTER(C.c_double)), uu.size,
+                                      out.ctypes.data_as(C.POINTER(C.c_uint64))))
+    return out
+
+
 def marginal(state: State, qubits) -> np.ndarray:
     """Unnormalised marginal over the given qubits (at most 16): 2^k FP64 sums,
     the lowest-numbered qubit most significant in the bin index."""

@@ -75,6 +75,7 @@ _SIGS = {
     "qs_infidelity": ([P, P, C.POINTER(C.c_double)], C.c_int),
     "qs_amplitudes": ([P, C.POINTER(C.c_uint64), SZ, P], C.c_int),
     "qs_sample": ([P, C.POINTER(C.c_double), SZ, C.POINTER(C.c_uint64)], C.c_int),
+    "qs_sample_noalloc": ([P, C.POINTER(C.c_double), SZ, C.POINTER(C.c_uint64)], C.c_int),
     "qs_marginal": ([P, C.c_uint64, C.POINTER(C.c_double)], C.c_int),
     "qs_adjoint_grad": ([P, P, C.POINTER(QsPauli), SZ, C.POINTER(C.c_double), C.POINTER(C.c_double), SZ],
                         C.c_int),

@@ -538,6 +538,41 @@ extern "C" qs_status qs_sample(qs_state* s, const double* u, size_t count, uint6
   });
 }
 
+// The same draws as qs_sample, with every device buffer in the library's
+// static per-GPU scratch: no device memory is allocated or freed.
+extern "C" qs_status qs_sample_noalloc(qs_state* s, const double* u, size_t count, uint64_t* out) {
+  return guarded([&] {
+    check_state(s);
+    if (count == 0) return;
+    if (!u || !out) fail(QS_EINVAL, "NULL argument");
+    if (s->n > kNoAllocSampleMaxQubits)
+      fail(QS_EINVAL, "qs_sample_noalloc: the state has " + std::to_string(s->n) + " qubits; its static scratch "
+                      "holds the sums of at most " + std::to_string(kNoAllocSampleMaxQubits) + " qubits");
+    if (count > kNoAllocSampleMaxDraws)
+      fail(QS_EINVAL, "qs_sample_noalloc: " + std::to_string(count) + " draws requested; at most " +
+                      std::to_string(kNoAllocSampleMaxDraws) + " per call");
+    for (size_t k = 0; k < count; ++k)
+      if (!(u[k] >= 0.0 && u[k] < 1.0)) fail(QS_EINVAL, "uniform numbers must lie in [0, 1)");
+    const NoAllocSampleScratch S = noalloc_sample_scratch(s->device);
+    const uint64_t N = 1ull << s->n;
+    if (s->dtype == QS_C64)
+      launch_norm2<float>((const cplx<float>*)s->cur_ptr(), N, S.norm_partials, S.norm_out, s->stream);
+    else
+      launch_norm2<double>((const cplx<double>*)s->cur_ptr(), N, S.norm_partials, S.norm_out, s->stream);
+    double nrm = 0.0;
+    check_hip(hipMemcpyAsync(&nrm, S.norm_out, sizeof nrm, hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+    s->sync();
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) fail(QS_EINVAL, "the state has no probability mass");
+    check_hip(hipMemcpyAsync(S.u, u, count * 8, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+    if (s->dtype == QS_C64)
+      launch_sample<float>((const cplx<float>*)s->cur_ptr(), s->n, S.u, count, S.out, S.sums, s->stream);
+    else
+      launch_sample<double>((const cplx<double>*)s->cur_ptr(), s->n, S.u, count, S.out, S.sums, s->stream);
+    check_hip(hipMemcpyAsync(out, S.out, count * 8, hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+    s->sync();
+  });
+}
+
 extern "C" qs_status qs_marginal(qs_state* s, uint64_t qubit_mask, double* out) {
   return guarded([&] {
     check_state(s);

@@ -12,7 +12,14 @@
 // sub-block sums and finally the sub-block's 64 probabilities.
 #include "kernels.h"
 
+#include <mutex>
+#include <string>
+
+#include "planner.h"
+
 namespace qs {
+
+void check_hip(hipError_t e, const char* what);
 
 namespace {
 
@@ -233,9 +240,9 @@ size_t sample_scratch_doubles(int n) {
 
 template <class R>
 void launch_sample(const cplx<R>* psi, int n, const double* u_dev, uint64_t count, uint64_t* out_dev,
-                   double* scratch, hipStream_t s) {
+                   double* work, hipStream_t s) {
   const SampleGeom G = sample_geometry(n);
-  double* sub = scratch;
+  double* sub = work;
   double* blk = sub + G.n_sub;
   double* P = blk + G.n_blk;
   QS_LAUNCH("sample_sub_sums", s, sub_sums_kernel<R>, dim3(grid_of(G.n_sub, kSampThreads / 64, 65536)),
@@ -247,6 +254,49 @@ void launch_sample(const cplx<R>* psi, int n, const double* u_dev, uint64_t coun
     QS_LAUNCH("sample_draw", s, sample_kernel<R>, dim3(grid_of(count, kSampThreads / 64, 1u << 30)),
               dim3(kSampThreads), 0, s, psi, sub, P, G.n_blk, G.subs_per_block, G.sub_len, u_dev, count,
               out_dev);
+}
+
+// ---- allocation-free sampling ----------------------------------------------
+// Static scratch of qs_sample_noalloc, one copy per GPU (kept until the
+// process ends): nothing in it needs clearing, since every region is written
+// before it is read within a call.  Calls that overlap on one GPU share it.
+namespace {
+constexpr size_t kNaNormDoubles = 2 * (size_t)kRedBlocks + 8;
+constexpr size_t kNaSumDoubles = ((size_t)1 << (kNoAllocSampleMaxQubits - 6)) +
+                                 2 * ((size_t)1 << (kNoAllocSampleMaxQubits - 14)) + 1;
+constexpr size_t kNaDoubles = kNaNormDoubles + kNaSumDoubles + 2 * kNoAllocSampleMaxDraws;
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+double* g_na_ptr[kNaMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+NoAllocSampleScratch noalloc_sample_scratch(int device) {
+  if (device < 0 || device >= kNaMaxDevices) fail(QS_EINVAL, "device ordinal out of range");
+  double* base;
+  {
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[device]) {
+      // the array's address differs per device: look it up with that device current
+      int prev = 0;
+      check_hip(hipGetDevice(&prev), "hipGetDevice");
+      if (prev != device) check_hip(hipSetDevice(device), "hipSetDevice");
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (prev != device) (void)hipSetDevice(prev);
+      check_hip(e, "hipGetSymbolAddress(scratch)");
+      g_na_ptr[device] = (double*)p;
+    }
+    base = g_na_ptr[device];
+  }
+  NoAllocSampleScratch S;
+  S.norm_partials = base;
+  S.norm_out = base + 2 * (size_t)kRedBlocks;
+  S.sums = base + kNaNormDoubles;
+  S.u = S.sums + kNaSumDoubles;
+  S.out = (uint64_t*)(S.u + kNoAllocSampleMaxDraws);
+  return S;
 }
 
 size_t marginal_partials(const MarginalArgs& A) { return ((size_t)1 << A.k) * A.chunks; }

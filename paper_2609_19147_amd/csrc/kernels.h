@@ -157,6 +157,25 @@ size_t sample_scratch_doubles(int n);
 template <class R>
 void launch_sample(const cplx<R>* psi, int n, const double* u_dev, uint64_t count, uint64_t* out_dev,
                    double* scratch, hipStream_t s);
+
+// Allocation-free sampling (qs_sample_noalloc): its scratch is one static
+// device array per GPU, sized for states of up to kNoAllocSampleMaxQubits
+// qubits and kNoAllocSampleMaxDraws draws per call.  Layout (doubles): the
+// norm reduction's partials (2 kRedBlocks) and result (8), the sampling sums
+// of a kNoAllocSampleMaxQubits-qubit state, the uniforms, the drawn indices.
+constexpr int kNoAllocSampleMaxQubits = 26;
+constexpr uint64_t kNoAllocSampleMaxDraws = 1ull << 16;
+struct NoAllocSampleScratch {
+  double* norm_partials;
+  double* norm_out;
+  double* sums;
+  double* u;
+  uint64_t* out;
+};
+// The array's device address on `device` (looked up with that device current
+// on the first call for it, then cached); fails with QS_EDEVICE if the lookup
+// fails.
+NoAllocSampleScratch noalloc_sample_scratch(int device);
 // Marginal over k <= 16 state bits sel[0] < sel[1] < ...: out[bin] (device),
 // bin bit j = state bit sel[j].
 struct MarginalArgs {
