@@ -128,6 +128,12 @@ typedef struct {
   int32_t low_bits;         /* contiguous low state bits of a tile pass over high bits
                                (runs of 2^low_bits amplitudes in HBM): 0 = per group, the
                                tile's remaining bits (at least 4); 2..8 = fixed */
+  int32_t coset_order;      /* which coset of its tile bits each workgroup of a tile pass
+                               takes: 0 = by geometry (contiguous tiles and tiles with runs
+                               of at most 16 amplitudes XCD-blocked, longer runs in launch
+                               order), 1 = XCD-blocked (each of the 8 XCDs a contiguous
+                               range of cosets), 2 = launch order (the workgroups resident
+                               at one time, on all XCDs, take neighbouring cosets) */
 } qs_plan_opts;
 
 typedef struct qs_state qs_state;

@@ -16,6 +16,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libqs.so")
+# standalone streaming-ceiling probe (bench.py runs it beside the benchmark)
+PROBE_SRC = os.path.join(CSRC, "ceiling_probe.hip")
+PROBE = os.path.join(PKG, "ceiling_probe")
 
 SOURCES = ["planner.cpp", "api.cpp", "runtime.cpp", "adjoint.cpp", "batch.cpp",
            "k_tile.hip", "k_dense.hip", "k_sample.hip", "k_stream.hip", "k_plain.hip", "k_reduce.hip"]
@@ -44,10 +47,22 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
+def build_probe() -> str:
+    tmp = PROBE + ".tmp"
+    cmd = [hipcc(), "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", *DEVICE_FLAGS, PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for ceiling_probe.hip:\n{r.stderr[-6000:]}")
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES) + 1)) as ex:
+        probe = ex.submit(build_probe)
         objs = list(ex.map(lambda s: _compile(s, list(extra)), SOURCES))
+        probe.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

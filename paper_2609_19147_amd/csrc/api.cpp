@@ -319,6 +319,8 @@ extern "C" qs_status qs_plan_create(int n, const qs_gate* gates, size_t n_gates,
       if (opts->window_k) o.window_k = opts->window_k;
       if (opts->low_bits && (opts->low_bits < 2 || opts->low_bits > 8)) fail(QS_EINVAL, "low_bits must be 0 or 2..8");
       if (opts->low_bits) low = opts->low_bits;
+      if (opts->coset_order < 0 || opts->coset_order > 2) fail(QS_EINVAL, "coset_order must be 0, 1 or 2");
+      o.coset_order = opts->coset_order;
     }
     int tb = o.max_tile_bits ? o.max_tile_bits : 13;
     if (tb < kRoundBits + 1 || tb > kMaxTileBits) fail(QS_EINVAL, "max_tile_bits out of range");

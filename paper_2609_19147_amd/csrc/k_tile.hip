@@ -522,7 +522,7 @@ __device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t 
 
 template <class R, bool kDiag>
 __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
-  tile_body<R, kDiag>(A, xcd_block(blockIdx.x, gridDim.x));
+  tile_body<R, kDiag>(A, A.order ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x));
 }
 
 // complex64 passes without diagonal layers: registers capped at 128 so that
@@ -530,7 +530,91 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
 // or four of 2^12, share a CU's LDS).
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 tile_kernel_c64(TileKArgs<float> A) {
-  tile_body<float, false>(A, xcd_block(blockIdx.x, gridDim.x));
+  tile_body<float, false>(A, A.order ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x));
+}
+
+// ---- software-pipelined tile passes ------------------------------------------
+// A tile that fills a CU's LDS (2^13 complex128 or 2^14 complex64 amplitudes)
+// leaves one workgroup per CU, so a workgroup per coset would load, run its
+// rounds and store strictly one after the other.  Instead one workgroup per
+// CU walks the cosets w, w + G, w + 2G, ... (G workgroups) and issues the
+// loads of its next coset into registers before it runs the current coset's
+// rounds: HBM reads overlap the rounds and the stores.  A thread moves
+// kPipeK 16-byte accesses per coset (an amplitude pair each for complex64,
+// one amplitude for complex128); the first PipeAccess::pre of them are
+// prefetched, the rest (complex128 only, whose rounds need the registers)
+// are issued at the top of the coset's turn, ahead of the prefetched ones'
+// LDS writes.
+constexpr int kPipeK = 16;
+template <class R>
+struct PipeAccess;
+template <>
+struct PipeAccess<float> {
+  using T = cplx2<float>;
+  static constexpr uint32_t amps = 2;
+  static constexpr int pre = 16;
+};
+template <>
+struct PipeAccess<double> {
+  using T = cplx<double>;
+  static constexpr uint32_t amps = 1;
+  static constexpr int pre = 8;
+};
+
+template <class R, int K0, int K1>
+__device__ __forceinline__ void pipe_issue(const TileKArgs<R>& A, const Ctx& C, typename PipeAccess<R>::T* v) {
+  using E = typename PipeAccess<R>::T;
+  constexpr uint32_t apa = PipeAccess<R>::amps;
+  const uint32_t step = apa * blockDim.x;
+#pragma unroll
+  for (int k = K0; k < K1; ++k) {
+    const uint32_t pos = apa * threadIdx.x + step * k;
+    v[k - K0] = ld_nt(reinterpret_cast<const E*>(A.psi + (C.base | C.dep(pos))));
+  }
+}
+
+template <class R, int K0, int K1>
+__device__ __forceinline__ void pipe_to_lds(const typename PipeAccess<R>::T* v, cplx<R>* T) {
+  using E = typename PipeAccess<R>::T;
+  constexpr uint32_t apa = PipeAccess<R>::amps;
+  const uint32_t step = apa * blockDim.x;
+#pragma unroll
+  for (int k = K0; k < K1; ++k) {
+    const uint32_t pos = apa * threadIdx.x + step * k;
+    *reinterpret_cast<E*>(T + lds_off(pos)) = v[k - K0];
+  }
+}
+
+// Requires 2^m = blockDim.x * kPipeK * PipeAccess<R>::amps (checked on the host).
+template <class R>
+__global__ void __launch_bounds__(kMaxThreads) tile_kernel_pipe(TileKArgs<R> A, uint32_t n_cosets) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
+  constexpr int P = PipeAccess<R>::pre;
+  typename PipeAccess<R>::T v[P];
+  const uint32_t G = gridDim.x;
+  uint32_t c = A.order ? blockIdx.x : xcd_block(blockIdx.x, G);
+  if (c < n_cosets) pipe_issue<R, 0, P>(A, coset_ctx(A, c), v);
+  for (; c < n_cosets; c += G) {
+    const Ctx C = coset_ctx(A, c);
+    __syncthreads();  // the previous coset's store has finished reading the tile
+    if constexpr (P < kPipeK) {
+      typename PipeAccess<R>::T w[kPipeK - P];
+      pipe_issue<R, P, kPipeK>(A, C, w);
+      pipe_to_lds<R, 0, P>(v, T);
+      pipe_to_lds<R, P, kPipeK>(w, T);
+    } else {
+      pipe_to_lds<R, 0, P>(v, T);
+    }
+    __syncthreads();
+    if (c + G < n_cosets) pipe_issue<R, 0, P>(A, coset_ctx(A, c + G), v);
+    tile_rounds<R, false>(A, C, T);
+    const double nacc = tile_store<R>(A, C, T);
+    if (A.norm_part != nullptr) {
+      const double t = block_sum_fixed(nacc);
+      if (threadIdx.x == 0) A.norm_part[c] = t;
+    }
+  }
 }
 
 // A batched instance's argument block, read field by field with scalar loads.
@@ -553,6 +637,7 @@ __device__ __forceinline__ TileKArgs<R> load_args(const TileKArgs<R>* descs, uin
   A.scale = P->scale;
   A.norm_part = nullptr;  // batched passes never report a norm
   A.init_amp = P->init_amp;
+  A.order = 0;
   return A;
 }
 
@@ -626,8 +711,39 @@ void launch_tile_k(const TileKArgs<R>& A, hipStream_t s) {
             tile_lds(A.m, sizeof(cplx<R>)), s, A);
 }
 
+// Workgroups of a pipelined pass: one per compute unit (at most one coset each).
+inline uint32_t pipe_grid(uint32_t n_cosets) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return n_cosets < (uint32_t)cus ? n_cosets : (uint32_t)cus;
+}
+
+template <class R>
+bool pipe_eligible(const TileKArgs<R>& A) {
+  // tiles that fill the LDS, without diagonal slots (whose rounds need the
+  // registers the prefetch would take)
+  return A.diag == nullptr && A.init_amp == 0.0 && A.m == (sizeof(R) == 8 ? 13u : 14u) &&
+         (1u << A.m) == tile_threads(A.m) * kPipeK * PipeAccess<R>::amps;
+}
+
 template <class R>
 void launch_tile(const TileKArgs<R>& A, hipStream_t s) {
+  if (pipe_eligible(A)) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      allow_dynamic_lds((const void*)tile_kernel_pipe<R>, kTileDynLds, "tile_pass");
+      attr_set = true;
+    }
+    const uint32_t n_cosets = 1u << (A.n - A.m);
+    QS_LAUNCH("tile_pass", s, tile_kernel_pipe<R>, dim3(pipe_grid(n_cosets)), dim3(tile_threads(A.m)),
+              tile_lds(A.m, sizeof(cplx<R>)), s, A, n_cosets);
+    return;
+  }
   if (A.diag != nullptr) {
     launch_tile_k<R, true>(A, s);
   } else if constexpr (sizeof(R) == 4) {

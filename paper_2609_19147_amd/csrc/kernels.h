@@ -63,6 +63,9 @@ struct TileKArgs {
   double* norm_part;  // null, or one FP64 sum of |psi|^2 as stored per tile
   double init_amp;    // 0: load the tile; else the tile starts as this real
                       // amplitude everywhere (a uniform state made on load)
+  uint32_t order;     // workgroup -> coset: 0 XCD-blocked (each XCD a contiguous
+                      // range of cosets), 1 launch order (concurrent workgroups
+                      // of all XCDs on neighbouring cosets)
 };
 template <class R> void launch_tile(const TileKArgs<R>& A, hipStream_t s);
 // count instances of one geometry (n qubits, m tile bits), descriptors in device

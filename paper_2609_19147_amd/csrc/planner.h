@@ -132,6 +132,8 @@ struct PlanOptions {
   int max_tile_bits = 0;  // 0 = default by dtype at apply time
   int dense_k_max = 6;    // largest UNITARY gate run as a dense block (< 4: none)
   int window_k = 5;       // dense-window fusion: largest window (< 4: off)
+  int coset_order = 0;    // tile passes' workgroup -> coset order: 0 by geometry,
+                          // 1 XCD-blocked, 2 launch order
 };
 
 struct PlanIR {

@@ -273,6 +273,16 @@ namespace qs {
 
 namespace {
 
+// Coset order of a tile pass (TileKArgs::order).  By geometry: measured at
+// 30 qubits, contiguous tiles stream fastest XCD-blocked, tiles over high
+// bits with runs of 2^5 amplitudes or more in launch order (neighbouring
+// cosets of all XCDs share DRAM rows), shorter runs XCD-blocked again.
+uint32_t tile_order(int opt, int L, int a) {
+  if (opt == 1) return 0;
+  if (opt == 2) return 1;
+  return (L == a || L <= 4) ? 0u : 1u;
+}
+
 template <class R>
 void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last, double* norm_last = nullptr) {
   const PlanDev& d = p.device_for(s.dtype);
@@ -300,6 +310,7 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last, double* 
         A.a = T.a;
         A.h = T.h;
         A.m = T.L + T.h;
+        A.order = tile_order(P.opt.coset_order, T.L, T.a);
         A.n_rounds = (uint32_t)T.rounds.size();
         A.n = s.n;
         A.scale = T.scale;

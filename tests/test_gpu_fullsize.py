@@ -67,14 +67,18 @@ def sample_indices(n, seed, count=8192):
     return np.unique(np.concatenate([ys, np.array([0, (1 << n) - 1], np.uint64)]))
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_benchmark_circuit_30q_sampled_outputs(qs, dtype):
+@pytest.mark.parametrize("dtype,tile_bits", [("c64", 0), ("c128", 0), ("c64", 14), ("c128", 12), ("c64", 12)])
+def test_benchmark_circuit_30q_sampled_outputs(qs, dtype, tile_bits):
     """The benchmark's plan (same circuit, same planner options) on a sparse
-    input: out[y] = (Walsh . QFT psi0)[src(y)] with src from the X/CNOT/SWAP block."""
+    input: out[y] = (Walsh . QFT psi0)[src(y)] with src from the X/CNOT/SWAP block.
+    Tiles that fill the LDS (2^13 complex128, 2^14 complex64 amplitudes) run
+    the pipelined kernel, one workgroup per CU walking 512 cosets."""
     from bench import BLOCK_SEED, circuit
     stream = circuit(N30)
-    plan = qs.Plan(N30, stream)
-    assert [L["kind"] for L in plan.describe()["layers"]] == ["tile", "tile", "tile", "gf2"]
+    plan = qs.Plan(N30, stream, max_tile_bits=tile_bits)
+    kinds = [L["kind"] for L in plan.describe()["layers"]]
+    assert kinds[-1] == "gf2" and set(kinds[:-1]) == {"tile"}
+    assert len(kinds) == (5 if tile_bits == 12 else 4)
     st, idx, c = sparse_on_device(qs, N30, dtype, seed=5)
     qs.apply(st, plan)
     ys = sample_indices(N30, 11)
