@@ -5,7 +5,10 @@
 // of layer l, after which every parameter occurrence of that layer contributes
 // 2 Re <lambda|K|phi> with K = U_l^dagger dU_l/dtheta restricted to its wire
 // (tile-pass windows: a 2x2 operator; diagonal layers: i * count of the
-// parameter's group).  All reductions are FP64.
+// parameter's group).  All reductions are FP64.  A tile pass is undone on both
+// states by one fused kernel that also sums the layer's cross densities from
+// the two tiles in LDS (4 S of traffic per layer); layers whose two tiles do
+// not fit in LDS take two passes and a separate cross-density read (6 S).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +22,9 @@
 using namespace qs;
 
 namespace {
+
+// Both LDS tiles of the fused adjoint pass (the tile kernels' dynamic LDS limit).
+constexpr size_t kDualLdsBytes = 144 * 1024;
 
 // Work state k of psi (same n, dtype, device and stream), made on first use
 // and kept with psi; its contents are overwritten by each sweep.
@@ -115,6 +121,9 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
   // bits in one read of phi and lambda (the layer's tile geometry), else one
   // reduction per bit; diagonal-layer parameters one reduction per group
   std::vector<RhoTileArgs> tile_rho(L);
+  std::vector<RhoTileArgs> dual_rho(L);             // fused: bits as positions in the inverse pass's tile
+  std::vector<char> dual(L, 0);
+  std::vector<double> rho_scale(L, 1.0);            // fused: staged tiles are unnormalised
   std::vector<std::map<int, size_t>> rho_slot(L);   // bit -> offset of its 8 sums
   std::vector<std::vector<int>> single_bits(L);     // bits reduced one at a time
   std::vector<std::map<std::pair<int, int>, size_t>> diag_slot(L);  // (diag, group) -> offset
@@ -128,6 +137,32 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
         if (std::find(bits.begin(), bits.end(), e.bit) == bits.end()) bits.push_back(e.bit);
       } else if (!diag_slot[fl].count({e.diag, e.group})) {
         diag_slot[fl][{e.diag, e.group}] = n_res++;
+      }
+    }
+    const LayerIR& IL = inv.ir.layers[L - 1 - fl];
+    if (IL.kind == L_TILE && bits.size() <= 32) {
+      const TilePassIR& T = inv.ir.passes[IL.index];
+      const uint32_t m = (uint32_t)(T.L + T.h), M = 1u << m;
+      bool ok = 2 * sizeof(cplx<R>) * (M + ((M >> 5) << 1)) <= kDualLdsBytes && m <= (sizeof(R) == 4 ? 14u : 13u);
+      RhoTileArgs A{};
+      A.L = (uint32_t)T.L;
+      A.a = (uint32_t)T.a;
+      A.h = (uint32_t)T.h;
+      A.m = m;
+      for (int b : bits) {
+        const int pos = b < T.L ? b : (b >= T.a && b < T.a + T.h ? T.L + b - T.a : -1);
+        if (pos < 0) ok = false;
+        else A.tbit[A.nbits++] = (uint32_t)pos;
+      }
+      if (ok) {
+        dual[fl] = 1;
+        dual_rho[fl] = A;
+        rho_scale[fl] = T.scale * T.scale;
+        tile_slot[fl] = n_res;
+        for (size_t k = 0; k < bits.size(); ++k) rho_slot[fl][bits[k]] = n_res + 8 * k;
+        n_res += 8 * bits.size();
+        rho_partials = std::max(rho_partials, rho_tile_partials(n, A));
+        continue;
       }
     }
     if (bits.empty()) continue;
@@ -175,8 +210,14 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
   double* res = part + rho_partials;
   for (size_t j = 0; j < L; ++j) {
     const size_t fl = L - 1 - j;  // forward layer being undone
-    apply_layers(phi, inv, j, j + 1);
-    apply_layers(lam, inv, j, j + 1);
+    if (dual[fl]) {
+      const TileKArgs<R> A = tile_args<R>(phi, inv, inv.ir.layers[j].index);
+      if (!launch_tile_dual<R>(A, (cplx<R>*)lam.cur_ptr(), dual_rho[fl], part, res + tile_slot[fl], psi.stream))
+        fail(QS_EDEVICE, "internal: fused adjoint pass rejected its tiles");
+    } else {
+      apply_layers(phi, inv, j, j + 1);
+      apply_layers(lam, inv, j, j + 1);
+    }
     const cplx<R>* ph = (const cplx<R>*)phi.cur_ptr();
     const cplx<R>* la = (const cplx<R>*)lam.cur_ptr();
     if (tile_rho[fl].nbits) launch_rho_tile<R>(ph, la, n, tile_rho[fl], part, res + tile_slot[fl], psi.stream);
@@ -205,7 +246,7 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
         const double* q = r.data() + rho_slot[fl].at(e.bit);
         cd acc = 0;
         for (int k = 0; k < 4; ++k) acc += e.K[k] * cd(q[2 * k], q[2 * k + 1]);
-        g[e.param] += e.coef * 2.0 * acc.real();
+        g[e.param] += e.coef * 2.0 * rho_scale[fl] * acc.real();
       } else {
         g[e.param] += e.coef * (-2.0) * r[diag_slot[fl].at({e.diag, e.group})];
       }

@@ -16,6 +16,7 @@
 // (bits outside the round, one sincospi per group) times a host-built
 // intra-round factor.
 #include "kernels.h"
+#include "rho.h"
 
 namespace qs {
 
@@ -37,6 +38,14 @@ struct Ctx {
   }
 };
 
+// u x + v y as one multiply-add chain per component (four instructions each,
+// against five for two complex products and an add).
+template <class R>
+__device__ __forceinline__ cplx<R> cmul2(cplx<R> u, cplx<R> x, cplx<R> v, cplx<R> y) {
+  return {fma(u.re, x.re, fma(-u.im, x.im, fma(v.re, y.re, -v.im * y.im))),
+          fma(u.re, x.im, fma(u.im, x.re, fma(v.re, y.im, v.im * y.re)))};
+}
+
 template <int S, class R>
 __device__ __forceinline__ void op_mat(cplx<R>* a, cptr<cplx<R>> u) {
   const cplx<R> u00 = ldc(u, 0), u01 = ldc(u, 1), u10 = ldc(u, 2), u11 = ldc(u, 3);
@@ -44,8 +53,8 @@ __device__ __forceinline__ void op_mat(cplx<R>* a, cptr<cplx<R>> u) {
   for (int j = 0; j < RN; ++j) {
     if (j & (1 << S)) continue;
     const cplx<R> x = a[j], y = a[j | (1 << S)];
-    a[j] = cadd(cmul(u00, x), cmul(u01, y));
-    a[j | (1 << S)] = cadd(cmul(u10, x), cmul(u11, y));
+    a[j] = cmul2(u00, x, u01, y);
+    a[j | (1 << S)] = cmul2(u10, x, u11, y);
   }
 }
 
@@ -617,6 +626,35 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel_pipe(TileKArgs<R> A, 
   }
 }
 
+// ---- fused adjoint step ---------------------------------------------------------
+// One workgroup per coset undoes the pass on both adjoint states: phi's and
+// lambda's tiles are loaded into two LDS tiles, the pass's rounds run on each,
+// the cross densities of the layer's parameter bits are summed from the two
+// resulting tiles, and both tiles are stored back -- 4 S of HBM traffic per
+// layer instead of 6 S for two passes and a separate re-read of both states.
+template <class R, bool kDiag>
+__global__ void __launch_bounds__(kMaxThreads) tile_kernel_dual(TileKArgs<R> A, cplx<R>* lam, RhoTileArgs Q,
+                                                                 double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[rho::kRhoMaxWaves][32];
+  const uint32_t M = 1u << A.m;
+  cplx<R>* T0 = reinterpret_cast<cplx<R>*>(smem_raw);
+  cplx<R>* T1 = T0 + lds_off(M);
+  const uint32_t ntiles = gridDim.x;
+  const uint32_t coset = A.order ? blockIdx.x : xcd_block(blockIdx.x, ntiles);
+  const Ctx C = coset_ctx(A, coset);
+  TileKArgs<R> B = A;
+  B.psi = lam;
+  tile_load<R>(A, C, T0);
+  tile_load<R>(B, C, T1);
+  __syncthreads();
+  tile_rounds<R, kDiag>(A, C, T0);
+  tile_rounds<R, kDiag>(A, C, T1);
+  if (Q.nbits) rho::accumulate_tile<R>(T0, T1, M, Q, red, partials, coset, ntiles);
+  tile_store<R>(A, C, T0);
+  tile_store<R>(B, C, T1);
+}
+
 // A batched instance's argument block, read field by field with scalar loads.
 template <class R>
 __device__ __forceinline__ TileKArgs<R> load_args(const TileKArgs<R>* descs, uint32_t i) {
@@ -759,6 +797,37 @@ void launch_tile(const TileKArgs<R>& A, hipStream_t s) {
   }
 }
 
+template <class R, bool kDiag>
+void launch_tile_dual_k(const TileKArgs<R>& A, cplx<R>* lam, const RhoTileArgs& Q, double* partials, size_t lds,
+                        hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    allow_dynamic_lds((const void*)tile_kernel_dual<R, kDiag>, kTileDynLds, "tile_pass_dual");
+    attr_set = true;
+  }
+  QS_LAUNCH("tile_pass_dual", s, (tile_kernel_dual<R, kDiag>), dim3(1u << (A.n - A.m)),
+            dim3(tile_threads_for<R, kDiag>(A.m)), lds, s, A, lam, Q, partials);
+}
+
+template <class R>
+bool launch_tile_dual(const TileKArgs<R>& A, cplx<R>* lam, const RhoTileArgs& Q, double* partials, double* out,
+                      hipStream_t s) {
+  const size_t lds = 2 * tile_lds(A.m, sizeof(cplx<R>));
+  if (lds > (size_t)kTileDynLds || Q.nbits > 32 || A.init_amp != 0.0 || A.norm_part != nullptr) return false;
+  for (uint32_t k = 0; k < Q.nbits; ++k)
+    if (Q.tbit[k] >= A.m) return false;
+  if (A.diag != nullptr)
+    launch_tile_dual_k<R, true>(A, lam, Q, partials, lds, s);
+  else
+    launch_tile_dual_k<R, false>(A, lam, Q, partials, lds, s);
+  if (Q.nbits) launch_rho_finalize(partials, 1u << (A.n - A.m), 8 * Q.nbits, out, s);
+  return true;
+}
+
+template bool launch_tile_dual<float>(const TileKArgs<float>&, cplx<float>*, const RhoTileArgs&, double*, double*,
+                                      hipStream_t);
+template bool launch_tile_dual<double>(const TileKArgs<double>&, cplx<double>*, const RhoTileArgs&, double*, double*,
+                                       hipStream_t);
 template void launch_tile<float>(const TileKArgs<float>&, hipStream_t);
 template void launch_tile<double>(const TileKArgs<double>&, hipStream_t);
 template void launch_tile_batched<float>(const TileKArgs<float>*, uint32_t, uint32_t, uint32_t, bool, hipStream_t);

@@ -68,6 +68,18 @@ struct TileKArgs {
                       // of all XCDs on neighbouring cosets)
 };
 template <class R> void launch_tile(const TileKArgs<R>& A, hipStream_t s);
+// Fused adjoint step (declared here, RhoTileArgs below): the pass A undone on
+// two states at once -- A.psi (phi) and lam, each staged in LDS -- followed
+// by the cross densities of the requested tile bits Q.tbit[0 .. Q.nbits)
+// (positions in the pass's tile) between the two resulting tiles, folded into
+// out[8 Q.nbits] (device) through partials (rho_tile_partials doubles).  The
+// sums are of the tiles as staged, before the pass's butterfly
+// normalisation A.scale is applied on the store: true sums = scale^2 x out.
+// Returns false (nothing launched) when two tiles do not fit in LDS.
+struct RhoTileArgs;
+template <class R>
+bool launch_tile_dual(const TileKArgs<R>& A, cplx<R>* lam, const RhoTileArgs& Q, double* partials, double* out,
+                      hipStream_t s);
 // count instances of one geometry (n qubits, m tile bits), descriptors in device
 // memory; has_diag: some descriptor has a diagonal slot.
 template <class R>
@@ -212,6 +224,8 @@ struct RhoTileArgs {
   uint32_t tbit[32];
 };
 size_t rho_tile_partials(int n, const RhoTileArgs& A);
+// out[v] = sum over tiles of partials[v ntiles + tile] for v < nvals (compensated, fixed order).
+void launch_rho_finalize(const double* partials, uint32_t ntiles, uint32_t nvals, double* out, hipStream_t s);
 bool rho_tile_fits(uint32_t m, size_t amp_bytes);  // both tiles of 2^m amplitudes fit in LDS
 template <class R>
 bool launch_rho_tile(const cplx<R>* phi, const cplx<R>* lam, int n, const RhoTileArgs& A, double* partials,

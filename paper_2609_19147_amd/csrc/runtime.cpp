@@ -283,12 +283,43 @@ uint32_t tile_order(int opt, int L, int a) {
   return (L == a || L <= 4) ? 0u : 1u;
 }
 
+}  // namespace
+
+template <class R>
+TileKArgs<R> tile_args(qs_state& s, qs_plan& p, int pass) {
+  const PlanDev& d = p.device_for(s.dtype);
+  const char* base = (const char*)d.blob;
+  const PlanIR& P = p.ir;
+  const TilePassIR& T = P.passes[pass];
+  if (T.L + T.h > (s.dtype == QS_C64 ? 14 : 13)) fail(QS_EINVAL, "tile too large for this dtype");
+  TileKArgs<R> A;
+  std::memset(&A, 0, sizeof A);
+  A.psi = (cplx<R>*)s.cur_ptr();
+  A.rounds = (const TileRound*)(base + d.pass_rounds[pass]);
+  A.ops = (const TileOp*)(base + d.pass_ops[pass]);
+  A.coef = (const cplx<R>*)(base + d.pass_coef[pass]);
+  A.diag = d.pass_diag[pass] ? (const DiagDev*)(base + d.pass_diag[pass]) : nullptr;
+  A.qtab = (const int8_t*)(base + d.pass_qtab[pass]);
+  A.L = T.L;
+  A.a = T.a;
+  A.h = T.h;
+  A.m = T.L + T.h;
+  A.order = tile_order(P.opt.coset_order, T.L, T.a);
+  A.n_rounds = (uint32_t)T.rounds.size();
+  A.n = s.n;
+  A.scale = T.scale;
+  return A;
+}
+template TileKArgs<float> tile_args<float>(qs_state&, qs_plan&, int);
+template TileKArgs<double> tile_args<double>(qs_state&, qs_plan&, int);
+
+namespace {
+
 template <class R>
 void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last, double* norm_last = nullptr) {
   const PlanDev& d = p.device_for(s.dtype);
   const char* base = (const char*)d.blob;
   const PlanIR& P = p.ir;
-  const int max_bits = s.dtype == QS_C64 ? 14 : 13;
   for (size_t li = first; li < last; ++li) {
     const LayerIR& L = P.layers[li];
     switch (L.kind) {
@@ -296,24 +327,7 @@ void apply_layers_t(qs_state& s, qs_plan& p, size_t first, size_t last, double* 
         launch_diag<R>((cplx<R>*)s.cur_ptr(), s.n, diag_dev(d, base, L.index, L.inverse != 0), s.stream);
         break;
       case L_TILE: {
-        const TilePassIR& T = P.passes[L.index];
-        if (T.L + T.h > max_bits) fail(QS_EINVAL, "tile too large for this dtype");
-        TileKArgs<R> A;
-        std::memset(&A, 0, sizeof A);
-        A.psi = (cplx<R>*)s.cur_ptr();
-        A.rounds = (const TileRound*)(base + d.pass_rounds[L.index]);
-        A.ops = (const TileOp*)(base + d.pass_ops[L.index]);
-        A.coef = (const cplx<R>*)(base + d.pass_coef[L.index]);
-        A.diag = d.pass_diag[L.index] ? (const DiagDev*)(base + d.pass_diag[L.index]) : nullptr;
-        A.qtab = (const int8_t*)(base + d.pass_qtab[L.index]);
-        A.L = T.L;
-        A.a = T.a;
-        A.h = T.h;
-        A.m = T.L + T.h;
-        A.order = tile_order(P.opt.coset_order, T.L, T.a);
-        A.n_rounds = (uint32_t)T.rounds.size();
-        A.n = s.n;
-        A.scale = T.scale;
+        TileKArgs<R> A = tile_args<R>(s, p, L.index);
         A.norm_part = li + 1 == last ? norm_last : nullptr;
         launch_tile<R>(A, s.stream);
         break;

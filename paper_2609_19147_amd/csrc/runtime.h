@@ -104,6 +104,10 @@ struct qs_plan {
 namespace qs {
 
 void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last);
+// Kernel arguments of tile pass `pass` of plan p applied to state s (device
+// tables made on first use); norm_part unset.
+template <class R>
+TileKArgs<R> tile_args(qs_state& s, qs_plan& p, int pass);
 // Apply every layer and return ||psi||^2 of the result (FP64).  When the last
 // layer is a tile pass or a gather, its kernel sums |psi|^2 over what it
 // writes (no separate read of the state); otherwise a reduction follows.
