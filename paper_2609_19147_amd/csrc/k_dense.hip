@@ -19,7 +19,9 @@
 //   Yr += Ur Xr + Ui (-Xi),   Yi += Ur Xi + Ui Xr,
 // with U's fragments held in registers for the whole kernel and X's read from
 // LDS.  Results go back to the same LDS columns (each column block is read and
-// written by one wave only), then the tile is stored.
+// written by one wave only, or, for complex64 k = 6, by one pair of waves that
+// each compute half of its rows, with a barrier between their reads and
+// writes), then the tile is stored.
 //
 // Operand layouts of V_MFMA_{F32,F64}_16X16X4 (wave64): A[i][kk] in lane
 // i + 16 kk, B[kk][j] in lane j + 16 kk; D[i][j] in lane j + 16 (i / 4),
@@ -57,6 +59,90 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
 // LDS element of tile position pos (two pad elements every 32).
 __device__ __forceinline__ uint32_t dense_lds_off(uint32_t pos) { return pos + ((pos >> 5) << 1); }
 
+// Tile load and store with kIO 16-byte accesses per thread issued before any
+// is waited for: a loop that waits for each load before the next pays one
+// memory latency per access.  A k-qubit tile (c = 6 column bits) holds
+// 2^(k+6) amplitudes: two pair accesses per thread at k = 4, four at k = 5,
+// eight (in two batches, the matrix fragments filling the registers) at k = 6.
+template <class R, int K>
+constexpr int dense_io() { return K == 16 ? 2 : 4; }
+
+template <class R, int kIO>
+__device__ __forceinline__ void dense_load(const cplx<R>* __restrict__ psi, cplx<R>* T, uint32_t M, uint32_t base,
+                                           uint32_t L, const uint32_t* hi_tab) {
+  const uint32_t Lmask = (1u << L) - 1u, step = 2u * kDenseThreads;
+  for (uint32_t p0 = 2u * threadIdx.x; p0 < M; p0 += step * kIO) {
+    cplx2<R> v[kIO];
+#pragma unroll
+    for (int k = 0; k < kIO; ++k) {
+      const uint32_t p = p0 + step * k;
+      if (p < M) v[k] = ld_nt(reinterpret_cast<const cplx2<R>*>(psi + (base | (p & Lmask) | hi_tab[p >> L])));
+    }
+#pragma unroll
+    for (int k = 0; k < kIO; ++k) {
+      const uint32_t p = p0 + step * k;
+      if (p < M) *reinterpret_cast<cplx2<R>*>(T + dense_lds_off(p)) = v[k];
+    }
+  }
+}
+
+template <class R, int kIO>
+__device__ __forceinline__ void dense_store(cplx<R>* __restrict__ psi, const cplx<R>* T, uint32_t M, uint32_t base,
+                                            uint32_t L, const uint32_t* hi_tab) {
+  const uint32_t Lmask = (1u << L) - 1u, step = 2u * kDenseThreads;
+  for (uint32_t p0 = 2u * threadIdx.x; p0 < M; p0 += step * kIO) {
+    cplx2<R> v[kIO];
+#pragma unroll
+    for (int k = 0; k < kIO; ++k) {
+      const uint32_t p = p0 + step * k;
+      if (p < M) v[k] = *reinterpret_cast<const cplx2<R>*>(T + dense_lds_off(p));
+    }
+#pragma unroll
+    for (int k = 0; k < kIO; ++k) {
+      const uint32_t p = p0 + step * k;
+      if (p < M) st_nt(reinterpret_cast<cplx2<R>*>(psi + (base | (p & Lmask) | hi_tab[p >> L])), v[k]);
+    }
+  }
+}
+
+// complex128 k = 4: one 16-byte amplitude per lane and access.
+__device__ __forceinline__ void dense_load1(const cplx<double>* __restrict__ psi, cplx<double>* T, uint32_t M,
+                                            uint32_t base, uint32_t L, const uint32_t* hi_tab) {
+  constexpr int kIO = 8;
+  const uint32_t Lmask = (1u << L) - 1u;
+  for (uint32_t p0 = threadIdx.x; p0 < M; p0 += kDenseThreads * kIO) {
+    cplx<double> v[kIO];
+#pragma unroll
+    for (int k = 0; k < kIO; ++k) {
+      const uint32_t p = p0 + kDenseThreads * k;
+      if (p < M) v[k] = ld_nt(psi + (base | (p & Lmask) | hi_tab[p >> L]));
+    }
+#pragma unroll
+    for (int k = 0; k < kIO; ++k) {
+      const uint32_t p = p0 + kDenseThreads * k;
+      if (p < M) T[dense_lds_off(p)] = v[k];
+    }
+  }
+}
+__device__ __forceinline__ void dense_store1(cplx<double>* __restrict__ psi, const cplx<double>* T, uint32_t M,
+                                             uint32_t base, uint32_t L, const uint32_t* hi_tab) {
+  constexpr int kIO = 8;
+  const uint32_t Lmask = (1u << L) - 1u;
+  for (uint32_t p0 = threadIdx.x; p0 < M; p0 += kDenseThreads * kIO) {
+    cplx<double> v[kIO];
+#pragma unroll
+    for (int k = 0; k < kIO; ++k) {
+      const uint32_t p = p0 + kDenseThreads * k;
+      if (p < M) v[k] = T[dense_lds_off(p)];
+    }
+#pragma unroll
+    for (int k = 0; k < kIO; ++k) {
+      const uint32_t p = p0 + kDenseThreads * k;
+      if (p < M) st_nt(psi + (base | (p & Lmask) | hi_tab[p >> L]), v[k]);
+    }
+  }
+}
+
 // Deposit the low bits of v into the set bits of mask, in increasing order.
 __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
   uint32_t r = 0;
@@ -72,8 +158,12 @@ __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
 template <class R, int K>
 __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restrict__ psi, const cplx<R>* U_,
                                                               DenseGeom G) {
-  constexpr int RT = K / 16;  // 16-row tiles of U
   constexpr int KS = K / 4;   // 4-deep steps of the contraction
+  // 16-row tiles of U per wave: complex64 k = 6 splits its four between the
+  // two waves of a pair (each wave holds half of U's fragments, so three
+  // waves fit per SIMD); the pair's waves take the same column blocks
+  constexpr bool kSplit = sizeof(R) == 4 && K == 64;
+  constexpr int RT = kSplit ? 2 : K / 16;
   typedef typename Acc4<R>::T acc_t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const uint32_t M = 1u << G.m;
@@ -81,6 +171,8 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
   uint32_t* hi_tab = reinterpret_cast<uint32_t*>(smem_raw + sizeof(cplx<R>) * dense_lds_off(M));
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t li = lane & 15u, lk = lane >> 4;
+  const uint32_t rt0 = kSplit ? 2u * (wave & 1u) : 0u;                    // first row tile
+  const uint32_t cb0 = kSplit ? wave >> 1 : wave, cbs = kSplit ? 2u : 4u;  // column blocks
 
   // global offsets of the high tile bits (all of them targets)
   for (uint32_t h = threadIdx.x; h < (1u << G.n_hi); h += kDenseThreads) {
@@ -90,14 +182,14 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
     hi_tab[h] = off;
   }
 
-  // U fragments: A[i][kk] = U[16 rt + i][4 ks + kk]
+  // U fragments: A[i][kk] = U[16 (rt0 + rt) + i][4 ks + kk]
   const cptr<cplx<R>> U = to_const(U_);
   R ur[RT][KS], ui[RT][KS];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const uint32_t e = (16u * rt + li) * K + 4u * ks + lk;
+      const uint32_t e = (16u * (rt0 + rt) + li) * K + 4u * ks + lk;
       ur[rt][ks] = U[e].re;
       ui[rt][ks] = U[e].im;
     }
@@ -111,9 +203,8 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      drow[rt][v] = deposit(16u * rt + (sizeof(R) == 4 ? 4u * lk + v : lk + 4u * v), G.rowmask);
+      drow[rt][v] = deposit(16u * (rt0 + rt) + (sizeof(R) == 4 ? 4u * lk + v : lk + 4u * v), G.rowmask);
   const uint32_t ncb = (1u << G.c) >> 4;
-  const uint32_t Lmask = (1u << G.L) - 1u;
   __syncthreads();
 
   for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
@@ -125,50 +216,53 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
     if constexpr (sizeof(R) == 8 && K == 16) {
       // complex128, k = 4 (K = 16, memory-bound): one 16-byte amplitude per lane and
       // access (for k = 5 the extra address work costs more than it saves)
-      for (uint32_t p = threadIdx.x; p < M; p += kDenseThreads)
-        T[dense_lds_off(p)] = ld_nt(psi + (base | (p & Lmask) | hi_tab[p >> G.L]));
+      dense_load1(psi, T, M, base, G.L, hi_tab);
     } else {
-      for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
-        const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
-        *reinterpret_cast<cplx2<R>*>(T + dense_lds_off(p)) = ld_nt(reinterpret_cast<const cplx2<R>*>(psi + g));
-      }
+      dense_load<R, dense_io<R, K>()>(psi, T, M, base, G.L, hi_tab);
     }
     __syncthreads();
 
-    for (uint32_t cb = wave; cb < ncb; cb += kDenseThreads / 64) {
-      const uint32_t colp = deposit(16u * cb + li, colmask);
+    // uniform trip count: with split row tiles the two waves of a pair read
+    // all rows of a column block and each writes half of them back in place,
+    // so a barrier separates every round's reads from its writes
+    const uint32_t trips = (ncb + cbs - 1u) / cbs;
+    for (uint32_t it = 0; it < trips; ++it) {
+      const uint32_t cb = cb0 + it * cbs;
+      const bool active = cb < ncb;
+      const uint32_t colp = deposit(16u * (active ? cb : 0u) + li, colmask);
       acc_t yr[RT], yi[RT];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         yr[rt] = acc_t{0, 0, 0, 0};
         yi[rt] = acc_t{0, 0, 0, 0};
       }
+      if (active) {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const cplx<R> x = T[dense_lds_off(brow[ks] | colp)];
-        const R nxi = -x.im;
+        for (int ks = 0; ks < KS; ++ks) {
+          const cplx<R> x = T[dense_lds_off(brow[ks] | colp)];
+          const R nxi = -x.im;
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          yr[rt] = mfma16(ur[rt][ks], x.re, yr[rt]);
-          yr[rt] = mfma16(ui[rt][ks], nxi, yr[rt]);
-          yi[rt] = mfma16(ur[rt][ks], x.im, yi[rt]);
-          yi[rt] = mfma16(ui[rt][ks], x.re, yi[rt]);
+          for (int rt = 0; rt < RT; ++rt) {
+            yr[rt] = mfma16(ur[rt][ks], x.re, yr[rt]);
+            yr[rt] = mfma16(ui[rt][ks], nxi, yr[rt]);
+            yi[rt] = mfma16(ur[rt][ks], x.im, yi[rt]);
+            yi[rt] = mfma16(ui[rt][ks], x.re, yi[rt]);
+          }
         }
       }
+      if constexpr (kSplit) __syncthreads();
+      if (active) {
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) T[dense_lds_off(drow[rt][v] | colp)] = cplx<R>{yr[rt][v], yi[rt][v]};
+          for (int v = 0; v < 4; ++v) T[dense_lds_off(drow[rt][v] | colp)] = cplx<R>{yr[rt][v], yi[rt][v]};
+      }
     }
     __syncthreads();
     if constexpr (sizeof(R) == 8 && K == 16) {
-      for (uint32_t p = threadIdx.x; p < M; p += kDenseThreads)
-        st_nt(psi + (base | (p & Lmask) | hi_tab[p >> G.L]), T[dense_lds_off(p)]);
+      dense_store1(psi, T, M, base, G.L, hi_tab);
     } else {
-      for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
-        const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
-        st_nt(reinterpret_cast<cplx2<R>*>(psi + g), *reinterpret_cast<const cplx2<R>*>(T + dense_lds_off(p)));
-      }
+      dense_store<R, dense_io<R, K>()>(psi, T, M, base, G.L, hi_tab);
     }
     __syncthreads();
   }
@@ -206,17 +300,13 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<doubl
 #pragma unroll
     for (int v = 0; v < 4; ++v) drow[rt][v] = deposit(16u * rt + lk + 4u * v, G.rowmask);
   const uint32_t ncb = (1u << G.c) >> 4;
-  const uint32_t Lmask = (1u << G.L) - 1u;
   __syncthreads();
 
   for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
     uint32_t base = 0;
     for (uint32_t j = 0; j < G.n_free; ++j)
       if ((t >> j) & 1u) base |= 1u << G.free_bit[j];
-    for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
-      const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
-      *reinterpret_cast<cplx2<double>*>(T + dense_lds_off(p)) = ld_nt(reinterpret_cast<const cplx2<double>*>(psi + g));
-    }
+    dense_load<double, 4>(psi, T, M, base, G.L, hi_tab);
     __syncthreads();
     for (uint32_t cb = wave; cb < ncb; cb += kDenseThreads / 64) {
       const uint32_t colp = deposit(16u * cb + li, colmask);
@@ -245,10 +335,7 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<doubl
         for (int v = 0; v < 4; ++v) T[dense_lds_off(drow[rt][v] | colp)] = cplx<double>{yr[rt][v], yi[rt][v]};
     }
     __syncthreads();
-    for (uint32_t p = 2u * threadIdx.x; p < M; p += 2u * kDenseThreads) {
-      const uint32_t g = base | (p & Lmask) | hi_tab[p >> G.L];
-      st_nt(reinterpret_cast<cplx2<double>*>(psi + g), *reinterpret_cast<const cplx2<double>*>(T + dense_lds_off(p)));
-    }
+    dense_store<double, 4>(psi, T, M, base, G.L, hi_tab);
     __syncthreads();
   }
 }

@@ -82,3 +82,19 @@ def test_dense_equals_plain_per_gate_path(qs):
     ref.upload(psi0.astype(np.complex64))
     qs.apply_gates(ref, stream)
     assert qs.infidelity(st, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype,k", [("c64", 6), ("c64", 5), ("c128", 6)])
+def test_many_tile_blocks_at_24_qubits_against_oracle(qs, dtype, k):
+    """24 qubits (2^18 tiles over the persistent grid, each workgroup walking
+    a hundred tiles, as at the benchmark's 30 qubits): three seeded k-qubit
+    blocks against the oracle, element by element, then the inverse plan
+    back to the input and the norm."""
+    n = 24
+    stream = W.dense_block_stream(n, 3, k, 500 + k)
+    st, plan, psi0 = run_device(qs, n, stream, dtype, seed=9)
+    assert [L["kind"] for L in plan.describe()["layers"]] == ["dense"] * 3
+    check(st.download().astype(np.complex128), sv.run(psi0, n, stream), dtype, n)
+    qs.apply(st, plan.inverse())
+    check(st.download().astype(np.complex128), psi0, dtype, n)
+    assert abs(qs.norm2(st) - metrics.norm2(psi0)) <= (1e-6 if dtype == "c64" else 1e-13)
