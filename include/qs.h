@@ -134,6 +134,12 @@ typedef struct {
                                order), 1 = XCD-blocked (each of the 8 XCDs a contiguous
                                range of cosets), 2 = launch order (the workgroups resident
                                at one time, on all XCDs, take neighbouring cosets) */
+  int32_t diag_low_bits;    /* tile passes over high bits that carry diagonal layers:
+                               0 = default, -1 = the same low bits as other passes,
+                               2..8 = at most this many low bits (smaller tiles) */
+  int32_t balance_passes;   /* 0 = default: single-qubit ops after a tile pass's last
+                               diagonal layer move to the next tile pass when that
+                               evens out the two passes' arithmetic; -1 = off */
 } qs_plan_opts;
 
 typedef struct qs_state qs_state;

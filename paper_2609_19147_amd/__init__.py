@@ -243,13 +243,14 @@ class Plan:
 
     def __init__(self, n: int, gates, n_params: int = 0, mode: str = "fused", max_tile_bits: int = 0,
                  params=None, dense_k_max: int = 0, window_k: int = 0, low_bits: int = 0,
-                 coset_order: int = 0):
+                 coset_order: int = 0, diag_low_bits: int = 0, balance_passes: int = 0):
         self.n = int(n)
         self.gates = list(gates)
         self.n_params = int(n_params)
         cg = CGates(self.gates)
         opts = QsPlanOpts(_lib.QS_FUSED if mode == "fused" else _lib.QS_PLAIN, int(max_tile_bits),
-                          int(dense_k_max), int(window_k), int(low_bits), int(coset_order))
+                          int(dense_k_max), int(window_k), int(low_bits), int(coset_order),
+                          int(diag_low_bits), int(balance_passes))
         h = C.c_void_p()
         check(lib().qs_plan_create(self.n, cg.arr, cg.n, self.n_params, C.byref(opts), C.byref(h)))
         self.h = h

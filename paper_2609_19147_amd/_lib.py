@@ -33,7 +33,8 @@ class QsPauli(C.Structure):
 
 class QsPlanOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_tile_bits", C.c_int32), ("dense_k_max", C.c_int32),
-                ("window_k", C.c_int32), ("low_bits", C.c_int32), ("coset_order", C.c_int32)]
+                ("window_k", C.c_int32), ("low_bits", C.c_int32), ("coset_order", C.c_int32),
+                ("diag_low_bits", C.c_int32), ("balance_passes", C.c_int32)]
 
 
 class QsError(RuntimeError):

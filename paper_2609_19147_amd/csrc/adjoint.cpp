@@ -157,7 +157,8 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
       if (ok) {
         dual[fl] = 1;
         dual_rho[fl] = A;
-        rho_scale[fl] = T.scale * T.scale;
+        const double sc = inv.device_for(psi.dtype).pass_scale[IL.index];
+        rho_scale[fl] = sc * sc;
         tile_slot[fl] = n_res;
         for (size_t k = 0; k < bits.size(); ++k) rho_slot[fl][bits[k]] = n_res + 8 * k;
         n_res += 8 * bits.size();

@@ -321,6 +321,11 @@ extern "C" qs_status qs_plan_create(int n, const qs_gate* gates, size_t n_gates,
       if (opts->low_bits) low = opts->low_bits;
       if (opts->coset_order < 0 || opts->coset_order > 2) fail(QS_EINVAL, "coset_order must be 0, 1 or 2");
       o.coset_order = opts->coset_order;
+      if (opts->diag_low_bits != 0 && opts->diag_low_bits != -1 && (opts->diag_low_bits < 2 || opts->diag_low_bits > 8))
+        fail(QS_EINVAL, "diag_low_bits must be -1, 0 or 2..8");
+      o.diag_low_bits = opts->diag_low_bits;
+      if (opts->balance_passes < -1 || opts->balance_passes > 0) fail(QS_EINVAL, "balance_passes must be -1 or 0");
+      o.balance_passes = opts->balance_passes;
     }
     int tb = o.max_tile_bits ? o.max_tile_bits : 13;
     if (tb < kRoundBits + 1 || tb > kMaxTileBits) fail(QS_EINVAL, "max_tile_bits out of range");

@@ -110,14 +110,14 @@ void build_descs(qs_batch& B) {
         A.ops = (const TileOp*)(base + d.pass_ops[L.index]);
         A.coef = (const cplx<R>*)(base + d.pass_coef[L.index]);
         A.diag = d.pass_diag[L.index] ? (const DiagDev*)(base + d.pass_diag[L.index]) : nullptr;
-        A.qtab = (const int8_t*)(base + d.pass_qtab[L.index]);
+        A.qtab = (const int32_t*)(base + d.pass_qtab[L.index]);
         A.L = T.L;
         A.a = T.a;
         A.h = T.h;
         A.m = T.L + T.h;
-        A.n_rounds = (uint32_t)T.rounds.size();
+        A.n_rounds = d.pass_nrounds[L.index];
         A.n = p.ir.n;
-        A.scale = T.scale;
+        A.scale = d.pass_scale[L.index];
         // |+>^n made by the first layer's tile loads (no separate fill)
         if (li == 0 && B.init == 1) A.init_amp = plus_amplitude(G.n);
         std::memcpy(host.data() + off + k * sizeof A, &A, sizeof A);

@@ -248,11 +248,6 @@ template <class R, int NJ>
 __device__ __forceinline__ void diag_apply_total_angle(cplx<R>* a, uint32_t i0, const uint32_t (&off)[NJ],
                                                        const DiagDev& D);
 
-// The 16 amplitudes of a tile round: index i0 | (any subset of the round's
-// state bits b[0..3]), register j holding subset j.  For groups whose pair
-// table (qt, 8 bytes per group) says the count is a polynomial of degree <= 2
-// in the four bits, counts come from 5 evaluations (i0 and the single flips)
-// and the pair coefficients; other groups evaluate all 16 indices.
 // exp(i x) for an FP64 angle: reduced to [-pi, pi] against 2 pi split in two
 // doubles, then sin / cos in the state's precision.
 __device__ __forceinline__ double reduce_2pi(double x) {
@@ -344,69 +339,113 @@ __device__ __forceinline__ void diag_apply_angles(cplx<R>* a, uint32_t i0, uint3
   for (int j = 0; j < 16; ++j) a[j] = cmul(a[j], ph[j]);
 }
 
-template <class R>
-__device__ __forceinline__ void diag_apply_round(cplx<R>* a, uint32_t i0, uint32_t b0, uint32_t b1, uint32_t b2,
-                                                 uint32_t b3, const DiagDev& D, const int8_t* qt_) {
-  const cplx<R>* __restrict__ lut = (const cplx<R>*)D.lut;
+// Lookup-table mode of a diagonal round: a[j] *= prod_g LUT_g[count_g(i0 |
+// off_j)] (times the conjugates with kConj), off_j the subset j of the round's
+// register bits b[0..3].  A group whose pair-table row (qt, kPairRowWords
+// words per group) marks it quadratic gets its 16 counts from the count at i0,
+// the four single-bit changes d_k and the pair coefficients:
+//   count(j) = count(j without its top bit t) + d_t + sum_{k < t, k in j} q_kt,
+// one add per amplitude since the q sums are uniform; other groups evaluate all
+// 16 indices.  Table entries are read at 32-bit byte offsets from the group's
+// first entry.
+template <class R, bool kConj>
+__device__ __forceinline__ void diag_lut_round(cplx<R>* a, uint32_t i0, const uint32_t (&b)[4], const DiagDev& D,
+                                               cptr<int32_t> qt) {
   const cptr<DiagGroup> groups = to_const(D.groups);
-  const cptr<int8_t> qt = to_const(qt_);
+  const cptr<DiagTerm> terms = to_const(D.terms);
   for (int g = 0; g < D.n_groups; ++g) {
-    const int lb = groups[g].lut_begin;
+    const cptr<int32_t> row = qt + kPairRowWords * g;
+    const char* lut = reinterpret_cast<const char*>(D.lut) + sizeof(cplx<R>) * (size_t)groups[g].lut_begin;
     int cnt[16];
-    const cptr<int8_t> row = qt + kPairRowBytes * g;
     if (row[0]) {
-      int d[4];
-      int c0;
+      int c0, d[4];
       if (row[7]) {
-        // distinct bit-pair mismatches: the count at the base index (register
-        // bits zero), then deg_k - 2 popcount(N_k & base) per register bit
-        const cptr<DiagTerm> terms = to_const(D.terms);
+        // distinct bit-pair mismatches: deg_k - 2 popcount(N_k & i0) per bit
         c0 = 0;
-        for (int t = groups[g].term_begin; t < groups[g].term_end; ++t) {
-          const uint32_t m = terms[t].mask;
-          c0 += popc((i0 ^ (i0 >> terms[t].shift)) & m);
-        }
-        const cptr<uint32_t> nmask = reinterpret_cast<cptr<uint32_t>>(row + 16);
+        for (int t = groups[g].term_begin; t < groups[g].term_end; ++t)
+          c0 += popc((i0 ^ (i0 >> terms[t].shift)) & terms[t].mask);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) d[k] = (int)row[8 + k] - 2 * popc(i0 & nmask[k]);
+        for (int k = 0; k < 4; ++k) d[k] = row[8 + k] - 2 * popc(i0 & (uint32_t)row[12 + k]);
       } else {
-        const uint32_t off5[5] = {0u, b0, b1, b2, b3};
+        const uint32_t off5[5] = {0u, b[0], b[1], b[2], b[3]};
         int c5[5];
         diag_counts<5>(i0, off5, D.terms, groups[g].term_begin, groups[g].term_end, c5);
         c0 = c5[0];
 #pragma unroll
         for (int k = 0; k < 4; ++k) d[k] = c5[k + 1] - c5[0];
       }
-      const int c5_0 = c0;
-      const int q01 = row[1], q02 = row[2], q03 = row[3];
-      const int q12 = row[4], q13 = row[5], q23 = row[6];
+      // q[k][t] for k < t: pairs 01 02 03 12 13 23 at row[1..6]
+      const int q01 = row[1], q02 = row[2], q03 = row[3], q12 = row[4], q13 = row[5], q23 = row[6];
+      cnt[0] = c0;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        int c = c5_0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if ((j >> k) & 1) c += d[k];
-        if ((j & 3) == 3) c += q01;
-        if ((j & 5) == 5) c += q02;
-        if ((j & 9) == 9) c += q03;
-        if ((j & 6) == 6) c += q12;
-        if ((j & 10) == 10) c += q13;
-        if ((j & 12) == 12) c += q23;
-        cnt[j] = c;
+      for (int j = 1; j < 16; ++j) {
+        const int t = j >= 8 ? 3 : j >= 4 ? 2 : j >= 2 ? 1 : 0;
+        const int rest = j & ~(1 << t);
+        int qs = 0;
+        if (t == 1) qs = (rest & 1) ? q01 : 0;
+        if (t == 2) qs = ((rest & 1) ? q02 : 0) + ((rest & 2) ? q12 : 0);
+        if (t == 3) qs = ((rest & 1) ? q03 : 0) + ((rest & 2) ? q13 : 0) + ((rest & 4) ? q23 : 0);
+        cnt[j] = cnt[rest] + (d[t] + qs);
       }
     } else {
       uint32_t off[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j)
-        off[j] = ((j & 1) ? b0 : 0u) | ((j & 2) ? b1 : 0u) | ((j & 4) ? b2 : 0u) | ((j & 8) ? b3 : 0u);
+        off[j] = ((j & 1) ? b[0] : 0u) | ((j & 2) ? b[1] : 0u) | ((j & 4) ? b[2] : 0u) | ((j & 8) ? b[3] : 0u);
       diag_counts<16>(i0, off, D.terms, groups[g].term_begin, groups[g].term_end, cnt);
     }
+    // entries fetched eight at a time, all eight loads issued before the
+    // first use (the scheduler would otherwise wait on each load in turn to
+    // save registers)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      cplx<R> v = lut[lb + cnt[j]];
-      if (D.conj) v.im = -v.im;
-      a[j] = cmul(a[j], v);
+    for (int j0 = 0; j0 < 16; j0 += 8) {
+      cplx<R> v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        v[k] = *reinterpret_cast<const cplx<R>*>(lut + (uint32_t)cnt[j0 + k] * (uint32_t)sizeof(cplx<R>));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[j0 + k] = kConj ? cmulc(a[j0 + k], v[k]) : cmul(a[j0 + k], v[k]);
     }
+  }
+}
+
+// A one-group layer whose count is a sum of distinct bit-pair mismatches (the
+// row's quadratic and pair flags set): the lookup-table round without loops
+// over groups or branches on the row, for the pair row of the round's bits.
+template <class R, bool kConj>
+__device__ __forceinline__ void diag_pair_round(cplx<R>* a, uint32_t i0, const DiagDev& D, cptr<int32_t> row) {
+  const cptr<DiagGroup> groups = to_const(D.groups);
+  const cptr<DiagTerm> terms = to_const(D.terms);
+  const char* lut = reinterpret_cast<const char*>(D.lut) + sizeof(cplx<R>) * (size_t)groups[0].lut_begin;
+  int c0 = 0;
+  for (int t = groups[0].term_begin; t < groups[0].term_end; ++t)
+    c0 += popc((i0 ^ (i0 >> terms[t].shift)) & terms[t].mask);
+  int d[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) d[k] = row[8 + k] - 2 * popc(i0 & (uint32_t)row[12 + k]);
+  const int q01 = row[1], q02 = row[2], q03 = row[3], q12 = row[4], q13 = row[5], q23 = row[6];
+  int cnt[16];
+  cnt[0] = c0;
+#pragma unroll
+  for (int j = 1; j < 16; ++j) {
+    const int t = j >= 8 ? 3 : j >= 4 ? 2 : j >= 2 ? 1 : 0;
+    const int rest = j & ~(1 << t);
+    int qs = 0;
+    if (t == 1) qs = (rest & 1) ? q01 : 0;
+    if (t == 2) qs = ((rest & 1) ? q02 : 0) + ((rest & 2) ? q12 : 0);
+    if (t == 3) qs = ((rest & 1) ? q03 : 0) + ((rest & 2) ? q13 : 0) + ((rest & 4) ? q23 : 0);
+    cnt[j] = cnt[rest] + (d[t] + qs);
+  }
+#pragma unroll
+  for (int j0 = 0; j0 < 16; j0 += 8) {
+    cplx<R> v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      v[k] = *reinterpret_cast<const cplx<R>*>(lut + (uint32_t)cnt[j0 + k] * (uint32_t)sizeof(cplx<R>));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[j0 + k] = kConj ? cmulc(a[j0 + k], v[k]) : cmul(a[j0 + k], v[k]);
   }
 }
 

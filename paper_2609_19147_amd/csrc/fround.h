@@ -166,6 +166,28 @@ inline void fround_unitary2(const std::complex<double>* U, cplx<float>* out, Nor
 
 // Entries in device precision: unit-modulus ones as fround_phase, anything
 // else to nearest.
+// A tile pass's store scale in float: among the floats within two ulp of the
+// nearest, the one whose norm factor (f / x)^2 best cancels the running
+// deviation (the scale carries the normalisation of factored rotations and
+// of unscaled butterflies, so its rounding acts like a rotation's).
+inline double fround_scale(double x, NormAcc& acc) {
+  if (fround_exact(x)) return x;
+  const float f0 = (float)x;
+  double best = f0, best_e = INFINITY, best_dev = 0.0;
+  for (int k = -2; k <= 2; ++k) {
+    const double f = fround_step(f0, k);
+    const double dev = (f / x) * (f / x) - 1.0;
+    const double e = std::fabs(acc.sum + dev);
+    if (e < best_e) {
+      best_e = e;
+      best = f;
+      best_dev = dev;
+    }
+  }
+  acc.sum += best_dev;
+  return best;
+}
+
 template <class R>
 std::vector<cplx<R>> round_entries(const std::vector<std::complex<double>>& v) {
   std::vector<cplx<R>> o(v.size());

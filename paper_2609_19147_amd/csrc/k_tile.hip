@@ -169,6 +169,28 @@ __device__ __forceinline__ void op_ry(cplx<R>* a, cplx<R> c) {
     a[j | (1 << S)] = {c.im * x.re + c.re * y.re, c.im * x.im + c.re * y.im};
   }
 }
+// Factored rotations, the common factor applied at the store: [[1, -i t],
+// [-i t, 1]] and [[1, -t], [t, 1]], one multiply-add per output component.
+template <int S, class R>
+__device__ __forceinline__ void op_rxf(cplx<R>* a, R t) {
+#pragma unroll
+  for (int j = 0; j < RN; ++j) {
+    if (j & (1 << S)) continue;
+    const cplx<R> x = a[j], y = a[j | (1 << S)];
+    a[j] = {fma(t, y.im, x.re), fma(-t, y.re, x.im)};
+    a[j | (1 << S)] = {fma(t, x.im, y.re), fma(-t, x.re, y.im)};
+  }
+}
+template <int S, class R>
+__device__ __forceinline__ void op_ryf(cplx<R>* a, R t) {
+#pragma unroll
+  for (int j = 0; j < RN; ++j) {
+    if (j & (1 << S)) continue;
+    const cplx<R> x = a[j], y = a[j | (1 << S)];
+    a[j] = {fma(-t, y.re, x.re), fma(-t, y.im, x.im)};
+    a[j | (1 << S)] = {fma(t, x.re, y.re), fma(t, x.im, y.im)};
+  }
+}
 
 // ---- round patterns as functors: f(a, g) transforms the 16 registers of the
 // group whose smallest index is g (index bits outside the round).
@@ -198,6 +220,26 @@ struct FRx4 {
     op_rx<1>(a, ldc(c, 1));
     op_rx<2>(a, ldc(c, 2));
     op_rx<3>(a, ldc(c, 3));
+  }
+};
+template <class R>
+struct FRx4F {
+  cptr<cplx<R>> c;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const {
+    op_rxf<0>(a, c[0].re);
+    op_rxf<1>(a, c[1].re);
+    op_rxf<2>(a, c[2].re);
+    op_rxf<3>(a, c[3].re);
+  }
+};
+template <class R>
+struct FRy4F {
+  cptr<cplx<R>> c;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const {
+    op_ryf<0>(a, c[0].re);
+    op_ryf<1>(a, c[1].re);
+    op_ryf<2>(a, c[2].re);
+    op_ryf<3>(a, c[3].re);
   }
 };
 template <class R>
@@ -251,9 +293,8 @@ __device__ __forceinline__ DiagDev diag_slot(const DiagDev* slots, int d) {
   return D;
 }
 
-template <class R, bool kDiag>
+template <class R>
 struct RoundLoop {
-  const TileKArgs<R>& A;
   const Ctx& C;
   cptr<TileRound> R_;
   cplx<R>* T;
@@ -275,19 +316,55 @@ struct RoundLoop {
       cplx<R> a[RN];
 #pragma unroll
       for (int j = 0; j < RN; ++j) a[j] = Tg[loff[j]];
-      const uint32_t gglobal = C.base | C.dep(gpos);
-      if (kDiag && R_->diag >= 0) {
-        // register j holds index gglobal | dep(round bits of j)
-        const uint32_t b0 = C.dep(1u << t0), b1 = C.dep(1u << t1), b2 = C.dep(1u << t2), b3 = C.dep(1u << t3);
-        if (R_->qcoef >= 0)
-          diag_apply_angles<R>(a, gglobal, b0, b1, b2, b3, diag_slot(A.diag, R_->diag), A.coef + R_->qcoef);
-        else
-          diag_apply_round<R>(a, gglobal, b0, b1, b2, b3, diag_slot(A.diag, R_->diag), A.qtab + R_->qoff);
-      }
-      f(a, gglobal);
+      f(a, C.base | C.dep(gpos));
 #pragma unroll
       for (int j = 0; j < RN; ++j) Tg[loff[j]] = a[j];
     }
+  }
+};
+
+// RT_DIAG rounds: register j of the group at index g holds index g | b_j with
+// b_j the subset j of the round's state bits b[0..3].
+template <class R, bool kConj>
+struct FDiagLut {
+  DiagDev D;
+  cptr<int32_t> qt;
+  uint32_t b[4];
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const { diag_lut_round<R, kConj>(a, g, b, D, qt); }
+};
+template <class R, bool kConj>
+struct FDiagPair {
+  DiagDev D;
+  cptr<int32_t> row;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const { diag_pair_round<R, kConj>(a, g, D, row); }
+};
+template <class R, bool kConj, bool kFactored>
+struct FDiagPairRx4 {
+  DiagDev D;
+  cptr<int32_t> row;
+  cptr<cplx<R>> c;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const {
+    diag_pair_round<R, kConj>(a, g, D, row);
+    if constexpr (kFactored) {
+      op_rxf<0>(a, c[0].re);
+      op_rxf<1>(a, c[1].re);
+      op_rxf<2>(a, c[2].re);
+      op_rxf<3>(a, c[3].re);
+    } else {
+      op_rx<0>(a, ldc(c, 0));
+      op_rx<1>(a, ldc(c, 1));
+      op_rx<2>(a, ldc(c, 2));
+      op_rx<3>(a, ldc(c, 3));
+    }
+  }
+};
+template <class R>
+struct FDiagAngles {
+  DiagDev D;
+  const cplx<R>* qp;
+  uint32_t b[4];
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const {
+    diag_apply_angles<R>(a, g, b[0], b[1], b[2], b[3], D, qp);
   }
 };
 
@@ -373,8 +450,49 @@ __device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C,
   const cptr<cplx<R>> coef = to_const(A.coef);
   for (uint32_t r = 0; r < A.n_rounds; ++r) {
     const cptr<TileRound> R_ = rounds + r;
-    const RoundLoop<R, kDiag> L{A, C, R_, T, ngroups, nthr};
+    const RoundLoop<R> L{C, R_, T, ngroups, nthr};
     switch (R_->type) {
+      case RT_DIAG:
+        if constexpr (kDiag) {
+          const DiagDev D = diag_slot(A.diag, R_->diag);
+          const uint32_t b[4] = {C.dep(1u << R_->tbit[0]), C.dep(1u << R_->tbit[1]), C.dep(1u << R_->tbit[2]),
+                                 C.dep(1u << R_->tbit[3])};
+          if (R_->qcoef >= 0)
+            L(FDiagAngles<R>{D, A.coef + R_->qcoef, {b[0], b[1], b[2], b[3]}});
+          else if (D.conj)
+            L(FDiagLut<R, true>{D, to_const(A.qtab) + R_->qoff, {b[0], b[1], b[2], b[3]}});
+          else
+            L(FDiagLut<R, false>{D, to_const(A.qtab) + R_->qoff, {b[0], b[1], b[2], b[3]}});
+        }
+        break;
+      case RT_DIAG_PAIR:
+        if constexpr (kDiag) {
+          const DiagDev D = diag_slot(A.diag, R_->diag);
+          if (D.conj)
+            L(FDiagPair<R, true>{D, to_const(A.qtab) + R_->qoff});
+          else
+            L(FDiagPair<R, false>{D, to_const(A.qtab) + R_->qoff});
+        }
+        break;
+      case RT_DIAG_PAIR_RX:
+      case RT_DIAG_PAIR_RXF:
+        if constexpr (kDiag) {
+          const DiagDev D = diag_slot(A.diag, R_->diag);
+          const cptr<int32_t> row = to_const(A.qtab) + R_->qoff;
+          const cptr<cplx<R>> c = coef + R_->coef4;
+          if (R_->type == RT_DIAG_PAIR_RXF) {
+            if (D.conj)
+              L(FDiagPairRx4<R, true, true>{D, row, c});
+            else
+              L(FDiagPairRx4<R, false, true>{D, row, c});
+          } else {
+            if (D.conj)
+              L(FDiagPairRx4<R, true, false>{D, row, c});
+            else
+              L(FDiagPairRx4<R, false, false>{D, row, c});
+          }
+        }
+        break;
       case RT_QFT4:
         L(FQft4<R, false>{ops + R_->op_begin, coef});
         break;
@@ -392,6 +510,12 @@ __device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C,
         break;
       case RT_MAT4_RY:
         L(FRy4<R>{coef + R_->coef4});
+        break;
+      case RT_MAT4_RXF:
+        L(FRx4F<R>{coef + R_->coef4});
+        break;
+      case RT_MAT4_RYF:
+        L(FRy4F<R>{coef + R_->coef4});
         break;
       case RT_OP1: {
         const cptr<TileOp> op = ops + R_->op_begin;
@@ -534,12 +658,13 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel(TileKArgs<R> A) {
   tile_body<R, kDiag>(A, A.order ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x));
 }
 
-// complex64 passes without diagonal layers: registers capped at 128 so that
-// four waves fit per SIMD (two 512-thread workgroups of 2^13-amplitude tiles,
-// or four of 2^12, share a CU's LDS).
+// complex64 passes: registers capped at 128 so that four waves fit per SIMD
+// (two 512-thread workgroups of 2^13-amplitude tiles, or four of 2^12, share
+// a CU's LDS).
+template <bool kDiag>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 tile_kernel_c64(TileKArgs<float> A) {
-  tile_body<float, false>(A, A.order ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x));
+  tile_body<float, kDiag>(A, A.order ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---- software-pipelined tile passes ------------------------------------------
@@ -633,7 +758,8 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel_pipe(TileKArgs<R> A, 
 // resulting tiles, and both tiles are stored back -- 4 S of HBM traffic per
 // layer instead of 6 S for two passes and a separate re-read of both states.
 template <class R, bool kDiag>
-__global__ void __launch_bounds__(kMaxThreads) tile_kernel_dual(TileKArgs<R> A, cplx<R>* lam, RhoTileArgs Q,
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+tile_kernel_dual(TileKArgs<R> A, cplx<R>* lam, RhoTileArgs Q,
                                                                  double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[rho::kRhoMaxWaves][32];
@@ -683,7 +809,8 @@ __device__ __forceinline__ TileKArgs<R> load_args(const TileKArgs<R>* descs, uin
 // XCD-aware order of the workgroups) runs coset (v & (2^shift - 1)) of
 // instance (v >> shift).
 template <class R, bool kDiag>
-__global__ void __launch_bounds__(kMaxThreads) tile_kernel_batched(const TileKArgs<R>* __restrict__ descs,
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+tile_kernel_batched(const TileKArgs<R>* __restrict__ descs,
                                                                     uint32_t shift) {
   const uint32_t v = xcd_block(blockIdx.x, gridDim.x);
   tile_body<R, kDiag>(load_args(descs, v >> shift), v & ((1u << shift) - 1u));
@@ -694,13 +821,9 @@ inline uint32_t tile_threads(uint32_t m) {
   return threads < 64 ? 64 : (threads > (uint32_t)kMaxThreads ? (uint32_t)kMaxThreads : threads);
 }
 
-// The complex64 kernels with diagonal slots need more than 128 VGPRs (three
-// waves per SIMD, twelve per CU); 256-thread workgroups let two tiles of 2^13
-// amplitudes share a CU, so one tile's loads overlap the other's rounds.
 template <class R, bool kDiag>
 inline uint32_t tile_threads_for(uint32_t m) {
-  const uint32_t t = tile_threads(m);
-  return (kDiag && sizeof(R) == 4 && t > 256u) ? 256u : t;
+  return tile_threads(m);
 }
 
 // Dynamic LDS limit of the tile kernels: the largest tile (2^14 complex64 or
@@ -749,6 +872,17 @@ void launch_tile_k(const TileKArgs<R>& A, hipStream_t s) {
             tile_lds(A.m, sizeof(cplx<R>)), s, A);
 }
 
+template <bool kDiag>
+void launch_tile_c64(const TileKArgs<float>& A, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    allow_dynamic_lds((const void*)tile_kernel_c64<kDiag>, kTileDynLds, "tile_pass");
+    attr_set = true;
+  }
+  QS_LAUNCH("tile_pass", s, tile_kernel_c64<kDiag>, dim3(1u << (A.n - A.m)), dim3(tile_threads(A.m)),
+            tile_lds(A.m, sizeof(cplx<float>)), s, A);
+}
+
 // Workgroups of a pipelined pass: one per compute unit (at most one coset each).
 inline uint32_t pipe_grid(uint32_t n_cosets) {
   static int cus = 0;
@@ -782,18 +916,16 @@ void launch_tile(const TileKArgs<R>& A, hipStream_t s) {
               tile_lds(A.m, sizeof(cplx<R>)), s, A, n_cosets);
     return;
   }
-  if (A.diag != nullptr) {
-    launch_tile_k<R, true>(A, s);
-  } else if constexpr (sizeof(R) == 4) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      allow_dynamic_lds((const void*)tile_kernel_c64, kTileDynLds, "tile_pass");
-      attr_set = true;
-    }
-    QS_LAUNCH("tile_pass", s, tile_kernel_c64, dim3(1u << (A.n - A.m)), dim3(tile_threads(A.m)),
-              tile_lds(A.m, sizeof(cplx<R>)), s, A);
+  if constexpr (sizeof(R) == 4) {
+    if (A.diag != nullptr)
+      launch_tile_c64<true>(A, s);
+    else
+      launch_tile_c64<false>(A, s);
   } else {
-    launch_tile_k<R, false>(A, s);
+    if (A.diag != nullptr)
+      launch_tile_k<R, true>(A, s);
+    else
+      launch_tile_k<R, false>(A, s);
   }
 }
 

@@ -55,7 +55,7 @@ struct TileKArgs {
   const TileOp* ops;
   const cplx<R>* coef;
   const DiagDev* diag;  // the pass's diagonal slots (device memory), or null
-  const int8_t* qtab;   // pair coefficients of the diagonal rounds (TileRound::qoff)
+  const int32_t* qtab;  // pair coefficients of the diagonal rounds (TileRound::qoff)
   uint32_t L, a, h, m;
   uint32_t n_rounds;
   uint32_t n;

@@ -66,6 +66,18 @@ enum TileRoundType : int32_t {
   RT_QFT1 = 7,     // one QFT (or inverse QFT) stage, on any register bit
   RT_QH1 = 8,      // one QFT stage followed by H on the same register bit
   RT_OP1 = 9,      // one single-qubit op (MAT, DIAG or H) on any register bit
+  RT_DIAG = 10,    // device only: the round's diagonal slot, no ops (a planner round
+                   // with a diagonal becomes an RT_DIAG round followed by the round)
+  RT_DIAG_PAIR = 11,     // device only: RT_DIAG of a one-group layer whose count is a
+                         // sum of distinct bit-pair mismatches (pair table row flags)
+  RT_DIAG_PAIR_RX = 12,  // device only: RT_DIAG_PAIR, then the RT_MAT4_RX rotations
+  // device only, factored rotations: every a (RX, RY) with |b| <= 8 |a|, the
+  // kernel applies [[1, -i t], [-i t, 1]] (RY [[1, -t], [t, 1]]) with
+  // coef[coef4 + r] = (t, 0), t = b / a, and the pass's store scale carries
+  // the product of the a
+  RT_MAT4_RXF = 13,
+  RT_MAT4_RYF = 14,
+  RT_DIAG_PAIR_RXF = 15,
 };
 // The planner splits a round matching none of the patterns into a sequence of
 // rounds over the same register bits (RT_MAT4 groups and RT_QFT1 stages).
@@ -77,7 +89,7 @@ struct TileRound {
   int32_t diag_conj;         // 1: multiply by the conjugate phase (inverse)
   int32_t type;              // TileRoundType
   int32_t coef4;             // RT_MAT4*: coefficient offset of the four matrices
-  int32_t qoff;              // diag: byte offset of the round's pair table in the pass's
+  int32_t qoff;              // diag: word offset of the round's pair table in the pass's
                              // quadratic table, or -1 (evaluate every amplitude's counts)
   int32_t qcoef;             // diag, angle mode: coefficient offset of the six pair
                              // phases exp(i Q_kl); -1: lookup-table mode
@@ -101,8 +113,10 @@ struct DiagTerm {
   int32_t pad;
 };
 
-// Bytes per group in a diagonal round's pair table (see the round builder).
-constexpr int kPairRowBytes = 32;
+// 32-bit words per group in a diagonal round's pair table (see the round
+// builder): {quadratic flag, q01, q02, q03, q12, q13, q23, pair flag,
+// deg_0..deg_3, N_0..N_3}.
+constexpr int kPairRowWords = 16;
 
 struct DiagGroup {
   int32_t term_begin, term_end;  // into the layer's term array

@@ -720,6 +720,10 @@ double plan_cost(const PlanIR& P) {
 
 namespace {
 
+// Low bits kept by high tile passes with diagonal layers unless the plan
+// options say otherwise (-1: as many as the pass's group has).
+constexpr int kDefaultDiagLowBits = 6;
+
 struct Sched {
   int n;
   int L;                                // least low bits of a high tile
@@ -1169,20 +1173,20 @@ class Builder {
       T.L = sched.grp[best][0];
       T.a = sched.grp[best][1];
       T.h = sched.grp[best][2];
-      // A pass with diagonal slots runs a kernel with more registers (fewer
-      // waves per SIMD): it does better with smaller tiles, more of them per
-      // compute unit, than with longer HBM runs.  Such a high pass keeps only
-      // the minimum of low bits; ops on the bits given up wait for a later pass.
+      // diag_low_bits = k > 0: a high pass with diagonal layers keeps only k
+      // low bits (smaller tiles, more of them per compute unit, shorter HBM
+      // runs); ops on the bits given up wait for a later pass.
+      const int dl = P.opt.diag_low_bits == 0 ? kDefaultDiagLowBits : P.opt.diag_low_bits;
       bool has_diag = false;
       for (int idx : best_list) has_diag = has_diag || seg[idx].ir.type == 1;
-      if (has_diag && T.h > 0 && T.L > sched.L) {
-        const uint32_t small = ((1u << sched.L) - 1u) | (((1u << T.h) - 1u) << T.a);
+      if (dl > 0 && has_diag && T.h > 0 && T.L > dl) {
+        const uint32_t small = ((1u << dl) - 1u) | (((1u << T.h) - 1u) << T.a);
         std::vector<int> list;
         scan_mask(small, deps, done, list);
         bool diag_kept = false;
         for (int idx : list) diag_kept = diag_kept || seg[idx].ir.type == 1;
         if (diag_kept) {
-          T.L = sched.L;
+          T.L = dl;
           best_list = list;
         }
       }
@@ -1438,6 +1442,117 @@ void finalize_pass(const PlanIR& P, TilePassIR& T) {
   T.scale = std::pow(0.5, 0.5 * T.n_butterfly);
 }
 
+// Read / write masks of a pass item (the scheduler's conflict rule): an op
+// writes its bit, a QFT stage also reads the bits below it down to its
+// register base, a diagonal reads its support.
+void item_masks(const PlanIR& P, const ItemIR& it, uint32_t& W, uint32_t& R) {
+  if (it.type == 1) {
+    W = 0;
+    R = P.diags[it.index].support;
+    return;
+  }
+  const OpIR& o = P.ops[it.index];
+  W = 1u << o.bit;
+  R = (o.kind == OP_QFT || o.kind == OP_QFT_INV) ? ((1u << o.bit) - 1u) & ~((1u << o.base) - 1u) : 0u;
+}
+
+// Vector-ALU work of a finalized pass per group of 16 amplitudes, in units of
+// one register bit's 2x2 butterflies (64 lane operations): a four-bit round of
+// 2x2 matrices or rotations about 4.5, a one-op round 1.5, a diagonal round 3,
+// the tile's load and store 1.5.
+double pass_work(const TilePassIR& T) {
+  double w = 1.5;
+  for (const TileRound& r : T.rounds) {
+    if (r.op_end > r.op_begin) {
+      if (r.type == RT_OP1 || r.type == RT_QFT1 || r.type == RT_QH1) w += 1.5;
+      else if (r.type == RT_H4) w += 2.5;
+      else w += 4.5;
+    }
+    if (r.diag >= 0) w += 3.0;
+  }
+  return w;
+}
+
+// A pass with diagonal layers followed by another tile pass: single-qubit ops
+// after the pass's last diagonal, on bits that the next tile also holds,
+// commute past the rest of the pass when nothing after them in it touches
+// their bits, and may then run at the start of the next pass instead.  The
+// pass carrying the diagonal is the one whose arithmetic approaches the
+// memory time, so ops move (lowest bits first, as many as lower the larger
+// of the two passes' work) when that evens out the pair.
+void rebalance_diag_passes(PlanIR& P) {
+  for (size_t li = 0; li + 1 < P.layers.size(); ++li) {
+    if (P.layers[li].kind != L_TILE || P.layers[li + 1].kind != L_TILE) continue;
+    TilePassIR& A = P.passes[P.layers[li].index];
+    TilePassIR& B = P.passes[P.layers[li + 1].index];
+    int last = -1;
+    for (size_t k = 0; k < A.items.size(); ++k)
+      if (A.items[k].type == 1) last = (int)k;
+    if (last < 0) continue;
+    std::vector<int> cand;  // candidate bits, ascending
+    for (size_t k = last + 1; k < A.items.size(); ++k) {
+      const OpIR& o = P.ops[A.items[k].index];
+      if (o.kind == OP_QFT || o.kind == OP_QFT_INV || tile_pos(B, o.bit) < 0) continue;
+      if (std::find(cand.begin(), cand.end(), o.bit) == cand.end()) cand.push_back(o.bit);
+    }
+    if (cand.empty()) continue;
+    std::sort(cand.begin(), cand.end());
+    auto split = [&](uint32_t S, TilePassIR& A2, TilePassIR& B2) -> bool {
+      A2 = A;
+      B2 = B;
+      A2.items.assign(A.items.begin(), A.items.begin() + last + 1);
+      std::vector<ItemIR> moved;
+      for (size_t k = last + 1; k < A.items.size(); ++k) {
+        const ItemIR& it = A.items[k];
+        const OpIR& o = P.ops[it.index];
+        const bool mv = (S >> o.bit) & 1u && o.kind != OP_QFT && o.kind != OP_QFT_INV;
+        if (!mv) {
+          A2.items.push_back(it);
+          continue;
+        }
+        // every later item that stays must commute with it
+        uint32_t W, R;
+        item_masks(P, it, W, R);
+        for (size_t k2 = k + 1; k2 < A.items.size(); ++k2) {
+          const OpIR& o2 = P.ops[A.items[k2].index];
+          if ((S >> o2.bit) & 1u && o2.kind != OP_QFT && o2.kind != OP_QFT_INV) continue;
+          uint32_t W2, R2;
+          item_masks(P, A.items[k2], W2, R2);
+          if ((W & (W2 | R2)) || (W2 & R)) return false;
+        }
+        moved.push_back(it);
+      }
+      B2.items = moved;
+      B2.items.insert(B2.items.end(), B.items.begin(), B.items.end());
+      finalize_pass(P, A2);
+      finalize_pass(P, B2);
+      return true;
+    };
+    TilePassIR A0 = A, B0 = B;
+    finalize_pass(P, A0);
+    finalize_pass(P, B0);
+    double best = std::max(pass_work(A0), pass_work(B0));
+    uint32_t bestS = 0;
+    uint32_t S = 0;
+    for (int b : cand) {
+      S |= 1u << b;
+      TilePassIR A2, B2;
+      if (!split(S, A2, B2)) continue;
+      const double w = std::max(pass_work(A2), pass_work(B2));
+      if (w < best - 1e-9) {
+        best = w;
+        bestS = S;
+      }
+    }
+    if (bestS) {
+      TilePassIR A2, B2;
+      split(bestS, A2, B2);
+      A.items = A2.items;
+      B.items = B2.items;
+    }
+  }
+}
+
 }  // namespace
 
 std::vector<PairNeighbours> pair_neighbours(const DiagNumeric& num, int n) {
@@ -1489,6 +1604,7 @@ static PlanIR structured_plan(int n, std::vector<NGate> gates, size_t n_params, 
   P.windows = windows;
   Builder B(P, tile_bits, low_bits);
   B.run();
+  if (opt.balance_passes >= 0) rebalance_diag_passes(P);
   for (auto& T : P.passes) finalize_pass(P, T);
   return P;
 }

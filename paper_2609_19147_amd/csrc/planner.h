@@ -134,6 +134,10 @@ struct PlanOptions {
   int window_k = 5;       // dense-window fusion: largest window (< 4: off)
   int coset_order = 0;    // tile passes' workgroup -> coset order: 0 by geometry,
                           // 1 XCD-blocked, 2 launch order
+  int diag_low_bits = 0;  // high tile passes carrying diagonal layers: 0 default,
+                          // -1 the group's low bits, k > 0 at most k low bits
+  int balance_passes = 0; // >= 0: ops after a pass's last diagonal may move to
+                          // the next tile pass to even out the two (-1: off)
 };
 
 struct PlanIR {

@@ -39,17 +39,18 @@ constexpr int kAngleModeGroups = 3;
 // x AND y = xy for a bond on two register bits, linear or constant otherwise.
 // The kernel then evaluates the count at the group's base index and at the
 // four single-bit flips, and adds q_kl for every pair of set register bits.
-// Row per group (kPairRowBytes): {quadratic flag, q01, q02, q03, q12, q13,
-// q23, pair flag, deg_0..deg_3, 0, 0, 0, 0, N_0..N_3 as uint32}.  With the pair
-// flag set (a sum of distinct bit-pair mismatches) the kernel obtains the four
-// flipped counts from the base count as base + deg_k - 2 popcount(N_k & base)
-// instead of evaluating every term four more times.
+// Row per group (kPairRowWords 32-bit words): {quadratic flag, q01, q02, q03,
+// q12, q13, q23, pair flag, deg_0..deg_3, N_0..N_3}.  With the pair flag set
+// (a sum of distinct bit-pair mismatches) the kernel obtains the four flipped
+// counts from the base count as base + deg_k - 2 popcount(N_k & base) instead
+// of evaluating every term four more times.  Whole words keep every field a
+// scalar load in the kernel.
 void round_pair_table(const DiagNumeric& num, const std::vector<PairNeighbours>& pn, const int g[4],
-                      std::vector<int8_t>& out) {
+                      std::vector<int32_t>& out) {
   static const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
   for (size_t gi = 0; gi < num.groups.size(); ++gi) {
     const DiagGroup& G = num.groups[gi];
-    int8_t row[kPairRowBytes] = {1, 0};
+    int32_t row[kPairRowWords] = {1, 0};
     int q[6] = {0, 0, 0, 0, 0, 0};
     for (int t = G.term_begin; t < G.term_end; ++t) {
       const DiagTerm& T = num.terms[t];
@@ -63,20 +64,15 @@ void round_pair_table(const DiagNumeric& num, const std::vector<PairNeighbours>&
         if (hi - lo == T.shift && ((T.mask >> lo) & 1u)) q[e] += T.form == DT_SHIFT_XOR ? -2 : 1;
       }
     }
-    for (int e = 0; e < 6; ++e) {
-      if (q[e] < -127 || q[e] > 127) row[0] = 0;
-      row[1 + e] = (int8_t)q[e];
-    }
-    bool pairs = row[0] != 0 && pn[gi].ok;
-    for (int k = 0; k < 4 && pairs; ++k) pairs = pn[gi].deg[g[k]] <= 127;
-    if (pairs) {
+    for (int e = 0; e < 6; ++e) row[1 + e] = q[e];
+    if (row[0] != 0 && pn[gi].ok) {
       row[7] = 1;
       for (int k = 0; k < 4; ++k) {
-        row[8 + k] = (int8_t)pn[gi].deg[g[k]];
-        std::memcpy(row + 16 + 4 * k, &pn[gi].mask[g[k]], 4);
+        row[8 + k] = pn[gi].deg[g[k]];
+        std::memcpy(row + 12 + k, &pn[gi].mask[g[k]], 4);
       }
     }
-    out.insert(out.end(), row, row + kPairRowBytes);
+    out.insert(out.end(), row, row + kPairRowWords);
   }
 }
 
@@ -95,11 +91,13 @@ void round_pass_unitaries(const TilePassIR& T, const std::vector<TileRound>& rou
   for (const TileRound& r : rounds) {
     if (r.type == RT_MAT4) {
       for (int bb = 0; bb < 4; ++bb) mat2(r.coef4 + 4 * bb);
-    } else if (r.type == RT_MAT4_RX || r.type == RT_MAT4_RY) {
+    } else if (r.type == RT_MAT4_RX || r.type == RT_MAT4_RY || r.type == RT_DIAG_PAIR_RX) {
       for (int bb = 0; bb < 4; ++bb) {
         const cplx<float> f = fround_pair(coef[r.coef4 + bb], acc);
         cr[r.coef4 + bb] = {(R)f.re, (R)f.im};
       }
+    } else if (r.type == RT_MAT4_RXF || r.type == RT_MAT4_RYF || r.type == RT_DIAG_PAIR_RXF) {
+      continue;  // factored rotations: their norm is in the pass scale
     } else {
       for (int k = r.op_begin; k < r.op_end; ++k) {
         const TileOp& op = T.ops[k];
@@ -145,31 +143,90 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
   d.pass_coef.assign(P.passes.size(), 0);
   d.pass_diag.assign(P.passes.size(), 0);
   d.pass_qtab.assign(P.passes.size(), 0);
+  d.pass_nrounds.assign(P.passes.size(), 0);
+  d.pass_scale.assign(P.passes.size(), 1.0);
   for (size_t i = 0; i < P.passes.size(); ++i) {
     const TilePassIR& T = P.passes[i];
-    std::vector<TileRound> rounds;
-    std::vector<cd> coef = pass_coefficients_device(P, T, p.params, rounds);
-    std::vector<int8_t> qtab;
-    for (TileRound& r : rounds) {
+    std::vector<TileRound> planned, rounds;
+    std::vector<cd> coef = pass_coefficients_device(P, T, p.params, planned);
+    // A round's diagonal runs as a round of its own over the same register
+    // bits (RT_DIAG), so that the butterfly rounds' code carries no phase
+    // evaluation; a one-group layer in the pair-mismatch form has its own
+    // round (RT_DIAG_PAIR), fused with a following rotation round into one
+    // (RT_DIAG_PAIR_RX).
+    std::vector<int32_t> qtab;
+    for (TileRound r : planned) {
       r.qoff = -1;
       r.qcoef = -1;
-      if (r.diag < 0) continue;
+      if (r.diag < 0) {
+        rounds.push_back(r);
+        continue;
+      }
       int g[4];
       for (int k = 0; k < 4; ++k) g[k] = r.tbit[k] < T.L ? r.tbit[k] : r.tbit[k] - T.L + T.a;
-      r.qoff = (int32_t)qtab.size();
       const DiagNumeric& num = nums[T.diag_slots[r.diag]];
+      TileRound dr = r;
+      dr.op_end = dr.op_begin;
+      dr.coef4 = -1;
+      dr.type = RT_DIAG;
+      dr.qoff = (int32_t)qtab.size();
       round_pair_table(num, pns[T.diag_slots[r.diag]], g, qtab);
-      // angle mode for layers with many groups, all quadratic: the six pair
-      // phases exp(i sum_g theta_g q_g,kl) join the pass's coefficients
-      bool all_quad = num.groups.size() >= (size_t)kAngleModeGroups;
-      for (size_t gi = 0; gi < num.groups.size(); ++gi) all_quad = all_quad && qtab[r.qoff + kPairRowBytes * gi] != 0;
-      if (all_quad) {
-        r.qcoef = (int32_t)coef.size();
-        for (int e = 0; e < 6; ++e) {
-          double Q = 0.0;
-          for (size_t gi = 0; gi < num.groups.size(); ++gi) Q += num.theta[gi] * qtab[r.qoff + kPairRowBytes * gi + 1 + e];
-          coef.push_back(std::polar(1.0, Q));
+      const int32_t* row0 = qtab.data() + dr.qoff;
+      if (num.groups.size() == 1 && row0[0] && row0[7]) {
+        if (r.type == RT_MAT4_RX) {
+          r.type = RT_DIAG_PAIR_RX;
+          r.qoff = dr.qoff;
+          rounds.push_back(r);
+          continue;
         }
+        dr.type = RT_DIAG_PAIR;
+      } else {
+        // angle mode for layers with many groups, all quadratic: the six pair
+        // phases exp(i sum_g theta_g q_g,kl) join the pass's coefficients
+        bool all_quad = num.groups.size() >= (size_t)kAngleModeGroups;
+        for (size_t gi = 0; gi < num.groups.size(); ++gi)
+          all_quad = all_quad && qtab[dr.qoff + kPairRowWords * gi] != 0;
+        if (all_quad) {
+          dr.qcoef = (int32_t)coef.size();
+          for (int e = 0; e < 6; ++e) {
+            double Q = 0.0;
+            for (size_t gi = 0; gi < num.groups.size(); ++gi)
+              Q += num.theta[gi] * qtab[dr.qoff + kPairRowWords * gi + 1 + e];
+            coef.push_back(std::polar(1.0, Q));
+          }
+        }
+      }
+      rounds.push_back(dr);
+      r.diag = -1;
+      rounds.push_back(r);
+    }
+    d.pass_nrounds[i] = (uint32_t)rounds.size();
+    // Rotation rounds (RX / RY, alone or after a pair diagonal) whose four
+    // matrices all have |b| <= 8 |a| run factored: [[a, -i b], [-i b, a]] =
+    // a [[1, -i t], [-i t, 1]] with t = b / a (RY alike), one multiply-add
+    // per output component in the kernel, the factors a joining the pass
+    // scale applied at the store.  With t rounded to the state's precision
+    // the factor is taken as a sqrt((1 + t^2) / (1 + t'^2)), which keeps a
+    // unitary rotation unitary for the rounded t'.  The bound on |t| keeps the
+    // unnormalised amplitudes of a pass far from overflow.
+    double pscale = T.scale;
+    std::vector<int32_t> rot_coef;  // coefficient indices in factored form
+    for (TileRound& r : rounds) {
+      if (r.type != RT_MAT4_RX && r.type != RT_MAT4_RY && r.type != RT_DIAG_PAIR_RX) continue;
+      bool ok = true;
+      for (int bb = 0; bb < 4; ++bb) {
+        const cd e = coef[r.coef4 + bb];
+        ok = ok && e.real() != 0.0 && std::fabs(e.imag()) <= 8.0 * std::fabs(e.real());
+      }
+      if (!ok) continue;
+      r.type = r.type == RT_MAT4_RX ? RT_MAT4_RXF : (r.type == RT_MAT4_RY ? RT_MAT4_RYF : RT_DIAG_PAIR_RXF);
+      for (int bb = 0; bb < 4; ++bb) {
+        cd& e = coef[r.coef4 + bb];
+        rot_coef.push_back(r.coef4 + bb);
+        const double t = e.imag() / e.real();
+        const double tr = sizeof(R) == sizeof(float) ? (double)(float)t : t;
+        pscale *= e.real() * std::sqrt((1.0 + t * t) / (1.0 + tr * tr));
+        e = cd(tr, 0.0);
       }
     }
     if (!qtab.empty()) d.pass_qtab[i] = b.put(qtab);
@@ -177,6 +234,9 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
     d.pass_ops[i] = b.put(T.ops);
     std::vector<cplx<R>> cr = round_entries<R>(coef);
     if (sizeof(R) == sizeof(float)) round_pass_unitaries(T, rounds, coef, cr, acc);
+    for (int32_t k : rot_coef) cr[k] = {(R)coef[k].real(), (R)coef[k].imag()};
+    if (sizeof(R) == sizeof(float)) pscale = fround_scale(pscale, acc);
+    d.pass_scale[i] = pscale;
     d.pass_coef[i] = b.put(cr);
     // slot descriptors hold device addresses: filled in once the blob has one
     if (!T.diag_slots.empty()) d.pass_diag[i] = b.put(std::vector<DiagDev>(T.diag_slots.size()));
@@ -299,15 +359,15 @@ TileKArgs<R> tile_args(qs_state& s, qs_plan& p, int pass) {
   A.ops = (const TileOp*)(base + d.pass_ops[pass]);
   A.coef = (const cplx<R>*)(base + d.pass_coef[pass]);
   A.diag = d.pass_diag[pass] ? (const DiagDev*)(base + d.pass_diag[pass]) : nullptr;
-  A.qtab = (const int8_t*)(base + d.pass_qtab[pass]);
+  A.qtab = (const int32_t*)(base + d.pass_qtab[pass]);
   A.L = T.L;
   A.a = T.a;
   A.h = T.h;
   A.m = T.L + T.h;
   A.order = tile_order(P.opt.coset_order, T.L, T.a);
-  A.n_rounds = (uint32_t)T.rounds.size();
+  A.n_rounds = d.pass_nrounds[pass];
   A.n = s.n;
-  A.scale = T.scale;
+  A.scale = d.pass_scale[pass];
   return A;
 }
 template TileKArgs<float> tile_args<float>(qs_state&, qs_plan&, int);

@@ -71,6 +71,8 @@ struct PlanDev {
   std::vector<size_t> pass_rounds, pass_ops, pass_coef;
   std::vector<size_t> pass_diag;  // per pass: its diagonal slots as DiagDev[] (0: none)
   std::vector<size_t> pass_qtab;  // per pass: pair coefficients of its diagonal rounds
+  std::vector<uint32_t> pass_nrounds;  // per pass: device rounds (diagonals as rounds of their own)
+  std::vector<double> pass_scale;      // per pass: the store's scale (butterflies, factored rotations)
   std::vector<size_t> dense_mat, dense_mat_dagger;  // per dense block
   std::vector<size_t> plain_mat;  // per layer (only dense plain gates), else 0
 };

@@ -242,3 +242,58 @@ def test_empty_and_identity_plans(qs, dtype):
     qs.apply(st, qs.Plan(n, [W.G("RX", 3, theta=0.4), W.G("RX", 3, theta=-0.4)]))
     tol = INF64 if dtype == "c64" else INF128
     assert metrics.infidelity(st.download(), held.astype(np.complex128)) <= tol
+
+
+# ------------------------------------------------------------------ rotation layers
+# Rotation rounds run in factored form when every |tan| <= 8 (one multiply-add
+# per component, the cosines in the pass's store scale) and unfactored
+# otherwise; both forms, negative cosines and the fused diagonal-then-rotation
+# round are exercised, forward and through the inverse plan.
+ROT_ANGLES = {
+    "small": lambda q: 0.05 + 0.01 * q,
+    "wide": lambda q: -2.5 + 0.4 * q,
+    "near_pi": lambda q: math.pi - 0.01 * (q + 1),
+    "mixed": lambda q: [0.3, math.pi - 0.02, -1.1, 2.9, 0.7][q % 5],
+}
+
+
+@pytest.mark.parametrize("kind", ["RX", "RY"])
+@pytest.mark.parametrize("angles", sorted(ROT_ANGLES))
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_rotation_layers_factored_and_plain_forms(qs, kind, angles, dtype):
+    n = 16
+    f = ROT_ANGLES[angles]
+    stream = []
+    for layer in range(3):
+        stream += [W.G(kind, q, theta=f(q) * (1.0 + 0.1 * layer)) for q in range(n)]
+        stream += [W.G("RZZ", q, q + 1, theta=0.3 + 0.05 * layer) for q in range(n - 1)]
+    stream += [W.G(kind, q, theta=f(n - 1 - q)) for q in range(n)]
+    st, psi0 = start(qs, n, dtype)
+    plan = qs.Plan(n, stream, max_tile_bits=8)
+    qs.apply(st, plan)
+    ref = sv.run(psi0, n, stream)
+    compare(qs, st, ref, dtype, n)
+    assert abs(qs.norm2(st) - metrics.norm2(ref)) < (1e-6 if dtype == "c64" else 1e-13)
+    qs.apply(st, plan.inverse())
+    compare(qs, st, psi0, dtype, n)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("dl,bal", [(0, 0), (-1, 0), (-1, -1), (4, 0)])
+def test_tfim_diagonal_pass_options_match_oracle(qs, dtype, dl, bal):
+    n = 18
+    stream = W.tfim_strang_stream(n, 1.0, 0.8, 0.05, 6)
+    st, psi0 = start(qs, n, dtype)
+    qs.apply(st, qs.Plan(n, stream, max_tile_bits=10, diag_low_bits=dl, balance_passes=bal))
+    compare(qs, st, sv.run(psi0, n, stream), dtype, n)
+
+
+def test_long_rotation_runs_keep_the_norm(qs):
+    # 60 Strang steps at 20 qubits in complex64: the factored rotations' scales
+    # are rounded with the running norm compensation
+    n = 20
+    stream = W.tfim_strang_stream(n, 1.0, 0.9, 0.07, 60)
+    st, _ = start(qs, n, "c64")
+    before = qs.norm2(st)
+    qs.apply(st, qs.Plan(n, stream))
+    assert abs(qs.norm2(st) / before - 1.0) < 2e-6

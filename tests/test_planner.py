@@ -433,3 +433,62 @@ def test_mixed_streams_choose_windows_per_chunk():
     assert len(d["layers"]) < len(d0["layers"])
     # the structured head stays a tile pass: no window swallows the transform
     assert k[0] == "tile"
+
+
+@pytest.mark.parametrize("balance", [0, -1])
+@pytest.mark.parametrize("dl", [0, -1, 2, 4])
+def test_diagonal_pass_geometry_and_balance_options(balance, dl):
+    # every combination of the two knobs is the same operator
+    n = 14
+    st = W.tfim_strang_stream(n, 1.0, 0.8, 0.05, 4)
+    d = check_plan(n, st, psi0=sv.basis(n, 0), tol=1e-11, max_tile_bits=8, diag_low_bits=dl,
+                   balance_passes=balance)
+    assert set(kinds(d)) == {"tile"}
+    if dl > 0:
+        for L in d["layers"]:
+            if L["diags"] and L["h"] > 0:
+                assert L["L"] <= dl
+
+
+def test_balance_moves_ops_after_the_diagonal_to_the_next_pass():
+    # structure at 25 qubits: with balancing the diagonal-carrying passes hand
+    # trailing rotations on low bits to the following contiguous pass; the pass
+    # count and the total op count are unchanged
+    st = W.tfim_strang_stream(25, 1.0, 0.8, 0.05, 10)
+    on = qs.Plan(25, st, diag_low_bits=-1).describe()["layers"]
+    off = qs.Plan(25, st, diag_low_bits=-1, balance_passes=-1).describe()["layers"]
+    assert len(on) == len(off)
+    assert sum(len(L["ops"]) for L in on) == sum(len(L["ops"]) for L in off)
+    moved = 0
+    for a, b in zip(on, off):
+        if a["diags"]:
+            assert len(a["ops"]) <= len(b["ops"])
+            moved += len(b["ops"]) - len(a["ops"])
+    assert moved > 0
+    # and the semantics at a size the interpreter runs
+    n = 12
+    st12 = W.tfim_strang_stream(n, 1.0, 0.7, 0.1, 5)
+    d_on = check_plan(n, st12, psi0=sv.basis(n, 0), tol=1e-11, max_tile_bits=7, diag_low_bits=-1)
+    d_off = check_plan(n, st12, psi0=sv.basis(n, 0), tol=1e-11, max_tile_bits=7, diag_low_bits=-1,
+                       balance_passes=-1)
+    assert [len(L["ops"]) for L in d_on["layers"]] != [len(L["ops"]) for L in d_off["layers"]]
+
+
+def test_balance_keeps_qaoa_layers_exact():
+    # a random 3-regular MaxCut instance, angles bound as parameters
+    inst = W.qaoa_instances(1, 5, depth=3, n_choices=(12,))[0]
+    n = inst.n
+    stream = W.qaoa_stream(inst, param_offset=0, h_layer=True)
+    params = np.empty(6)
+    params[0::2], params[1::2] = inst.gammas, inst.betas
+    for tb in (5, 7):
+        for bal in (0, -1):
+            check_plan(n, stream, params=params, n_params=6, tol=1e-11, max_tile_bits=tb, balance_passes=bal)
+
+
+def test_option_ranges():
+    st = W.tfim_strang_stream(6, 1.0, 0.8, 0.05, 1)
+    for kw in ({"diag_low_bits": 1}, {"diag_low_bits": 9}, {"diag_low_bits": -2}, {"balance_passes": 1},
+               {"balance_passes": -2}):
+        with pytest.raises(qs.QsError):
+            qs.Plan(6, st, **kw)
