@@ -239,41 +239,48 @@ def qaoa_tile_bits(n):
     return max(6, min(14, (n + 4) // 2))
 
 
+def qaoa_plan(qs, inst, depth, opts):
+    prm = np.empty(2 * depth)
+    prm[0::2] = inst.gammas
+    prm[1::2] = inst.betas
+    return qs.Plan(inst.n, W.qaoa_stream(inst, param_offset=0, h_layer=False), n_params=2 * depth, params=prm,
+                   **opts)
+
+
+def qaoa_tuned_options(qs, insts, depth):
+    """Plan options per qubit count (tile limit x low bits of the diagonal
+    passes), tuned on a batch of 16 instances of that size and cached by the
+    tuner: a later process on the same device reads the cache and runs
+    nothing."""
+    from paper_2609_19147_amd.tune import TileTuner, option_grid
+    tuner = TileTuner()
+    out = {}
+    for n in sorted({i.n for i in insts}):
+        sample = [i for i in insts if i.n == n][:16]
+        built = {}
+
+        def run(opts, sample=sample, built=built):
+            key = tuple(sorted(opts.items()))
+            if key not in built:
+                built[key] = qs.Batch([qaoa_plan(qs, i, depth, opts) for i in sample], init="plus")
+            built[key].run()
+
+        tiles = range(max(8, qaoa_tile_bits(n) - 3), min(14, n - 2) + 1)
+        out[n] = tuner.best_options(f"qaoa-maxcut-p{depth}-batched", n, "c64", run,
+                                    option_grid(max_tile_bits=tiles, diag_low_bits=(0, -1)))
+        del built
+    return out
+
+
 def bench_batched_qaoa(qs, torch, count=512, depth=4, seed=512, reps=10):
     """512 MaxCut QAOA instances (n uniform over 16..24 even, 3-regular graphs,
     p = 4, angles U[0, pi)) as one recorded graph launch + one batched FP64
     expectation, against the per-instance fused and plain per-gate paths
     (plain-mode plans built beforehand); the three arms interleaved in every
     repeat."""
-    from paper_2609_19147_amd.tune import TileTuner
     insts = W.qaoa_instances(count, seed, depth=depth)
-
-    def angles(inst):
-        prm = np.empty(2 * depth)
-        prm[0::2] = inst.gammas
-        prm[1::2] = inst.betas
-        return prm
-
-    def make_plan(inst, tb):
-        return qs.Plan(inst.n, W.qaoa_stream(inst, param_offset=0, h_layer=False), n_params=2 * depth,
-                       max_tile_bits=tb, params=angles(inst))
-
-    # tile limit per qubit count, tuned on a batch of 16 instances (untimed)
-    tuner = TileTuner()
-    tile_bits = {}
-    for n in sorted({i.n for i in insts}):
-        sample = [i for i in insts if i.n == n][:16]
-        built = {}
-
-        def run(tb, sample=sample, built=built):
-            if tb not in built:
-                built[tb] = qs.Batch([make_plan(i, tb) for i in sample], init="plus")
-            built[tb].run()
-
-        cands = range(max(8, qaoa_tile_bits(n) - 3), min(14, n - 2) + 1)
-        tile_bits[n] = tuner.best(f"qaoa-maxcut-p{depth}-batched", n, "c64", run, cands)
-        del built
-    plans = [make_plan(inst, tile_bits[inst.n]) for inst in insts]
+    options = qaoa_tuned_options(qs, insts, depth)
+    plans = [qaoa_plan(qs, inst, depth, options[inst.n]) for inst in insts]
     plain = [qs.Plan(inst.n, W.qaoa_stream(inst, h_layer=False), mode="plain") for inst in insts]
     obs = [W.maxcut_terms(inst.edges) for inst in insts]
     t0 = time.perf_counter()
@@ -325,7 +332,7 @@ def bench_batched_qaoa(qs, torch, count=512, depth=4, seed=512, reps=10):
             "max_abs_diff_vs_fused": float(np.max(np.abs(res["batched"] - res["fused"]))),
             "max_norm_drift_batched": float(np.max(np.abs(norms - 1.0))),
             "mean_cut": round(float(np.mean(res["batched"])), 4),
-            "tile_bits_by_n": {str(k): v for k, v in tile_bits.items()}}
+            "options_by_n": {str(k): v for k, v in sorted(options.items())}}
 
 
 def bench_adjoint(qs, torch, n=24, layers=8, seed=24, ps_sample=8, reps=10):
@@ -710,6 +717,37 @@ def manifest(qs, torch):
             "timing": "HIP events on the library stream + host wall clock around K steps, synchronised"}
 
 
+def profile_run(qs, torch, name):
+    """One warm application of a section's fused path alone (no plain or
+    per-instance arms): what rocprofv3 counter runs attach to."""
+    if name == "tfim25":
+        n = 25
+        plan = qs.Plan(n, W.tfim_strang_stream(n, 1.0, 0.8, 0.05, 40))
+        st = qs.State(n, "c64")
+
+        def run():
+            st.set_basis(0)
+            qs.apply(st, plan)
+    elif name == "batched_qaoa":
+        # plan options from the tuner's cache (a bench.py --only batched_qaoa
+        # run in the same environment fills it; otherwise the tuning runs here)
+        depth = 4
+        insts = W.qaoa_instances(512, 512, depth=depth)
+        options = qaoa_tuned_options(qs, insts, depth)
+        B = qs.Batch([qaoa_plan(qs, i, depth, options[i.n]) for i in insts], init="plus")
+
+        def run():
+            B.run()
+    else:
+        raise SystemExit(f"no profile run for {name}")
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    return {"profile_run": name, "ms": round(1e3 * (time.perf_counter() - t0), 3)}
+
+
 SECTIONS = {
     "batched_qaoa": lambda qs, torch: bench_batched_qaoa(qs, torch),
     "adjoint": lambda qs, torch: bench_adjoint(qs, torch),
@@ -736,6 +774,8 @@ def main():
                     help="also run one plain device copy of the state (2 S bytes) as a counter calibration")
     ap.add_argument("--only", choices=sorted(SECTIONS),
                     help="run one extra section alone and print its JSON (a profiling aid; not the benchmark line)")
+    ap.add_argument("--profile-run", choices=["tfim25", "batched_qaoa"],
+                    help="one warm application of a section's fused path, for counter runs (not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU only; sharding over several GPUs is "
@@ -747,6 +787,9 @@ def main():
 
     if args.only:
         print(json.dumps({args.only: SECTIONS[args.only](qs, torch)}))
+        return
+    if args.profile_run:
+        print(json.dumps(profile_run(qs, torch, args.profile_run)))
         return
 
     n = args.n

@@ -27,3 +27,33 @@ def test_picks_fastest_and_caches(tmp_path):
     # other keys are tuned separately
     assert t2.best("qaoa", 22, "c64", run, [12]) == 12
     assert len(json.loads(path.read_text())) == 2
+
+
+def test_option_grid_and_best_options(tmp_path):
+    from paper_2609_19147_amd.tune import option_grid
+    grid = option_grid(max_tile_bits=(12, 13), diag_low_bits=(0, -1))
+    assert grid == [{"diag_low_bits": 0, "max_tile_bits": 12}, {"diag_low_bits": 0, "max_tile_bits": 13},
+                    {"diag_low_bits": -1, "max_tile_bits": 12}, {"diag_low_bits": -1, "max_tile_bits": 13}]
+    try:
+        option_grid(tile=(1,))
+        raise AssertionError("unknown option accepted")
+    except ValueError:
+        pass
+    calls = []
+
+    def run(opts):
+        calls.append(opts)
+        time.sleep(0.001 if opts == {"diag_low_bits": -1, "max_tile_bits": 12} else 0.004)
+
+    path = tmp_path / "tune.json"
+    t = TileTuner(str(path), device="test-gpu", sync=lambda: None)
+    best = t.best_options("tfim", 25, "c64", run, grid, reps=2)
+    assert best == {"diag_low_bits": -1, "max_tile_bits": 12}
+    assert len(calls) == 4 * 3
+    calls.clear()
+    t2 = TileTuner(str(path), device="test-gpu", sync=lambda: None)
+    assert t2.best_options("tfim", 25, "c64", run, grid) == best
+    assert calls == []
+    # the tile-only entry and the options entry of one workload do not collide
+    assert t2.best("tfim", 25, "c64", lambda tb: None, [13]) == 13
+    assert len(json.loads(path.read_text())) == 2
