@@ -60,6 +60,7 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
   // host-side validation of every parameter occurrence first (no device work on failure)
   std::vector<std::vector<GradEntry>> entries = grad_entries(P, p.params);
   qs_plan& inv = p.inverse();
+  const TableUse use_fwd(p, psi.dtype, psi.stream), use_inv(inv, psi.dtype, psi.stream);
   const size_t L = P.layers.size();
   // Pauli terms -> bit masks, sorted by x, complex coefficient c * i^{#Y}
   struct T3 {
@@ -83,7 +84,7 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
   std::stable_sort(ts.begin(), ts.end(), [](const T3& a, const T3& b) { return a.x < b.x; });
 
   // forward
-  apply_layers(psi, p, 0, L);
+  apply_layers(psi, p, 0, L, false);
   qs_state& phi = work_state(psi, 0);
   qs_state& lam = work_state(psi, 1);
   copy_state<R>(phi, psi);
@@ -216,8 +217,8 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
       if (!launch_tile_dual<R>(A, (cplx<R>*)lam.cur_ptr(), dual_rho[fl], part, res + tile_slot[fl], psi.stream))
         fail(QS_EDEVICE, "internal: fused adjoint pass rejected its tiles");
     } else {
-      apply_layers(phi, inv, j, j + 1);
-      apply_layers(lam, inv, j, j + 1);
+      apply_layers(phi, inv, j, j + 1, false);
+      apply_layers(lam, inv, j, j + 1, false);
     }
     const cplx<R>* ph = (const cplx<R>*)phi.cur_ptr();
     const cplx<R>* la = (const cplx<R>*)lam.cur_ptr();

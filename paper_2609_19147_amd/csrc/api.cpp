@@ -372,6 +372,19 @@ extern "C" qs_status qs_plan_describe(const qs_plan* p, char* buf, size_t cap, s
 }
 
 qs_plan::~qs_plan() {
+  // work that reads the tables, and a pending upload, finish first
+  for (int k = 0; k < 2; ++k) {
+    for (auto& u : users[k]) {
+      if (u.done) hipEventSynchronize(u.done);
+      if (u.done && !u.external) hipEventDestroy(u.done);
+      if (u.external && u.batch) qs::batch_plan_freed(u.batch, this);
+    }
+    if (ready[k]) {
+      hipEventSynchronize(ready[k]);
+      hipEventDestroy(ready[k]);
+    }
+    if (staging[k]) hipHostFree(staging[k]);
+  }
   for (auto& d : dev)
     if (d.blob) hipFree(d.blob);
   delete inv;

@@ -42,6 +42,8 @@ struct qs_batch {
   size_t red_doubles = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after every run: the plans order table updates after it
+  bool plan_freed = false;    // a plan was freed while the batch lived: it no longer runs
   // observables stored by qs_batch_set_observables: device tables, results
   // and partials in one allocation, descriptors in group order
   void* obs_dev = nullptr;
@@ -56,6 +58,11 @@ qs_batch::~qs_batch() {
   if (exec) hipGraphExecDestroy(exec);
   if (graph) hipGraphDestroy(graph);
   if (stream) hipStreamSynchronize(stream);
+  if (done) {
+    for (qs_plan* p : plans)
+      if (p) p->remove_external_user(dtype, done);
+    hipEventDestroy(done);
+  }
   if (desc) hipFree(desc);
   if (red) hipFree(red);
   if (arena) hipFree(arena);
@@ -262,12 +269,25 @@ extern "C" qs_status qs_batch_create(size_t n_inst, const int* n_qubits, const q
   }
 }
 
+namespace qs {
+void batch_plan_freed(qs_batch* b, const qs_plan* p) {
+  for (auto& q : b->plans)
+    if (q == p) {
+      q = nullptr;
+      b->plan_freed = true;
+    }
+}
+}  // namespace qs
+
 extern "C" qs_status qs_batch_refresh(qs_batch* b) {
   try {
     if (!b) fail(QS_EINVAL, "batch is NULL");
+    if (b->plan_freed) fail(QS_EINVAL, "a plan of the batch has been freed");
     for (auto* p : b->plans)
       if (!p->bound) fail(QS_EINVAL, "plan parameters are not bound");
     check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    if (!b->done) check_hip(hipEventCreateWithFlags(&b->done, hipEventDisableTiming), "hipEventCreateWithFlags");
+    for (qs_plan* p : b->plans) p->add_external_user(b->dtype, b->stream, b->done, b);
     if (b->exec) {
       hipGraphExecDestroy(b->exec);
       b->exec = nullptr;
@@ -303,9 +323,14 @@ extern "C" qs_status qs_batch_refresh(qs_batch* b) {
 extern "C" qs_status qs_batch_run(qs_batch* b) {
   try {
     if (!b || !b->exec) fail(QS_EINVAL, "batch is NULL or not recorded");
+    if (b->plan_freed) fail(QS_EINVAL, "a plan of the batch has been freed");
+    // tables re-uploaded since the batch last read them: wait for them on the
+    // batch's stream (device-side)
+    for (qs_plan* p : b->plans) p->sync_external_user(b->dtype, b->done, b->stream);
     prof_begin("batch_graph", b->stream);
     check_hip(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
     prof_end(b->stream);
+    check_hip(hipEventRecord(b->done, b->stream), "hipEventRecord");
     return QS_OK;
   } catch (const Error& e) {
     g_last_error = e.msg;

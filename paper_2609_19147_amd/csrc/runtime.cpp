@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 
 namespace qs {
 
@@ -317,16 +318,119 @@ qs_plan& qs_plan::inverse() {
   return *inv;
 }
 
-void qs_plan::refresh_device() {
-  bool any = dev[0].blob || dev[1].blob;
-  if (!any) return;
-  // kernels already enqueued may still read the tables
-  check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
-  for (int k = 0; k < 2; ++k)
-    if (dev[k].blob) {
-      dev[k].valid = false;
-      device_for((qs_dtype)k);
+namespace {
+
+// The library's stream for table uploads on the current device (default
+// priority, non-blocking: it never waits for the null stream).
+hipStream_t upload_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) fail(QS_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev]) check_hip(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  return streams[dev];
+}
+
+qs_plan::TableUser& user_of(std::vector<qs_plan::TableUser>& users, hipStream_t s) {
+  for (auto& u : users)
+    if (u.stream == s && !u.external) return u;
+  qs_plan::TableUser u;
+  u.stream = s;
+  check_hip(hipEventCreateWithFlags(&u.done, hipEventDisableTiming), "hipEventCreateWithFlags");
+  users.push_back(u);
+  return users.back();
+}
+
+}  // namespace
+
+const PlanDev& qs_plan::acquire(qs_dtype dt, hipStream_t s) {
+  const PlanDev& d = device_for(dt);
+  TableUser& u = user_of(users[dt], s);
+  if (u.seen < uploads[dt]) {
+    check_hip(hipStreamWaitEvent(s, ready[dt], 0), "hipStreamWaitEvent");
+    u.seen = uploads[dt];
+  }
+  return d;
+}
+
+void qs_plan::release(qs_dtype dt, hipStream_t s) {
+  check_hip(hipEventRecord(user_of(users[dt], s).done, s), "hipEventRecord");
+}
+
+void qs_plan::add_external_user(qs_dtype dt, hipStream_t s, hipEvent_t done, qs_batch* b) {
+  device_for(dt);
+  for (auto& u : users[dt])
+    if (u.external && u.done == done) return;
+  TableUser u;
+  u.stream = s;
+  u.done = done;
+  u.external = true;
+  u.batch = b;
+  u.seen = uploads[dt];  // the batch waits when it (re)reads the tables
+  users[dt].push_back(u);
+}
+
+void qs_plan::sync_external_user(qs_dtype dt, hipEvent_t done, hipStream_t s) {
+  for (auto& u : users[dt])
+    if (u.external && u.done == done) {
+      if (u.seen < uploads[dt]) {
+        check_hip(hipStreamWaitEvent(s, ready[dt], 0), "hipStreamWaitEvent");
+        u.seen = uploads[dt];
+      }
+      return;
     }
+}
+
+void qs_plan::remove_external_user(qs_dtype dt, hipEvent_t done) {
+  auto& v = users[dt];
+  for (size_t k = 0; k < v.size(); ++k)
+    if (v[k].external && v[k].done == done) {
+      v.erase(v.begin() + (long)k);
+      return;
+    }
+}
+
+void qs_plan::refresh_device() {
+  for (int k = 0; k < 2; ++k) {
+    PlanDev& d = dev[k];
+    if (!d.blob) continue;
+    PlanDev nd;
+    Blob b;
+    if (k == QS_C64) build_blob<float>(*this, nd, b);
+    else build_blob<double>(*this, nd, b);
+    if (b.bytes.size() != d.bytes) {
+      // a different table size (never for a parameter update of one plan):
+      // wait for the readers, then rebuild in place of the old tables
+      for (auto& u : users[k]) check_hip(hipEventSynchronize(u.done), "hipEventSynchronize");
+      d.valid = false;
+      device_for((qs_dtype)k);
+      continue;
+    }
+    fill_slots(ir, nd, (const char*)d.blob, b);
+    // the staging buffer is free once the previous upload has run
+    if (uploads[k]) check_hip(hipEventSynchronize(ready[k]), "hipEventSynchronize");
+    if (staging_cap[k] < b.bytes.size()) {
+      if (staging[k]) check_hip(hipHostFree(staging[k]), "hipHostFree");
+      staging[k] = nullptr;
+      staging_cap[k] = 0;
+      check_hip(hipHostMalloc(&staging[k], b.bytes.size(), hipHostMallocDefault), "hipHostMalloc(plan tables)");
+      staging_cap[k] = b.bytes.size();
+    }
+    if (!ready[k]) check_hip(hipEventCreateWithFlags(&ready[k], hipEventDisableTiming), "hipEventCreateWithFlags");
+    std::memcpy(staging[k], b.bytes.data(), b.bytes.size());
+    const hipStream_t up = upload_stream();
+    for (auto& u : users[k]) check_hip(hipStreamWaitEvent(up, u.done, 0), "hipStreamWaitEvent");
+    check_hip(hipMemcpyAsync(d.blob, staging[k], b.bytes.size(), hipMemcpyHostToDevice, up), "hipMemcpyAsync(plan tables)");
+    check_hip(hipEventRecord(ready[k], up), "hipEventRecord");
+    uploads[k] += 1;
+    // host-side kernel arguments (offsets are unchanged; scales follow the parameters)
+    nd.blob = d.blob;
+    nd.bytes = d.bytes;
+    nd.valid = true;
+    d = std::move(nd);
+  }
 }
 
 namespace qs {
@@ -498,10 +602,18 @@ double distance_t(qs_state& a, qs_state& b, double ar, double ai, double bs) {
 
 }  // namespace
 
-void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last) {
+void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last, bool track) {
   s.plain_acc = NormAcc{};  // plain layers' rounding compensation restarts with every call
+  if (track) {
+    // nothing is recorded into a stream that is being captured
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    check_hip(hipStreamIsCapturing(s.stream, &cs), "hipStreamIsCapturing");
+    track = cs == hipStreamCaptureStatusNone;
+  }
+  if (track) p.acquire(s.dtype, s.stream);
   if (s.dtype == QS_C64) apply_layers_t<float>(s, p, first, last);
   else apply_layers_t<double>(s, p, first, last);
+  if (track) p.release(s.dtype, s.stream);
 }
 
 void apply_plain_gate(qs_state& s, const NGate& g, const std::vector<double>& params, bool inverse) {
@@ -536,7 +648,7 @@ void apply_graph(qs_state& s, qs_plan& p) {
   }
   if (P.layers.empty()) return;
   if (gather) s.ensure_other();
-  p.device_for(s.dtype);
+  p.acquire(s.dtype, s.stream);
   PlanGraphEntry* hit = nullptr;
   for (auto& e : s.graphs)
     if (e.plan_uid == p.uid && e.version == p.version && e.cur0 == s.cur) hit = &e;
@@ -553,7 +665,7 @@ void apply_graph(qs_state& s, qs_plan& p) {
     s.stream = s.capture_stream;
     check_hip(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-      apply_layers(s, p, 0, P.layers.size());
+      apply_layers(s, p, 0, P.layers.size(), false);
     } catch (...) {
       hipGraph_t gg = nullptr;
       hipStreamEndCapture(s.stream, &gg);
@@ -586,6 +698,7 @@ void apply_graph(qs_state& s, qs_plan& p) {
   prof_begin("plan_graph", s.stream);
   check_hip(hipGraphLaunch(hit->exec, s.stream), "hipGraphLaunch");
   prof_end(s.stream);
+  p.release(s.dtype, s.stream);
   s.cur = hit->cur1;
 }
 
@@ -608,8 +721,10 @@ double apply_norm2(qs_state& s, qs_plan& p) {
   }
   s.ensure_red();
   s.ensure_norm(tiles);
+  p.acquire(s.dtype, s.stream);
   if (s.dtype == QS_C64) apply_layers_t<float>(s, p, 0, L, s.norm_part);
   else apply_layers_t<double>(s, p, 0, L, s.norm_part);
+  p.release(s.dtype, s.stream);
   launch_fold_partials(s.norm_part, tiles, s.red_partials, s.red_out, s.stream);
   double o;
   check_hip(hipMemcpyAsync(&o, s.red_out, sizeof o, hipMemcpyDeviceToHost, s.stream), "hipMemcpyAsync");

@@ -97,15 +97,70 @@ struct qs_plan {
   qs_plan* inv = nullptr;        // inverse plan (adjoint sweeps), built on demand
   uint64_t inv_version = 0;
 
+  // Stream ordering of the device tables (per precision).  Every stream that
+  // runs work reading the tables is listed with an event recorded after its
+  // latest such work (release); a parameter update stages the new tables in
+  // pinned memory, makes the library's upload stream wait for those events
+  // (device-side waits: neither the host nor other streams stall) and uploads
+  // there, recording `ready`; each reading stream waits for `ready` once per
+  // update before its next work (acquire).  A batch lists its stream with an
+  // event it records itself after every run (external: not owned here).
+  struct TableUser {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint64_t seen = 0;      // uploads this stream has waited for
+    bool external = false;  // event owned by the caller (a batch)
+    qs_batch* batch = nullptr;  // that caller, told when the plan is freed first
+  };
+  std::vector<TableUser> users[2];
+  hipEvent_t ready[2] = {nullptr, nullptr};
+  uint64_t uploads[2] = {0, 0};
+  void* staging[2] = {nullptr, nullptr};  // pinned host image of the last upload
+  size_t staging_cap[2] = {0, 0};
+
   void refresh_device();  // rebuild the tables of every precision already on the device
   const qs::PlanDev& device_for(qs_dtype dt);
+  // device tables for work about to be enqueued on s (waits, on s, for a
+  // pending update), and the mark after that work is enqueued
+  const qs::PlanDev& acquire(qs_dtype dt, hipStream_t s);
+  void release(qs_dtype dt, hipStream_t s);
+  // a batch's stream and completion event as a user of the tables
+  void add_external_user(qs_dtype dt, hipStream_t s, hipEvent_t done, qs_batch* b);
+  void remove_external_user(qs_dtype dt, hipEvent_t done);
+  // that user's stream waits for an upload it has not seen yet
+  void sync_external_user(qs_dtype dt, hipEvent_t done, hipStream_t s);
   qs_plan& inverse();     // the inverse plan with the current parameters
   ~qs_plan();
 };
 
 namespace qs {
 
-void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last);
+// A plan of batch b is being freed: the batch drops its pointer to it and
+// refuses to run from then on (its recorded launches read the plan's tables).
+void batch_plan_freed(qs_batch* b, const qs_plan* p);
+
+// acquire on construction, release on scope exit (also when an error unwinds
+// a sequence of enqueued work).
+struct TableUse {
+  qs_plan& p;
+  qs_dtype dt;
+  hipStream_t s;
+  TableUse(qs_plan& p_, qs_dtype dt_, hipStream_t s_) : p(p_), dt(dt_), s(s_) { p.acquire(dt, s); }
+  ~TableUse() {
+    try {
+      p.release(dt, s);
+    } catch (...) {
+    }
+  }
+  TableUse(const TableUse&) = delete;
+  TableUse& operator=(const TableUse&) = delete;
+};
+
+// Layers [first, last) on the state's stream.  track: order the work against
+// parameter updates of p (acquire / release; skipped while the stream is
+// being captured); callers that bracket a sequence of calls themselves pass
+// false.
+void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last, bool track = true);
 // Kernel arguments of tile pass `pass` of plan p applied to state s (device
 // tables made on first use); norm_part unset.
 template <class R>

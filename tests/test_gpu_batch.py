@@ -287,3 +287,22 @@ def test_batched_pair_count_observables_against_per_state_reduction(qs):
         assert abs(qs.expect(st, obs[k]) - got[k]) < 1e-9
         ref = sv.run(sv.basis(n, 0), n, plans[k].gates)
         assert abs(sv.expect(ref, n, obs[k]) - got[k]) < 1e-5
+
+
+def test_freeing_a_plan_before_its_batch(qs):
+    # the batch notices that one of its plans was freed and refuses to run
+    # (its recorded launches read that plan's tables); freeing the batch
+    # afterwards touches no freed plan
+    insts, plans, B = qaoa_batch(qs, 3, 11, 1, (8,))
+    B.run()
+    import torch
+    torch.cuda.synchronize()
+    doomed = plans[1]
+    lib = qs._lib.lib()
+    lib.qs_plan_free(doomed.h)
+    doomed.h = None
+    with pytest.raises(qs.QsError):
+        B.run()
+    with pytest.raises(qs.QsError):
+        B.refresh()
+    del B

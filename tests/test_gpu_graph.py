@@ -80,3 +80,35 @@ def test_graph_falls_back_for_host_staged_gates(qs):
     qs.apply_graph(a, plan)
     qs.apply(b, plan)
     assert np.array_equal(a.download(), b.download())
+
+
+def test_parameter_updates_are_ordered_after_enqueued_work(qs):
+    # set_params uploads the new tables on the library's upload stream after
+    # the work already enqueued on any stream that reads them: an apply that
+    # is still running keeps its parameters, applies after the update see the
+    # new ones, with no device-wide synchronisation in between
+    import torch
+    n = 20
+    stream = W.hea_stream(n, 6)
+    plan = qs.Plan(n, stream, n_params=12 * n)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = qs.State(n, "c64", stream=s1)
+    b = qs.State(n, "c64", stream=s2)
+    p0, p1 = W.hea_params(n, 6, 1), W.hea_params(n, 6, 2)
+    plan.set_params(p0)
+    qs.apply(a, plan)          # warm: tables on the device
+    a.sync()
+    ref_a = sv.run(sv.run(sv.basis(n, 0), n, stream, p0), n, stream, p0)
+    ref_b = sv.run(sv.basis(n, 0), n, stream, p1)
+    for _ in range(3):
+        a.set_basis(0)
+        b.set_basis(0)
+        plan.set_params(p0)
+        qs.apply(a, plan)      # enqueued on s1, reads the p0 tables
+        qs.apply_graph(a, plan)
+        plan.set_params(p1)    # no host wait for s1
+        qs.apply(b, plan)      # s2, after the p1 upload
+        a.sync()
+        b.sync()
+        assert metrics.infidelity(a.download().astype(np.complex128), ref_a) < 1e-9
+        assert metrics.infidelity(b.download().astype(np.complex128), ref_b) < 1e-9
