@@ -152,6 +152,12 @@ typedef struct qs_batch qs_batch;
 const char* qs_last_error(void);
 /* Version string and the device architecture the library was built for. */
 const char* qs_version(void);
+/* Device bytes the library holds in amplitude buffers it allocated (states,
+ * scratch halves, adjoint work states and scratch, batch arenas), and the cap
+ * on them: the environment variable QS_MAX_BYTES (bytes, read at the first
+ * allocation; unset or 0: no cap).  An allocation that would exceed the cap
+ * fails with QS_ENOMEM before any device call.  Either pointer may be NULL. */
+qs_status qs_memory_info(size_t* held, size_t* cap);
 
 /* ---- states (Section "State Management": a flat amplitude array) ------- */
 

@@ -32,6 +32,13 @@ def version() -> str:
     return lib().qs_version().decode()
 
 
+def memory_info():
+    """(bytes held in library-allocated amplitude buffers, QS_MAX_BYTES cap or 0)."""
+    held, cap = C.c_size_t(), C.c_size_t()
+    check(lib().qs_memory_info(C.byref(held), C.byref(cap)))
+    return held.value, cap.value
+
+
 # ------------------------------------------------------------------ marshalling
 class CGates:
     """A C array of qs_gate plus the matrix buffers it points into."""

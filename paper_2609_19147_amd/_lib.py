@@ -50,6 +50,7 @@ SZ = C.c_size_t
 _SIGS = {
     "qs_last_error": ([], C.c_char_p),
     "qs_version": ([], C.c_char_p),
+    "qs_memory_info": ([C.POINTER(SZ), C.POINTER(SZ)], C.c_int),
     "qs_alloc": ([C.c_int, C.c_int, P, P, SZ, P, C.POINTER(P)], C.c_int),
     "qs_free": ([P], C.c_int),
     "qs_state_buffers": ([P, C.POINTER(P), C.POINTER(P)], C.c_int),

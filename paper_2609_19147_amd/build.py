@@ -25,6 +25,7 @@ SOURCES = ["planner.cpp", "api.cpp", "runtime.cpp", "adjoint.cpp", "batch.cpp",
 
 ARCH = os.environ.get("QS_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are kept out of every kernel.
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
@@ -64,7 +65,9 @@ def build(verbose: bool = False, extra=()) -> str:
         objs = list(ex.map(lambda s: _compile(s, list(extra)), SOURCES))
         probe.result()
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    # rocTX for the profiler ranges (rocprofiler-sdk's marker library)
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           f"-L{ROCM}/lib", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM}/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")

@@ -36,11 +36,7 @@ qs_state& work_state(qs_state& psi, int k) {
     s->dtype = psi.dtype;
     s->device = psi.device;
     s->stream = psi.stream;
-    const size_t bytes = s->state_bytes();
-    size_t fr = 0, tot = 0;
-    check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
-    if (bytes > fr) fail(QS_ENOMEM, "no device memory for the adjoint states");
-    if (hipMalloc(&s->buf[0], bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of an adjoint state failed");
+    s->buf[0] = alloc_amplitudes(s->state_bytes(), "adjoint work state");
     s->owned[0] = true;
     w = std::move(s);
   }
@@ -83,6 +79,7 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
   }
   std::stable_sort(ts.begin(), ts.end(), [](const T3& a, const T3& b) { return a.x < b.x; });
 
+  const Range range("qs.adjoint");
   // forward
   apply_layers(psi, p, 0, L, false);
   qs_state& phi = work_state(psi, 0);

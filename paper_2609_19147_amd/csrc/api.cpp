@@ -19,6 +19,11 @@
 #include "qs.h"
 #include "runtime.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
+#include <atomic>
+#include <cstdlib>
+
 using namespace qs;
 
 namespace qs {
@@ -115,19 +120,84 @@ static qs_status guarded(F&& f) {
 extern "C" const char* qs_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char* qs_version(void) { return "qs 0.1 (gfx950, wave64)"; }
 
+extern "C" qs_status qs_memory_info(size_t* held, size_t* cap) {
+  return guarded([&] {
+    if (held) *held = qs::amplitude_bytes_held();
+    if (cap) *cap = qs::amplitude_cap();
+  });
+}
+
+// ---------------------------------------------------------------- profiler ranges
+namespace qs {
+Range::Range(const char* name) { roctxRangePushA(name); }
+Range::~Range() { roctxRangePop(); }
+
+namespace {
+void plan_phase_range(const char* phase, bool begin) {
+  if (begin) roctxRangePushA(phase);
+  else roctxRangePop();
+}
+// the planner's phases report to rocTX from the moment the library is loaded
+const bool g_phase_hook_set = (set_plan_phase_hook(&plan_phase_range), true);
+}  // namespace
+}  // namespace qs
+
+// ---------------------------------------------------------------- device memory
+namespace qs {
+namespace {
+std::atomic<size_t> g_amp_held{0};
+
+size_t amp_cap_read() {
+  static const size_t cap = [] {
+    const char* e = std::getenv("QS_MAX_BYTES");
+    if (!e || !*e) return (size_t)0;
+    char* end = nullptr;
+    const unsigned long long v = std::strtoull(e, &end, 10);
+    return (end && *end == '\0') ? (size_t)v : (size_t)0;
+  }();
+  return cap;
+}
+}  // namespace
+
+size_t amplitude_cap() { return amp_cap_read(); }
+
+void* alloc_amplitudes(size_t bytes, const char* what) {
+  const size_t cap = amp_cap_read();
+  if (cap) {
+    size_t held = g_amp_held.load();
+    do {
+      if (held + bytes > cap)
+        fail(QS_ENOMEM, std::string(what) + ": over the QS_MAX_BYTES cap (" + std::to_string(held) + " + " +
+                            std::to_string(bytes) + " > " + std::to_string(cap) + " bytes)");
+    } while (!g_amp_held.compare_exchange_weak(held, held + bytes));
+  } else {
+    g_amp_held += bytes;
+  }
+  size_t fr = 0, tot = 0;
+  void* p = nullptr;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess || bytes > fr || hipMalloc(&p, bytes) != hipSuccess) {
+    g_amp_held -= bytes;
+    fail(QS_ENOMEM, std::string(what) + ": not enough free device memory");
+  }
+  return p;
+}
+
+void free_amplitudes(void* p, size_t bytes) {
+  if (!p) return;
+  hipFree(p);
+  g_amp_held -= bytes;
+}
+
+size_t amplitude_bytes_held() { return g_amp_held.load(); }
+}  // namespace qs
+
 // ---------------------------------------------------------------- states
 size_t qs_state::amp_bytes() const { return dtype == QS_C64 ? 8 : 16; }
 size_t qs_state::state_bytes() const { return amp_bytes() << n; }
 
 void qs_state::ensure_other() {
   if (buf[1 - cur]) return;
-  size_t bytes = state_bytes();
-  size_t fr = 0, tot = 0;
-  check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
-  if (bytes > fr) fail(QS_ENOMEM, "not enough device memory for the permutation scratch buffer");
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of the scratch buffer failed");
-  buf[1 - cur] = p;
+  buf[1 - cur] = alloc_amplitudes(state_bytes(), "permutation scratch buffer");
   owned[1 - cur] = true;
 }
 
@@ -153,11 +223,11 @@ void* qs_state::ensure_work_buf(size_t bytes) {
   if (work_cap >= bytes) return work_buf;
   if (work_buf) {
     check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
-    check_hip(hipFree(work_buf), "hipFree");
+    free_amplitudes(work_buf, work_cap);
     work_buf = nullptr;
     work_cap = 0;
   }
-  if (hipMalloc(&work_buf, bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of the adjoint scratch failed");
+  work_buf = alloc_amplitudes(bytes, "adjoint scratch");
   work_cap = bytes;
   return work_buf;
 }
@@ -181,19 +251,13 @@ extern "C" qs_status qs_alloc(int n, qs_dtype dtype, void* buf, void* scratch, s
     s->stream = (hipStream_t)stream;
     const size_t need = s->state_bytes();
     if ((buf && bytes < need) || (scratch && bytes < need)) fail(QS_EINVAL, "given buffer smaller than 2^n amplitudes");
-    size_t alloc = (buf ? 0 : need);
-    if (alloc) {
-      size_t fr = 0, tot = 0;
-      check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
-      if (alloc > fr) fail(QS_ENOMEM, "state does not fit in free device memory");
-    }
-    check_hip(hipGetDevice(&s->device), "hipGetDevice");
     if (buf) {
       s->buf[0] = buf;
     } else {
-      if (hipMalloc(&s->buf[0], need) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of the state failed");
+      s->buf[0] = alloc_amplitudes(need, "state");  // the cap is checked before any device call
       s->owned[0] = true;
     }
+    check_hip(hipGetDevice(&s->device), "hipGetDevice");
     if (scratch) s->buf[1] = scratch;
     *out = s.release();
   });
@@ -201,13 +265,13 @@ extern "C" qs_status qs_alloc(int n, qs_dtype dtype, void* buf, void* scratch, s
 
 qs_state::~qs_state() {
   for (int k = 0; k < 2; ++k)
-    if (owned[k] && buf[k]) hipFree(buf[k]);
+    if (owned[k] && buf[k]) free_amplitudes(buf[k], state_bytes());
   if (red_partials) hipFree(red_partials);
   if (red_out) hipFree(red_out);
   if (norm_part) hipFree(norm_part);
   free_graphs(*this);
   if (matbuf) hipFree(matbuf);
-  if (work_buf) hipFree(work_buf);
+  if (work_buf) free_amplitudes(work_buf, work_cap);
 }
 
 extern "C" qs_status qs_free(qs_state* s) {
@@ -306,6 +370,7 @@ extern "C" qs_status qs_sync(qs_state* s) {
 extern "C" qs_status qs_plan_create(int n, const qs_gate* gates, size_t n_gates, size_t n_params,
                                     const qs_plan_opts* opts, qs_plan** out) {
   return guarded([&] {
+    const Range range("qs.plan_create");
     if (!out) fail(QS_EINVAL, "out is NULL");
     PlanOptions o;
     int low = 0;

@@ -28,6 +28,7 @@ struct qs_batch {
   std::vector<int> nq;
   std::vector<qs_plan*> plans;
   void* arena = nullptr;
+  size_t arena_bytes = 0;
   std::vector<size_t> offset;  // amplitude offset of each instance
   std::vector<std::unique_ptr<qs_state>> views;
   struct Group {
@@ -65,7 +66,7 @@ qs_batch::~qs_batch() {
   }
   if (desc) hipFree(desc);
   if (red) hipFree(red);
-  if (arena) hipFree(arena);
+  if (arena) free_amplitudes(arena, arena_bytes);
   if (obs_dev) hipFree(obs_dev);
   if (own_stream && stream) hipStreamDestroy(stream);
 }
@@ -229,10 +230,8 @@ extern "C" qs_status qs_batch_create(size_t n_inst, const int* n_qubits, const q
         total += 1ull << G.n;
       }
     const size_t bytes = total * B->amp_bytes();
-    size_t fr = 0, tot = 0;
-    check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
-    if (bytes > fr) fail(QS_ENOMEM, "batch states do not fit in free device memory");
-    if (hipMalloc(&B->arena, bytes) != hipSuccess) fail(QS_ENOMEM, "hipMalloc of the batch arena failed");
+    B->arena = alloc_amplitudes(bytes, "batch states");
+    B->arena_bytes = bytes;
     if (stream) {
       B->stream = (hipStream_t)stream;
     } else {
@@ -283,6 +282,7 @@ extern "C" qs_status qs_batch_refresh(qs_batch* b) {
   try {
     if (!b) fail(QS_EINVAL, "batch is NULL");
     if (b->plan_freed) fail(QS_EINVAL, "a plan of the batch has been freed");
+    const Range range("qs.batch.record");
     for (auto* p : b->plans)
       if (!p->bound) fail(QS_EINVAL, "plan parameters are not bound");
     check_hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");

@@ -16,6 +16,23 @@
 
 namespace qs {
 
+namespace {
+PlanPhaseHook g_phase_hook = nullptr;
+
+struct Phase {
+  const char* name;
+  explicit Phase(const char* n) : name(n) {
+    if (g_phase_hook) g_phase_hook(name, true);
+  }
+  ~Phase() {
+    if (g_phase_hook) g_phase_hook(name, false);
+  }
+};
+}  // namespace
+
+void set_plan_phase_hook(PlanPhaseHook hook) { g_phase_hook = hook; }
+
+
 void fail(qs_status code, const std::string& msg) { throw Error{code, msg}; }
 
 static const double kPi = 3.14159265358979323846;
@@ -95,6 +112,7 @@ int gate_arity(const qs_gate& g) {
 }
 
 std::vector<NGate> normalise_gates(int n, const qs_gate* g, size_t count, size_t n_params) {
+  const Phase ph("qs.plan.normalise");
   if (n < 1 || n > QS_MAX_QUBITS) fail(QS_EINVAL, "qubit count out of range");
   if (count > 0 && !g) fail(QS_EINVAL, "gate array is NULL");
   std::vector<NGate> out;
@@ -1602,9 +1620,16 @@ static PlanIR structured_plan(int n, std::vector<NGate> gates, size_t n_params, 
   P.tile_bits = tile_bits;
   P.low_bits = low_bits;
   P.windows = windows;
-  Builder B(P, tile_bits, low_bits);
-  B.run();
-  if (opt.balance_passes >= 0) rebalance_diag_passes(P);
+  {
+    const Phase ph("qs.plan.schedule");
+    Builder B(P, tile_bits, low_bits);
+    B.run();
+  }
+  if (opt.balance_passes >= 0) {
+    const Phase ph("qs.plan.balance");
+    rebalance_diag_passes(P);
+  }
+  const Phase ph("qs.plan.rounds");
   for (auto& T : P.passes) finalize_pass(P, T);
   return P;
 }
@@ -1622,6 +1647,7 @@ PlanIR build_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOp
     for (size_t i = 0; i < P.gates.size(); ++i) P.layers.push_back({L_PLAIN, (int32_t)i});
     return P;
   }
+  const Phase ph("qs.plan.build");
   PlanIR best = structured_plan(n, gates, n_params, opt, tile_bits, low_bits, 0);
   // Generic matrix fusion of decomposed blocks (Section "Limitations and
   // Future Work"): candidates with dense windows over the whole stream and
@@ -1631,6 +1657,7 @@ PlanIR build_plan(int n, std::vector<NGate> gates, size_t n_params, const PlanOp
   const int kw = std::min(std::min(opt.window_k, opt.dense_k_max), std::min(n - 4, QS_MAX_GATE_WIRES));
   if (kw < 4) return best;
   double best_cost = plan_cost(best);
+  const Phase phw("qs.plan.windows");
   std::vector<NGate> fused;
   const int formed = fuse_windows(n, gates, kw, fused);
   if (formed == 0) return best;

@@ -166,6 +166,11 @@ double plan_cost(const PlanIR& P);
 // 4 bits.  Returns the number of windows formed.
 int fuse_windows(int n, const std::vector<NGate>& in, int kmax, std::vector<NGate>& out);
 
+// Optional observer of the planner's phases (the library installs one that
+// opens and closes profiler ranges; none by default).
+using PlanPhaseHook = void (*)(const char* phase, bool begin);
+void set_plan_phase_hook(PlanPhaseHook hook);
+
 // Validate + normalise the user's gates.
 std::vector<NGate> normalise_gates(int n, const qs_gate* g, size_t count, size_t n_params);
 // Build the plan.  tile_bits / low_bits fix the tile geometry.

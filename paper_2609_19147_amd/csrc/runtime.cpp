@@ -287,6 +287,7 @@ const PlanDev& qs_plan::device_for(qs_dtype dt) {
     for (auto& g : ir.gf2s) gf2.push_back(gf2_args(ir.n, g, kGf2MaxC));
   }
   if (d.valid) return d;
+  const Range range("qs.plan.tables");
   Blob b;
   if (dt == QS_C64) build_blob<float>(*this, d, b);
   else build_blob<double>(*this, d, b);
@@ -393,6 +394,7 @@ void qs_plan::remove_external_user(qs_dtype dt, hipEvent_t done) {
 }
 
 void qs_plan::refresh_device() {
+  const Range range("qs.plan.update");
   for (int k = 0; k < 2; ++k) {
     PlanDev& d = dev[k];
     if (!d.blob) continue;
@@ -603,6 +605,7 @@ double distance_t(qs_state& a, qs_state& b, double ar, double ai, double bs) {
 }  // namespace
 
 void apply_layers(qs_state& s, qs_plan& p, size_t first, size_t last, bool track) {
+  const Range range("qs.apply");
   s.plain_acc = NormAcc{};  // plain layers' rounding compensation restarts with every call
   if (track) {
     // nothing is recorded into a stream that is being captured

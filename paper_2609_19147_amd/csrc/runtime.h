@@ -80,6 +80,26 @@ struct PlanDev {
 void check_hip(hipError_t e, const char* what);
 extern thread_local std::string g_last_error;
 
+// A profiler range (rocTX) over a scope: planner phases, table builds and
+// updates, applies, batch recording and adjoint sweeps appear under these
+// names in rocprofv3 --marker-trace.
+struct Range {
+  explicit Range(const char* name);
+  ~Range();
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
+// Amplitude buffers the library allocates (states, their scratch halves,
+// adjoint work states and scratch, batch arenas) count against the cap
+// QS_MAX_BYTES (environment variable, bytes, read once; unset or 0: none).
+// The allocation also fails with QS_ENOMEM when the device's free memory is
+// short.  free_amplitudes takes the size that was allocated.
+void* alloc_amplitudes(size_t bytes, const char* what);
+void free_amplitudes(void* p, size_t bytes);
+size_t amplitude_bytes_held();
+size_t amplitude_cap();
+
 }  // namespace qs
 
 namespace qs {

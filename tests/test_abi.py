@@ -54,3 +54,29 @@ def test_extension_missing_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_max_bytes_cap_refuses_before_any_device_call():
+    # a fresh process with QS_MAX_BYTES set: a state above the cap fails with
+    # QS_ENOMEM and names the cap, with no device present
+    import subprocess
+    import sys
+    code = (
+        "import ctypes\n"
+        "from paper_2609_19147_amd import _lib\n"
+        "lib = _lib.lib()\n"
+        "h = ctypes.c_void_p()\n"
+        "rc = lib.qs_alloc(20, _lib.QS_C64, None, None, 0, None, ctypes.byref(h))\n"
+        "held, cap = ctypes.c_size_t(), ctypes.c_size_t()\n"
+        "assert lib.qs_memory_info(ctypes.byref(held), ctypes.byref(cap)) == 0\n"
+        "print(rc, cap.value, held.value, lib.qs_last_error().decode())\n"
+    )
+    env = dict(os.environ, QS_MAX_BYTES="4096")
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    rc, cap, held, msg = out.stdout.strip().split(" ", 3)
+    from paper_2609_19147_amd import _lib
+    assert int(rc) == _lib.QS_ENOMEM
+    assert int(cap) == 4096 and int(held) == 0
+    assert "QS_MAX_BYTES" in msg
