@@ -738,6 +738,30 @@ def profile_run(qs, torch, name):
 
         def run():
             B.run()
+    elif name == "adjoint":
+        # the C5 gradient with the tuner's tile limit (cached by a preceding
+        # bench.py --only adjoint run in the same environment)
+        from paper_2609_19147_amd.tune import TileTuner
+        n, layers = 24, 8
+        stream = W.hea_stream(n, layers)
+        params = W.hea_params(n, layers, 24)
+        terms = W.xxz_terms(n, 0.5)
+        st = qs.State(n, "c64")
+        plans = {}
+
+        def make(tb):
+            if tb not in plans:
+                plans[tb] = qs.Plan(n, stream, n_params=len(params), params=params, max_tile_bits=tb)
+            return plans[tb]
+
+        def tune_run(tb):
+            st.set_basis(0)
+            qs.adjoint_grad(st, make(tb), terms)
+        plan = make(TileTuner().best(f"adjoint-hea{layers}-xxz", n, "c64", tune_run, (11, 12, 13)))
+
+        def run():
+            st.set_basis(0)
+            qs.adjoint_grad(st, plan, terms)
     else:
         raise SystemExit(f"no profile run for {name}")
     run()
@@ -774,7 +798,7 @@ def main():
                     help="also run one plain device copy of the state (2 S bytes) as a counter calibration")
     ap.add_argument("--only", choices=sorted(SECTIONS),
                     help="run one extra section alone and print its JSON (a profiling aid; not the benchmark line)")
-    ap.add_argument("--profile-run", choices=["tfim25", "batched_qaoa"],
+    ap.add_argument("--profile-run", choices=["tfim25", "batched_qaoa", "adjoint"],
                     help="one warm application of a section's fused path, for counter runs (not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -306,12 +306,14 @@ struct RoundLoop {
     uint32_t loff[RN];
 #pragma unroll
     for (int j = 0; j < RN; ++j) loff[j] = R_->loff[j];
+    auto place = [&](uint32_t g) {
+      g = insert0(g, t0);
+      g = insert0(g, t1);
+      g = insert0(g, t2);
+      return insert0(g, t3);
+    };
     for (uint32_t g = threadIdx.x; g < ngroups; g += nthr) {
-      uint32_t gpos = g;
-      gpos = insert0(gpos, t0);
-      gpos = insert0(gpos, t1);
-      gpos = insert0(gpos, t2);
-      gpos = insert0(gpos, t3);
+      const uint32_t gpos = place(g);
       cplx<R>* Tg = T + lds_off(gpos);
       cplx<R> a[RN];
 #pragma unroll
@@ -438,9 +440,10 @@ __device__ __forceinline__ void tile_load(const TileKArgs<R>& A, const Ctx& C, c
 }
 
 template <class R, bool kDiag>
-__device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C, cplx<R>* T) {
+__device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C, cplx<R>* T, uint32_t nthr) {
+  // threads [0, nthr) take the register groups; every thread of the workgroup
+  // takes part in the barrier after each round
   const uint32_t M = 1u << A.m;
-  const uint32_t nthr = blockDim.x;
   // the pattern is uniform per round, so the dispatch sits
   // outside the per-thread group loop and every pattern runs its own loop
   // (registers loaded, transformed and stored with no value crossing a join)
@@ -574,8 +577,9 @@ __device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C,
 // Stores the tile; returns this thread's FP64 sum of |psi|^2 over what it
 // stored when the pass reports its norm (0 otherwise).
 template <class R>
-__device__ __forceinline__ double tile_store(const TileKArgs<R>& A, const Ctx& C, const cplx<R>* T) {
-  const uint32_t M = 1u << A.m, stride = 2 * blockDim.x;
+__device__ __forceinline__ double tile_store(const TileKArgs<R>& A, const Ctx& C, const cplx<R>* T, uint32_t nthr) {
+  // threads [0, nthr) store the tile
+  const uint32_t M = 1u << A.m, stride = 2 * nthr;
   double nacc = 0.0;
   cplx<R>* __restrict__ psi = A.psi;
   // with the pass's butterfly normalisation
@@ -583,7 +587,6 @@ __device__ __forceinline__ double tile_store(const TileKArgs<R>& A, const Ctx& C
   const bool do_scale = A.scale != 1.0;
   if constexpr (sizeof(R) == 8) {
     // complex128: one amplitude per lane and access (as in the load)
-    const uint32_t nthr = blockDim.x;
     constexpr int K = 2 * kChunk;
     for (uint32_t p0 = threadIdx.x; p0 < M; p0 += nthr * K) {
       cplx<R> v[K];
@@ -645,8 +648,8 @@ __device__ __forceinline__ void tile_body(const TileKArgs<R>& A, const uint32_t 
   const Ctx C = coset_ctx(A, coset);
   tile_load<R>(A, C, T);
   __syncthreads();
-  tile_rounds<R, kDiag>(A, C, T);
-  const double nacc = tile_store<R>(A, C, T);
+  tile_rounds<R, kDiag>(A, C, T, blockDim.x);
+  const double nacc = tile_store<R>(A, C, T, blockDim.x);
   if (A.norm_part != nullptr) {
     const double t = block_sum_fixed(nacc);
     if (threadIdx.x == 0) A.norm_part[coset] = t;
@@ -742,11 +745,84 @@ __global__ void __launch_bounds__(kMaxThreads) tile_kernel_pipe(TileKArgs<R> A, 
     }
     __syncthreads();
     if (c + G < n_cosets) pipe_issue<R, 0, P>(A, coset_ctx(A, c + G), v);
-    tile_rounds<R, false>(A, C, T);
-    const double nacc = tile_store<R>(A, C, T);
+    tile_rounds<R, false>(A, C, T, blockDim.x);
+    const double nacc = tile_store<R>(A, C, T, blockDim.x);
     if (A.norm_part != nullptr) {
       const double t = block_sum_fixed(nacc);
       if (threadIdx.x == 0) A.norm_part[c] = t;
+    }
+  }
+}
+
+// ---- warp-specialised persistent passes ---------------------------------------
+// For complex128 tiles that fill a CU's LDS (2^13 amplitudes) and whose pass
+// reports no norm: one persistent workgroup per CU of kWsConsumers threads
+// that run the rounds and store each tile, and kWsProducers threads that
+// hold the next coset's tile in registers (kWsK 16-byte loads each, issued
+// as soon as the current tile is in LDS) and write it into LDS once the
+// consumers have stored theirs.  HBM reads overlap the rounds and the
+// stores; the LDS hand-over is the only serial step.  Producer and consumer
+// code are separate loops (disjoint register live ranges) with the same
+// sequence of workgroup barriers: per coset, one per round, one after the
+// store and, when a next coset exists, one after its tile is written.
+constexpr uint32_t kWsConsumers = 256, kWsProducers = 256;
+constexpr int kWsK = 32;  // 16-byte accesses per producer thread and tile
+
+template <class R>
+__device__ __forceinline__ void ws_issue(const TileKArgs<R>& A, const Ctx& C, uint32_t pt,
+                                         typename PipeAccess<R>::T* v) {
+  using E = typename PipeAccess<R>::T;
+  constexpr uint32_t apa = PipeAccess<R>::amps;
+#pragma unroll
+  for (int k = 0; k < kWsK; ++k) {
+    const uint32_t pos = apa * (pt + kWsProducers * k);
+    v[k] = ld_nt(reinterpret_cast<const E*>(A.psi + (C.base | C.dep(pos))));
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void ws_to_lds(const typename PipeAccess<R>::T* v, uint32_t pt, cplx<R>* T) {
+  using E = typename PipeAccess<R>::T;
+  constexpr uint32_t apa = PipeAccess<R>::amps;
+#pragma unroll
+  for (int k = 0; k < kWsK; ++k) *reinterpret_cast<E*>(T + lds_off(apa * (pt + kWsProducers * k))) = v[k];
+}
+
+// Requires 2^m = kWsProducers * kWsK * PipeAccess<R>::amps and norm_part == null
+// (checked on the host).
+template <class R>
+__global__ void __launch_bounds__(kWsConsumers + kWsProducers) tile_kernel_ws(TileKArgs<R> A, uint32_t n_cosets) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<R>* T = reinterpret_cast<cplx<R>*>(smem_raw);
+  const uint32_t G = gridDim.x;
+  const uint32_t c0 = A.order ? blockIdx.x : xcd_block(blockIdx.x, G);
+  if (c0 >= n_cosets) return;  // the whole workgroup leaves together
+  const uint32_t R_ = A.n_rounds;
+  if (threadIdx.x >= kWsConsumers) {
+    const uint32_t pt = threadIdx.x - kWsConsumers;
+    typename PipeAccess<R>::T v[kWsK];
+    ws_issue<R>(A, coset_ctx(A, c0), pt, v);
+    ws_to_lds<R>(v, pt, T);
+    __syncthreads();  // first tile in LDS
+    for (uint32_t c = c0; c < n_cosets; c += G) {
+      const bool next = c + G < n_cosets;
+      if (next) ws_issue<R>(A, coset_ctx(A, c + G), pt, v);
+      for (uint32_t r = 0; r < R_; ++r) __syncthreads();  // the consumers' rounds
+      __syncthreads();  // the consumers have stored the tile
+      if (next) {
+        ws_to_lds<R>(v, pt, T);
+        __syncthreads();  // next tile in LDS
+      }
+    }
+  } else {
+    __syncthreads();  // first tile in LDS
+    for (uint32_t c = c0; c < n_cosets; c += G) {
+      const bool next = c + G < n_cosets;
+      const Ctx C = coset_ctx(A, c);
+      tile_rounds<R, false>(A, C, T, kWsConsumers);
+      tile_store<R>(A, C, T, kWsConsumers);
+      __syncthreads();  // tile read out of LDS
+      if (next) __syncthreads();  // next tile in LDS
     }
   }
 }
@@ -774,11 +850,11 @@ tile_kernel_dual(TileKArgs<R> A, cplx<R>* lam, RhoTileArgs Q,
   tile_load<R>(A, C, T0);
   tile_load<R>(B, C, T1);
   __syncthreads();
-  tile_rounds<R, kDiag>(A, C, T0);
-  tile_rounds<R, kDiag>(A, C, T1);
+  tile_rounds<R, kDiag>(A, C, T0, blockDim.x);
+  tile_rounds<R, kDiag>(A, C, T1, blockDim.x);
   if (Q.nbits) rho::accumulate_tile<R>(T0, T1, M, Q, red, partials, coset, ntiles);
-  tile_store<R>(A, C, T0);
-  tile_store<R>(B, C, T1);
+  tile_store<R>(A, C, T0, blockDim.x);
+  tile_store<R>(B, C, T1, blockDim.x);
 }
 
 // A batched instance's argument block, read field by field with scalar loads.
@@ -903,8 +979,27 @@ bool pipe_eligible(const TileKArgs<R>& A) {
          (1u << A.m) == tile_threads(A.m) * kPipeK * PipeAccess<R>::amps;
 }
 
+// complex128 tiles that fill the LDS (measured: for complex64 the pipelined
+// kernel is the faster one)
+template <class R>
+bool ws_eligible(const TileKArgs<R>& A) {
+  return sizeof(R) == 8 && pipe_eligible(A) && A.norm_part == nullptr &&
+         (1u << A.m) == kWsProducers * kWsK * PipeAccess<R>::amps;
+}
+
 template <class R>
 void launch_tile(const TileKArgs<R>& A, hipStream_t s) {
+  if (ws_eligible(A)) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      allow_dynamic_lds((const void*)tile_kernel_ws<R>, kTileDynLds, "tile_pass");
+      attr_set = true;
+    }
+    const uint32_t n_cosets = 1u << (A.n - A.m);
+    QS_LAUNCH("tile_pass", s, tile_kernel_ws<R>, dim3(pipe_grid(n_cosets)), dim3(kWsConsumers + kWsProducers),
+              tile_lds(A.m, sizeof(cplx<R>)), s, A, n_cosets);
+    return;
+  }
   if (pipe_eligible(A)) {
     static bool attr_set = false;
     if (!attr_set) {
