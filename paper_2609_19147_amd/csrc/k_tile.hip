@@ -77,27 +77,48 @@ __device__ __forceinline__ void op_h(cplx<R>* a) {
   }
 }
 
-// Unscaled QFT stage on register bit S: a1' = (a0 - a1) * w * E[k], with w the
-// group twiddle (bits outside the round) and E[k] the intra-round factor of
-// the register bits below S.  The inverse stage undoes it: a1 <- a1 conj(w E[k]),
-// then the butterfly.
-template <int S, class R, bool kInv>
+// Unscaled QFT stage on register bit S: a1' = (a0 - a1) t_k with t_k = w E[k],
+// w the group twiddle (bits outside the round) and E[k] the intra-round
+// factor of the register bits below S.  The inverse stage undoes it:
+// a1 <- a1 conj(t_k), then the butterfly.
+// kThenH: the Hadamard of bit S follows at once (no later stage of a round
+// acts on bit S or is controlled by it): with u = a0 + a1 and
+// v = t_k (a0 - a1), a0' = u + v and a1' = 2u - a0' (five multiply-adds and
+// four adds per pair instead of twelve operations).
+// kSym: E[k + 2^(S-1)] = i E[k], so the upper half of the t_k is the lower
+// half times i (register moves and sign flips, no multiplies).
+template <int S, class R, bool kInv, bool kThenH = false, bool kSym = false>
 __device__ __forceinline__ void op_qft(cplx<R>* a, cplx<R> w, cptr<cplx<R>> E) {
+  static_assert(!(kInv && kThenH), "the inverse stage has no fused Hadamard");
+  constexpr int K = 1 << S;
+  cplx<R> tw[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (kSym && k >= K / 2 && K >= 2)
+      tw[k] = {-tw[k - K / 2].im, tw[k - K / 2].re};
+    else
+      tw[k] = k == 0 ? w : cmul(w, ldc(E, k));
+  }
   // pairs (j, j | 2^S) with j = k + hi * 2^(S+1): the twiddle depends on k only
 #pragma unroll
-  for (int k = 0; k < (1 << S); ++k) {
-    const cplx<R> tw = k == 0 ? w : cmul(w, ldc(E, k));
+  for (int k = 0; k < K; ++k) {
+    const cplx<R> t = tw[k];
 #pragma unroll
     for (int hi = 0; hi < (RN >> (S + 1)); ++hi) {
       const int j = k + (hi << (S + 1));
       const cplx<R> x = a[j], y = a[j | (1 << S)];
-      if (!kInv) {
-        a[j] = cadd(x, y);
-        a[j | (1 << S)] = cmul(csub(x, y), tw);
-      } else {
-        const cplx<R> yt = cmulc(y, tw);
+      if constexpr (kInv) {
+        const cplx<R> yt = cmulc(y, t);
         a[j] = cadd(x, yt);
         a[j | (1 << S)] = csub(x, yt);
+      } else if constexpr (kThenH) {
+        const cplx<R> u = cadd(x, y), d = csub(x, y);
+        const cplx<R> s0 = {fma(t.re, d.re, fma(-t.im, d.im, u.re)), fma(t.re, d.im, fma(t.im, d.re, u.im))};
+        a[j] = s0;
+        a[j | (1 << S)] = {fma(R(2), u.re, -s0.re), fma(R(2), u.im, -s0.im)};
+      } else {
+        a[j] = cadd(x, y);
+        a[j | (1 << S)] = cmul(csub(x, y), t);
       }
     }
   }
@@ -119,16 +140,17 @@ __device__ __forceinline__ cplx<R> qft_w(cptr<TileOp> op, uint32_t gglobal, cplx
   return cispi<R>(stage_low(gglobal, p, op->base), p);
 }
 
-template <class R>
+// The four stages of a QFT round; kThenH: each followed by its Hadamard.
+template <class R, bool kThenH, bool kSym>
 __device__ __forceinline__ void round_qft4(cplx<R>* a, cptr<TileOp> ops, cptr<cplx<R>> coef, uint32_t gglobal) {
   cplx<R> w = qft_w<R>(ops + 0, gglobal, cplx<R>{R(1), R(0)});
-  op_qft<3, R, false>(a, w, coef + ops[0].coef);
+  op_qft<3, R, false, kThenH, kSym>(a, w, coef + ops[0].coef);
   w = qft_w<R>(ops + 1, gglobal, w);
-  op_qft<2, R, false>(a, w, coef + ops[1].coef);
+  op_qft<2, R, false, kThenH, kSym>(a, w, coef + ops[1].coef);
   w = qft_w<R>(ops + 2, gglobal, w);
-  op_qft<1, R, false>(a, w, coef + ops[2].coef);
+  op_qft<1, R, false, kThenH, kSym>(a, w, coef + ops[2].coef);
   w = qft_w<R>(ops + 3, gglobal, w);
-  op_qft<0, R, false>(a, w, coef + ops[3].coef);
+  op_qft<0, R, false, kThenH, kSym>(a, w, coef + ops[3].coef);
 }
 
 template <class R>
@@ -194,13 +216,12 @@ __device__ __forceinline__ void op_ryf(cplx<R>* a, R t) {
 
 // ---- round patterns as functors: f(a, g) transforms the 16 registers of the
 // group whose smallest index is g (index bits outside the round).
-template <class R, bool kThenH4>
+template <class R, bool kThenH4, bool kSym>
 struct FQft4 {
   cptr<TileOp> ops;
   cptr<cplx<R>> coef;
   __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const {
-    round_qft4<R>(a, ops, coef, g);
-    if (kThenH4) round_h4<R>(a);
+    round_qft4<R, kThenH4, kSym>(a, ops, coef, g);
   }
 };
 template <class R>
@@ -274,8 +295,7 @@ struct FQft1 {
   int p, base;
   __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t g) const {
     const cplx<R> w = cispi<R>(stage_low(g, p, base), p);
-    op_qft<S, R, kInv>(a, w, E);
-    if (kThenH) op_h<S>(a);
+    op_qft<S, R, kInv, kThenH>(a, w, E);
   }
 };
 
@@ -497,10 +517,16 @@ __device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C,
         }
         break;
       case RT_QFT4:
-        L(FQft4<R, false>{ops + R_->op_begin, coef});
+        L(FQft4<R, false, false>{ops + R_->op_begin, coef});
         break;
       case RT_QFT4_H4:
-        L(FQft4<R, true>{ops + R_->op_begin, coef});
+        L(FQft4<R, true, false>{ops + R_->op_begin, coef});
+        break;
+      case RT_QFT4S:
+        L(FQft4<R, false, true>{ops + R_->op_begin, coef});
+        break;
+      case RT_QFT4S_H4:
+        L(FQft4<R, true, true>{ops + R_->op_begin, coef});
         break;
       case RT_H4:
         L(FH4<R>{});

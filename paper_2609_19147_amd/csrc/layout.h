@@ -78,6 +78,12 @@ enum TileRoundType : int32_t {
   RT_MAT4_RXF = 13,
   RT_MAT4_RYF = 14,
   RT_DIAG_PAIR_RXF = 15,
+  // device only: RT_QFT4 / RT_QFT4_H4 whose stages' intra-round factors
+  // satisfy E[k + 2^(r-1)] = i E[k] on register bit r >= 1 (the stages of
+  // consecutive qubits with no dropped angle): the kernel multiplies out the
+  // lower half of each stage's twiddles only
+  RT_QFT4S = 16,
+  RT_QFT4S_H4 = 17,
 };
 // The planner splits a round matching none of the patterns into a sequence of
 // rounds over the same register bits (RT_MAT4 groups and RT_QFT1 stages).

@@ -230,6 +230,19 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
         e = cd(tr, 0.0);
       }
     }
+    // QFT rounds over consecutive qubits: the upper half of each stage's
+    // intra-round factors is i times the lower half (RT_QFT4S, RT_QFT4S_H4)
+    for (TileRound& r : rounds) {
+      if (r.type != RT_QFT4 && r.type != RT_QFT4_H4) continue;
+      bool sym = true;
+      for (int st = r.op_begin; st < r.op_end && sym; ++st) {
+        const TileOp& op = T.ops[st];
+        const int h = (1 << op.rbit) / 2;
+        for (int k = 0; k < h && sym; ++k)
+          sym = std::abs(coef[op.coef + k] * cd(0.0, 1.0) - coef[op.coef + k + h]) <= 1e-14;
+      }
+      if (sym) r.type = r.type == RT_QFT4 ? RT_QFT4S : RT_QFT4S_H4;
+    }
     if (!qtab.empty()) d.pass_qtab[i] = b.put(qtab);
     d.pass_rounds[i] = b.put(rounds);
     d.pass_ops[i] = b.put(T.ops);
