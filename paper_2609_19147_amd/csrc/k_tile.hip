@@ -214,6 +214,27 @@ __device__ __forceinline__ void op_ryf(cplx<R>* a, R t) {
   }
 }
 
+// A general single-qubit round as D2 T D1 (RT_ZYZ4 and its two reduced forms).
+template <class R, bool kD1, bool kD2>
+struct FZyz4 {
+  cptr<cplx<R>> c;  // D1[16] if kD1, then D2[16] if kD2, then t[4] as (t, 0)
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint32_t) const {
+    constexpr int o2 = kD1 ? 16 : 0, ot = o2 + (kD2 ? 16 : 0);
+    if constexpr (kD1) {
+#pragma unroll
+      for (int j = 0; j < RN; ++j) a[j] = cmul(a[j], ldc(c, j));
+    }
+    op_ryf<0>(a, c[ot + 0].re);
+    op_ryf<1>(a, c[ot + 1].re);
+    op_ryf<2>(a, c[ot + 2].re);
+    op_ryf<3>(a, c[ot + 3].re);
+    if constexpr (kD2) {
+#pragma unroll
+      for (int j = 0; j < RN; ++j) a[j] = cmul(a[j], ldc(c, o2 + j));
+    }
+  }
+};
+
 // ---- round patterns as functors: f(a, g) transforms the 16 registers of the
 // group whose smallest index is g (index bits outside the round).
 template <class R, bool kThenH4, bool kSym>
@@ -539,6 +560,15 @@ __device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C,
         break;
       case RT_MAT4_RY:
         L(FRy4<R>{coef + R_->coef4});
+        break;
+      case RT_ZYZ4:
+        L(FZyz4<R, true, true>{coef + R_->coef4});
+        break;
+      case RT_YZ4:
+        L(FZyz4<R, false, true>{coef + R_->coef4});
+        break;
+      case RT_ZY4:
+        L(FZyz4<R, true, false>{coef + R_->coef4});
         break;
       case RT_MAT4_RXF:
         L(FRx4F<R>{coef + R_->coef4});

@@ -84,6 +84,16 @@ enum TileRoundType : int32_t {
   // lower half of each stage's twiddles only
   RT_QFT4S = 16,
   RT_QFT4S_H4 = 17,
+  // device only: an RT_MAT4 round whose four matrices are unitary up to a
+  // positive factor, each factored as D2 [[1, -t], [t, 1]] D1 with diagonal
+  // D1, D2 and |t| <= 8: the kernel multiplies the 16 registers by the
+  // product table D1[j] (16 entries), applies the four real factored
+  // rotations (t_r = coef[coef4 + o + r].re, o = 16 per table present), then
+  // multiplies by D2[j]; the pass scale carries the factors.  RT_YZ4 has no
+  // D1 (all ones), RT_ZY4 no D2.
+  RT_ZYZ4 = 18,
+  RT_YZ4 = 19,
+  RT_ZY4 = 20,
 };
 // The planner splits a round matching none of the patterns into a sequence of
 // rounds over the same register bits (RT_MAT4 groups and RT_QFT1 stages).

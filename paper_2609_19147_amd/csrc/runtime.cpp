@@ -77,6 +77,55 @@ void round_pair_table(const DiagNumeric& num, const std::vector<PairNeighbours>&
   }
 }
 
+// A 2x2 matrix M = lambda V (V unitary, lambda > 0) as lambda c D2 T(t) D1
+// with T(t) = [[1, -t], [t, 1]], D1 = diag(1, p1) and D2 = diag(q0, q1) unit
+// phases, c = |V11| and t real: V11 = c q1 p1, V10 = c t q1, V00 = c q0 and
+// V01 = -c t q0 p1.  p1 = 1 when V10 / V11 is real (t keeps its sign), else
+// the phase that makes t = |V10 / V11|.  A D1 that is not all ones takes
+// D2's common phase q0 (then D2 = diag(1, q1 / q0)), so that rounds of one
+// kind of rotation pair (RZ after RY, or RY after RZ) need one table only.
+// False when M is not a scaled unitary or |t| > 8 (the bound of the
+// factored rotations).
+struct ZyzFactor {
+  cd p0 = 1.0, p1 = 1.0, q0 = 1.0, q1 = 1.0;
+  double t = 0.0, scale = 1.0;
+};
+static bool zyz_factor(const cd* M, ZyzFactor& f) {
+  const double lam = std::sqrt(std::abs(M[0] * M[3] - M[1] * M[2]));
+  if (!(lam > 0.0)) return false;
+  const cd V[4] = {M[0] / lam, M[1] / lam, M[2] / lam, M[3] / lam};
+  // unitarity: unit columns, orthogonal
+  if (std::fabs(std::norm(V[0]) + std::norm(V[2]) - 1.0) > 1e-10 ||
+      std::fabs(std::norm(V[1]) + std::norm(V[3]) - 1.0) > 1e-10 ||
+      std::abs(std::conj(V[0]) * V[1] + std::conj(V[2]) * V[3]) > 1e-10)
+    return false;
+  const double c = std::abs(V[3]);
+  if (!(c > 0.0)) return false;
+  const cd r = V[2] / V[3];
+  if (std::abs(r) > 8.0) return false;
+  if (std::fabs(r.imag()) <= 1e-15 * std::abs(r)) {
+    f.p1 = 1.0;
+    f.t = r.real();
+  } else {
+    f.p1 = std::abs(r) / r;
+    f.t = std::abs(r);
+  }
+  f.q1 = V[3] / (c * f.p1);
+  f.q0 = V[0] / c;
+  f.q0 /= std::abs(f.q0);
+  f.q1 /= std::abs(f.q1);
+  f.p1 /= std::abs(f.p1);
+  if (std::abs(-c * f.t * f.q0 * f.p1 - V[1]) > 1e-10) return false;
+  if (std::abs(f.p1 - 1.0) > 1e-15) {
+    f.p0 = f.q0;
+    f.p1 *= f.q0;
+    f.q1 /= f.q0;
+    f.q0 = 1.0;
+  }
+  f.scale = lam * c;
+  return true;
+}
+
 // The rotations and 2x2 unitaries a tile pass applies, rounded to float in
 // round order with the plan's running norm compensation (fround.h); the
 // entries were first rounded one by one (phases to unit modulus).
@@ -97,7 +146,8 @@ void round_pass_unitaries(const TilePassIR& T, const std::vector<TileRound>& rou
         const cplx<float> f = fround_pair(coef[r.coef4 + bb], acc);
         cr[r.coef4 + bb] = {(R)f.re, (R)f.im};
       }
-    } else if (r.type == RT_MAT4_RXF || r.type == RT_MAT4_RYF || r.type == RT_DIAG_PAIR_RXF) {
+    } else if (r.type == RT_MAT4_RXF || r.type == RT_MAT4_RYF || r.type == RT_DIAG_PAIR_RXF ||
+               r.type == RT_ZYZ4 || r.type == RT_YZ4 || r.type == RT_ZY4) {
       continue;  // factored rotations: their norm is in the pass scale
     } else {
       for (int k = r.op_begin; k < r.op_end; ++k) {
@@ -229,6 +279,42 @@ void build_blob(const qs_plan& p, PlanDev& d, Blob& b) {
         pscale *= e.real() * std::sqrt((1.0 + t * t) / (1.0 + tr * tr));
         e = cd(tr, 0.0);
       }
+    }
+    // General single-qubit rounds (RT_MAT4) whose matrices all factor as
+    // D2 T D1 (zyz_factor): two 16-entry phase tables (one when the other is
+    // all ones) and four factored real rotations, whose factors join the
+    // pass scale with the same unitarity correction as above.
+    for (TileRound& r : rounds) {
+      if (r.type != RT_MAT4) continue;
+      ZyzFactor f[4];
+      bool ok = true;
+      for (int bb = 0; bb < 4 && ok; ++bb) ok = zyz_factor(&coef[r.coef4 + 4 * bb], f[bb]);
+      if (!ok) continue;
+      bool d1 = false, d2 = false;
+      for (int bb = 0; bb < 4; ++bb) {
+        d1 = d1 || std::abs(f[bb].p0 - 1.0) > 1e-15 || std::abs(f[bb].p1 - 1.0) > 1e-15;
+        d2 = d2 || std::abs(f[bb].q0 - 1.0) > 1e-15 || std::abs(f[bb].q1 - 1.0) > 1e-15;
+      }
+      const int32_t off = (int32_t)coef.size();
+      auto table = [&](bool first) {
+        for (int j = 0; j < 16; ++j) {
+          cd v = 1.0;
+          for (int bb = 0; bb < 4; ++bb)
+            v *= first ? ((j >> bb) & 1 ? f[bb].p1 : f[bb].p0) : ((j >> bb) & 1 ? f[bb].q1 : f[bb].q0);
+          coef.push_back(v / std::abs(v));
+        }
+      };
+      if (d1) table(true);
+      if (d2 || !d1) table(false);
+      for (int bb = 0; bb < 4; ++bb) {
+        const double t = f[bb].t;
+        const double tr = sizeof(R) == sizeof(float) ? (double)(float)t : t;
+        pscale *= f[bb].scale * std::sqrt((1.0 + t * t) / (1.0 + tr * tr));
+        rot_coef.push_back((int32_t)coef.size());
+        coef.push_back(cd(tr, 0.0));
+      }
+      r.coef4 = off;
+      r.type = d1 && d2 ? RT_ZYZ4 : (d1 ? RT_ZY4 : RT_YZ4);
     }
     // QFT rounds over consecutive qubits: the upper half of each stage's
     // intra-round factors is i times the lower half (RT_QFT4S, RT_QFT4S_H4)
