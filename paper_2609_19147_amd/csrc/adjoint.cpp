@@ -86,25 +86,63 @@ void run_adjoint(qs_state& psi, qs_plan& p, const qs_pauli* terms, size_t n_term
   qs_state& lam = work_state(psi, 1);
   copy_state<R>(phi, psi);
   {
-    std::vector<uint32_t> xs, zs;
-    std::vector<double> cs;
-    for (auto& t : ts) {
-      xs.push_back(t.x);
-      zs.push_back(t.z);
-      cs.push_back(t.cr);
-      cs.push_back(t.ci);
+    // groups of one X mask; within a group each term's sign (-1)^{popcount(j & z)}
+    // is 1 - 2 count(j): constants join c0, Z and ZZ terms of equal coefficient
+    // share one count (disjoint masks), longer Z strings count their parity
+    std::vector<PauliGroup> groups;
+    std::vector<PauliCount> counts;
+    for (size_t t0 = 0; t0 < ts.size();) {
+      size_t t1 = t0;
+      while (t1 < ts.size() && ts[t1].x == ts[t0].x) ++t1;
+      PauliGroup G{};
+      G.x = ts[t0].x;
+      G.k0 = (int32_t)counts.size();
+      for (size_t t = t0; t < t1; ++t) {
+        const T3& T = ts[t];
+        G.c0re += T.cr;
+        G.c0im += T.ci;
+        if (T.z == 0) continue;
+        const int nz = __builtin_popcount(T.z);
+        int32_t form = DT_PARITY;
+        uint32_t shift = 0, mask = T.z;
+        if (nz == 1) {
+          form = DT_BITS;
+        } else if (nz == 2) {
+          const int lo = __builtin_ctz(T.z), hi = 31 - __builtin_clz(T.z);
+          form = DT_SHIFT_XOR;
+          shift = (uint32_t)(hi - lo);
+          mask = 1u << lo;
+        }
+        const double wre = -2.0 * T.cr, wim = -2.0 * T.ci;
+        bool merged = false;
+        if (form != DT_PARITY)
+          for (size_t k = (size_t)G.k0; k < counts.size() && !merged; ++k) {
+            PauliCount& K = counts[k];
+            if (K.form == form && K.shift == shift && K.wre == wre && K.wim == wim && !(K.mask & mask)) {
+              K.mask |= mask;
+              merged = true;
+            }
+          }
+        if (!merged) counts.push_back(PauliCount{form, shift, mask, 0, wre, wim});
+      }
+      G.nk = (int32_t)counts.size() - G.k0;
+      groups.push_back(G);
+      t0 = t1;
     }
-    const size_t nt = std::max<size_t>(ts.size(), 1);
-    void* dterms = psi.ensure_work_buf(nt * 16 + nt * 8);
-    uint32_t* dx = (uint32_t*)dterms;
-    uint32_t* dz = dx + nt;
-    double* dc = (double*)(dz + nt);  // byte offset 8 nt: aligned for doubles
-    if (!ts.empty()) {
-      check_hip(hipMemcpyAsync(dx, xs.data(), ts.size() * 4, hipMemcpyHostToDevice, psi.stream), "hipMemcpyAsync");
-      check_hip(hipMemcpyAsync(dz, zs.data(), ts.size() * 4, hipMemcpyHostToDevice, psi.stream), "hipMemcpyAsync");
-      check_hip(hipMemcpyAsync(dc, cs.data(), ts.size() * 16, hipMemcpyHostToDevice, psi.stream), "hipMemcpyAsync");
-    }
-    launch_pauli_apply<R>((const cplx<R>*)phi.cur_ptr(), (cplx<R>*)lam.cur_ptr(), n, dx, dz, dc, (int)ts.size(),
+    const size_t gbytes = std::max<size_t>(groups.size(), 1) * sizeof(PauliGroup);
+    const size_t kbytes = std::max<size_t>(counts.size(), 1) * sizeof(PauliCount);
+    void* dterms = psi.ensure_work_buf(gbytes + kbytes);
+    PauliGroup* dg = (PauliGroup*)dterms;
+    PauliCount* dk = (PauliCount*)((char*)dterms + gbytes);
+    if (!groups.empty())
+      check_hip(hipMemcpyAsync(dg, groups.data(), groups.size() * sizeof(PauliGroup), hipMemcpyHostToDevice,
+                               psi.stream),
+                "hipMemcpyAsync");
+    if (!counts.empty())
+      check_hip(hipMemcpyAsync(dk, counts.data(), counts.size() * sizeof(PauliCount), hipMemcpyHostToDevice,
+                               psi.stream),
+                "hipMemcpyAsync");
+    launch_pauli_apply<R>((const cplx<R>*)phi.cur_ptr(), (cplx<R>*)lam.cur_ptr(), n, dg, (int)groups.size(), dk,
                           psi.stream);
     psi.sync();
   }

@@ -322,48 +322,55 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
   }
 }
 
-// out_i = sum_t c_t s_t(i) psi_{i ^ x_t}; consecutive terms sharing x reuse the read.
+// out_i = sum over groups g of (c0_g + sum_k w_k count_k(j)) psi_j, j = i ^ x_g.
 template <class R>
 __global__ void __launch_bounds__(kThreads) pauli_apply_kernel(const cplx<R>* __restrict__ psi,
                                                                cplx<R>* __restrict__ out, uint64_t N,
-                                                               const uint32_t* __restrict__ xs,
-                                                               const uint32_t* __restrict__ zs,
-                                                               const double* __restrict__ cs, int nt) {
+                                                               const PauliGroup* groups, int ng,
+                                                               const PauliCount* counts) {
+  const cptr<PauliGroup> G = to_const(groups);
+  const cptr<PauliCount> K = to_const(counts);
   for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < N; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t i = (uint32_t)t;
-    double accr = 0.0, acci = 0.0;
-    uint32_t xprev = 0xffffffffu;
-    double pr = 0.0, pi = 0.0;
-    for (int k = 0; k < nt; ++k) {
-      const uint32_t x = xs[k];
-      if (x != xprev) {
-        const cplx<R> v = psi[i ^ x];
-        pr = v.re;
-        pi = v.im;
-        xprev = x;
+    double ar = 0.0, ai = 0.0;
+    for (int g = 0; g < ng; ++g) {
+      const uint32_t j = i ^ G[g].x;
+      double cr = G[g].c0re, ci = G[g].c0im;
+      const int k1 = G[g].k0 + G[g].nk;
+      for (int k = G[g].k0; k < k1; ++k) {
+        const int form = K[k].form;
+        const uint32_t m = K[k].mask;
+        int c;
+        if (form == DT_SHIFT_XOR)
+          c = popc((j ^ (j >> K[k].shift)) & m);
+        else if (form == DT_PARITY)
+          c = popc(j & m) & 1;
+        else
+          c = popc(j & m);
+        cr = fma(K[k].wre, (double)c, cr);
+        ci = fma(K[k].wim, (double)c, ci);
       }
-      const double sg = (popc((i ^ x) & zs[k]) & 1) ? -1.0 : 1.0;
-      const double cr = sg * cs[2 * k], ci = sg * cs[2 * k + 1];
-      accr += cr * pr - ci * pi;
-      acci += cr * pi + ci * pr;
+      const cplx<R> v = psi[j];
+      ar = fma(cr, (double)v.re, fma(-ci, (double)v.im, ar));
+      ai = fma(cr, (double)v.im, fma(ci, (double)v.re, ai));
     }
-    out[i] = {(R)accr, (R)acci};
+    out[i] = {(R)ar, (R)ai};
   }
 }
 
 }  // namespace
 
 template <class R>
-void launch_pauli_apply(const cplx<R>* psi, cplx<R>* out, int n, const uint32_t* x_dev, const uint32_t* z_dev,
-                        const double* c_dev, int n_terms, hipStream_t s) {
+void launch_pauli_apply(const cplx<R>* psi, cplx<R>* out, int n, const PauliGroup* groups, int n_groups,
+                        const PauliCount* counts, hipStream_t s) {
   const uint64_t N = 1ull << n;
   QS_LAUNCH("pauli_apply", s, pauli_apply_kernel<R>, dim3(grid_for(N, kThreads)), dim3(kThreads), 0, s, psi, out, N,
-            x_dev, z_dev, c_dev, n_terms);
+            groups, n_groups, counts);
 }
-template void launch_pauli_apply<float>(const cplx<float>*, cplx<float>*, int, const uint32_t*, const uint32_t*,
-                                        const double*, int, hipStream_t);
-template void launch_pauli_apply<double>(const cplx<double>*, cplx<double>*, int, const uint32_t*, const uint32_t*,
-                                         const double*, int, hipStream_t);
+template void launch_pauli_apply<float>(const cplx<float>*, cplx<float>*, int, const PauliGroup*, int,
+                                        const PauliCount*, hipStream_t);
+template void launch_pauli_apply<double>(const cplx<double>*, cplx<double>*, int, const PauliGroup*, int,
+                                         const PauliCount*, hipStream_t);
 
 template <class R>
 void launch_fill_basis(cplx<R>* psi, uint64_t N, uint64_t index, hipStream_t s) {

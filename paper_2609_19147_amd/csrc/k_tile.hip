@@ -913,6 +913,54 @@ tile_kernel_dual(TileKArgs<R> A, cplx<R>* lam, RhoTileArgs Q,
   tile_store<R>(B, C, T1, blockDim.x);
 }
 
+// The same step with persistent workgroups (as many as fit on the device,
+// each walking the cosets c, c + G, c + 2G, ...) that issue the loads of
+// their next coset's two tiles into registers before the current coset's
+// rounds, cross densities and stores: HBM reads overlap the work of the step,
+// which a workgroup per coset (two or four resident per CU, each loading,
+// computing and storing in turn) leaves exposed.  complex64 with
+// 2^m = blockDim.x * kDualPipeK * 2 (eight 16-byte accesses per thread and
+// tile; checked on the host).
+constexpr int kDualPipeK = 8;
+template <class R, bool kDiag>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2)))
+tile_kernel_dual_pipe(TileKArgs<R> A, cplx<R>* lam, RhoTileArgs Q, double* __restrict__ partials,
+                      uint32_t n_cosets) {
+  static_assert(sizeof(R) == 4, "complex64 tiles only");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[rho::kRhoMaxWaves][32];
+  const uint32_t M = 1u << A.m;
+  cplx<R>* T0 = reinterpret_cast<cplx<R>*>(smem_raw);
+  cplx<R>* T1 = T0 + lds_off(M);
+  TileKArgs<R> B = A;
+  B.psi = lam;
+  typename PipeAccess<R>::T v0[kDualPipeK], v1[kDualPipeK];
+  const uint32_t G = gridDim.x;
+  uint32_t c = A.order ? blockIdx.x : xcd_block(blockIdx.x, G);
+  if (c < n_cosets) {
+    const Ctx C = coset_ctx(A, c);
+    pipe_issue<R, 0, kDualPipeK>(A, C, v0);
+    pipe_issue<R, 0, kDualPipeK>(B, C, v1);
+  }
+  for (; c < n_cosets; c += G) {
+    const Ctx C = coset_ctx(A, c);
+    __syncthreads();  // the previous coset's stores have finished reading the tiles
+    pipe_to_lds<R, 0, kDualPipeK>(v0, T0);
+    pipe_to_lds<R, 0, kDualPipeK>(v1, T1);
+    __syncthreads();
+    if (c + G < n_cosets) {
+      const Ctx Cn = coset_ctx(A, c + G);
+      pipe_issue<R, 0, kDualPipeK>(A, Cn, v0);
+      pipe_issue<R, 0, kDualPipeK>(B, Cn, v1);
+    }
+    tile_rounds<R, kDiag>(A, C, T0, blockDim.x);
+    tile_rounds<R, kDiag>(A, C, T1, blockDim.x);
+    if (Q.nbits) rho::accumulate_tile<R>(T0, T1, M, Q, red, partials, c, n_cosets);
+    tile_store<R>(A, C, T0, blockDim.x);
+    tile_store<R>(B, C, T1, blockDim.x);
+  }
+}
+
 // A batched instance's argument block, read field by field with scalar loads.
 template <class R>
 __device__ __forceinline__ TileKArgs<R> load_args(const TileKArgs<R>* descs, uint32_t i) {
@@ -1083,13 +1131,37 @@ void launch_tile(const TileKArgs<R>& A, hipStream_t s) {
 template <class R, bool kDiag>
 void launch_tile_dual_k(const TileKArgs<R>& A, cplx<R>* lam, const RhoTileArgs& Q, double* partials, size_t lds,
                         hipStream_t s) {
+  const uint32_t n_cosets = 1u << (A.n - A.m), threads = tile_threads_for<R, kDiag>(A.m);
+  if constexpr (sizeof(R) == 4) {
+    if ((1u << A.m) == threads * kDualPipeK * PipeAccess<R>::amps) {
+      // persistent: the workgroups that fit on the device at once (a
+      // property of the kernel, its block size and LDS, looked up once each)
+      static bool attr_set = false;
+      static int per_cu[16] = {0};
+      if (!attr_set) {
+        allow_dynamic_lds((const void*)tile_kernel_dual_pipe<R, kDiag>, kTileDynLds, "tile_pass_dual");
+        attr_set = true;
+      }
+      int& nb = per_cu[A.m & 15];
+      if (nb == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)tile_kernel_dual_pipe<R, kDiag>,
+                                                          (int)threads, lds) != hipSuccess ||
+            nb < 1)
+          nb = 1;
+      }
+      const uint32_t grid = std::min<uint64_t>(n_cosets, (uint64_t)nb * pipe_grid(~0u));
+      QS_LAUNCH("tile_pass_dual", s, (tile_kernel_dual_pipe<R, kDiag>), dim3(grid), dim3(threads), lds, s, A, lam, Q,
+                partials, n_cosets);
+      return;
+    }
+  }
   static bool attr_set = false;
   if (!attr_set) {
     allow_dynamic_lds((const void*)tile_kernel_dual<R, kDiag>, kTileDynLds, "tile_pass_dual");
     attr_set = true;
   }
-  QS_LAUNCH("tile_pass_dual", s, (tile_kernel_dual<R, kDiag>), dim3(1u << (A.n - A.m)),
-            dim3(tile_threads_for<R, kDiag>(A.m)), lds, s, A, lam, Q, partials);
+  QS_LAUNCH("tile_pass_dual", s, (tile_kernel_dual<R, kDiag>), dim3(n_cosets), dim3(threads), lds, s, A, lam, Q,
+            partials);
 }
 
 template <class R>

@@ -204,11 +204,28 @@ template <class R>
 void launch_marginal(const cplx<R>* psi, const MarginalArgs& A, double* partials, double* out, hipStream_t s);
 
 // ---- adjoint support ----
-// out_i = sum_t c_t (-1)^{popcount((i ^ x_t) & z_t)} psi_{i ^ x_t}, terms sorted by x
-// (c_t complex: the Pauli coefficient times i^{#Y}); arrays in device memory.
+// out = H psi for a sum of Pauli terms c_t X^{x_t} Z^{z_t} (c_t complex: the
+// coefficient times i^{#Y}): out_i = sum_t c_t (-1)^{popcount(j & z_t)} psi_j
+// with j = i ^ x_t.  The terms of one X mask form a group whose coefficient
+// of j is c0 + sum_k w_k count_k(j), count_k one of the diagonal layers' count
+// forms (DT_BITS: single Z, DT_SHIFT_XOR: Z pairs at one distance, DT_PARITY:
+// longer Z strings), so that equal-coefficient Z and ZZ terms cost one
+// popcount together.  Groups and counts in device memory.
+struct PauliGroup {
+  uint32_t x;
+  int32_t k0, nk;  // counts [k0, k0 + nk)
+  int32_t pad;
+  double c0re, c0im;
+};
+struct PauliCount {
+  int32_t form;  // DT_BITS, DT_SHIFT_XOR or DT_PARITY
+  uint32_t shift, mask;
+  int32_t pad;
+  double wre, wim;
+};
 template <class R>
-void launch_pauli_apply(const cplx<R>* psi, cplx<R>* out, int n, const uint32_t* x_dev, const uint32_t* z_dev,
-                        const double* c_dev, int n_terms, hipStream_t s);
+void launch_pauli_apply(const cplx<R>* psi, cplx<R>* out, int n, const PauliGroup* groups, int n_groups,
+                        const PauliCount* counts, hipStream_t s);
 // rho[r][c] = sum over pairs on bit b of conj(lam_r) phi_c (8 doubles: re/im of
 // rho00, rho01, rho10, rho11).
 template <class R>

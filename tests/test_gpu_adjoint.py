@@ -197,3 +197,29 @@ def test_work_states_are_reused_across_calls_and_plans(qs):
     assert abs(e2 - gradients.energy(n, s2, p2, W.z_terms(n), psi0=psi0)) < 1e-5
     g_ref = gradients.parameter_shift(n, s2, p2, W.z_terms(n), psi0=psi0)
     assert np.max(np.abs(g2 - g_ref)) < 1e-5
+
+
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c128", 1e-11)])
+def test_mixed_pauli_strings(qs, dtype, tol):
+    """Observables beyond XXZ: random X/Y/Z strings of length 1-5 (some
+    sharing an X mask, some with equal coefficients and Z masks that overlap
+    or repeat), every term shape of the grouped H psi against the oracle's
+    energy and parameter-shift gradients."""
+    n, layers = 8, 2
+    stream = W.hea_stream(n, layers)
+    params = W.hea_params(n, layers, 7)
+    rng = np.random.default_rng(11)
+    terms = []
+    for _ in range(40):
+        k = int(rng.integers(1, 6))
+        qubits = rng.choice(n, size=k, replace=False)
+        ops = {int(q): "XYZ"[int(rng.integers(0, 3))] for q in qubits}
+        terms.append(W.pauli(float(rng.choice([0.5, -0.25, rng.normal()])), ops))
+    # repeated and same-coefficient diagonal terms (merged counts must stay disjoint)
+    terms += [W.pauli(0.5, {1: "Z", 2: "Z"}), W.pauli(0.5, {1: "Z", 2: "Z"}), W.pauli(0.5, {2: "Z", 3: "Z"}),
+              W.pauli(0.5, {4: "Z"}), W.pauli(0.5, {4: "Z"}), W.pauli(0.5, {5: "Z"}), W.pauli(1.5, {})]
+    plan = qs.Plan(n, stream, n_params=len(params), params=params)
+    e, g = qs.adjoint_grad(qs.State(n, dtype), plan, terms)
+    assert abs(e - gradients.energy(n, stream, params, terms)) < tol
+    g_ref = gradients.parameter_shift(n, stream, params, terms)
+    assert np.max(np.abs(g - g_ref)) < tol, np.max(np.abs(g - g_ref))
