@@ -105,6 +105,27 @@ __device__ __forceinline__ void dense_store(cplx<R>* __restrict__ psi, const cpl
   }
 }
 
+// Accesses [K0, K1) of a tile's pair accesses (p = 2 threadIdx.x + 2 kDenseThreads k)
+// into registers, and from registers into the LDS tile.
+template <class R, int K0, int K1>
+__device__ __forceinline__ void dense_issue(const cplx<R>* __restrict__ psi, uint32_t base, uint32_t L,
+                                            const uint32_t* hi_tab, cplx2<R>* v) {
+  const uint32_t Lmask = (1u << L) - 1u;
+#pragma unroll
+  for (int k = K0; k < K1; ++k) {
+    const uint32_t p = 2u * threadIdx.x + 2u * kDenseThreads * k;
+    v[k - K0] = ld_nt(reinterpret_cast<const cplx2<R>*>(psi + (base | (p & Lmask) | hi_tab[p >> L])));
+  }
+}
+template <class R, int K0, int K1>
+__device__ __forceinline__ void dense_put(cplx<R>* T, const cplx2<R>* v) {
+#pragma unroll
+  for (int k = K0; k < K1; ++k) {
+    const uint32_t p = 2u * threadIdx.x + 2u * kDenseThreads * k;
+    *reinterpret_cast<cplx2<R>*>(T + dense_lds_off(p)) = v[k - K0];
+  }
+}
+
 // complex128 k = 4: one 16-byte amplitude per lane and access.
 __device__ __forceinline__ void dense_load1(const cplx<double>* __restrict__ psi, cplx<double>* T, uint32_t M,
                                             uint32_t base, uint32_t L, const uint32_t* hi_tab) {
@@ -156,7 +177,7 @@ __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
 }
 
 template <class R, int K>
-__global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restrict__ psi, const cplx<R>* U_,
+__global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(3))) dense_kernel(cplx<R>* __restrict__ psi, const cplx<R>* U_,
                                                               DenseGeom G) {
   constexpr int KS = K / 4;   // 4-deep steps of the contraction
   // 16-row tiles of U per wave: complex64 k = 6 splits its four between the
@@ -207,13 +228,33 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
   const uint32_t ncb = (1u << G.c) >> 4;
   __syncthreads();
 
-  for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
-    // coset bits of tile t (the state bits outside the tile)
+  // complex64 k = 6 (2^12-amplitude tiles, eight pair accesses per thread):
+  // the first kPre accesses of the next tile are issued before this tile's
+  // contraction (the register file holds no more at three waves per SIMD),
+  // the rest at the top of the tile's turn
+  constexpr bool kPipe = kSplit;
+  constexpr int kAcc = 8, kPre = 4;
+  const bool pipe = kPipe && M == 2u * kDenseThreads * kAcc;  // full tiles (n - k >= 6)
+  auto tile_base = [&](uint32_t t) {
     uint32_t base = 0;
     for (uint32_t j = 0; j < G.n_free; ++j)
       if ((t >> j) & 1u) base |= 1u << G.free_bit[j];
+    return base;
+  };
+  cplx2<R> pre[kPipe ? kPre : 1];
+  if constexpr (kPipe) {
+    if (pipe && blockIdx.x < G.n_tiles) dense_issue<R, 0, kPre>(psi, tile_base(blockIdx.x), G.L, hi_tab, pre);
+  }
+  for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
+    // coset bits of tile t (the state bits outside the tile)
+    const uint32_t base = tile_base(t);
     // load: tile bit 0 is state bit 0, so pairs (p, p + 1) are adjacent
-    if constexpr (sizeof(R) == 8 && K == 16) {
+    if (kPipe && pipe) {
+      cplx2<R> rest[kAcc - kPre];
+      dense_issue<R, kPre, kAcc>(psi, base, G.L, hi_tab, rest);
+      dense_put<R, 0, kPre>(T, pre);
+      dense_put<R, kPre, kAcc>(T, rest);
+    } else if constexpr (sizeof(R) == 8 && K == 16) {
       // complex128, k = 4 (K = 16, memory-bound): one 16-byte amplitude per lane and
       // access (for k = 5 the extra address work costs more than it saves)
       dense_load1(psi, T, M, base, G.L, hi_tab);
@@ -221,6 +262,10 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel(cplx<R>* __restric
       dense_load<R, dense_io<R, K>()>(psi, T, M, base, G.L, hi_tab);
     }
     __syncthreads();
+    if constexpr (kPipe) {
+      if (pipe && t + gridDim.x < G.n_tiles)
+        dense_issue<R, 0, kPre>(psi, tile_base(t + gridDim.x), G.L, hi_tab, pre);
+    }
 
     // uniform trip count: with split row tiles the two waves of a pair read
     // all rows of a column block and each writes half of them back in place,
