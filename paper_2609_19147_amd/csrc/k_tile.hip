@@ -366,6 +366,59 @@ struct RoundLoop {
   }
 };
 
+// The same loop over two tiles at once (the fused adjoint step's phi and
+// lambda): one set of LDS addresses and one barrier per round for both.
+template <class R>
+struct RoundLoop2 {
+  const Ctx& C;
+  cptr<TileRound> R_;
+  cplx<R>* T;
+  cplx<R>* T1;
+  uint32_t ngroups, nthr;
+
+  template <class F>
+  __device__ __forceinline__ void operator()(const F& f) const {
+    const int t0 = R_->tbit[0], t1 = R_->tbit[1], t2 = R_->tbit[2], t3 = R_->tbit[3];
+    uint32_t loff[RN];
+#pragma unroll
+    for (int j = 0; j < RN; ++j) loff[j] = R_->loff[j];
+    for (uint32_t g = threadIdx.x; g < ngroups; g += nthr) {
+      uint32_t gpos = insert0(g, t0);
+      gpos = insert0(gpos, t1);
+      gpos = insert0(gpos, t2);
+      gpos = insert0(gpos, t3);
+      cplx<R>* Ta = T + lds_off(gpos);
+      cplx<R>* Tb = T1 + lds_off(gpos);
+      cplx<R> a[RN], b[RN];
+#pragma unroll
+      for (int j = 0; j < RN; ++j) a[j] = Ta[loff[j]];
+#pragma unroll
+      for (int j = 0; j < RN; ++j) b[j] = Tb[loff[j]];
+      const uint32_t gg = C.base | C.dep(gpos);
+      f(a, gg);
+      f(b, gg);
+#pragma unroll
+      for (int j = 0; j < RN; ++j) Ta[loff[j]] = a[j];
+#pragma unroll
+      for (int j = 0; j < RN; ++j) Tb[loff[j]] = b[j];
+    }
+  }
+};
+template <class R, bool kTwo>
+struct LoopOf {
+  using type = RoundLoop<R>;
+  __device__ static type make(const Ctx& C, cptr<TileRound> R_, cplx<R>* T, cplx<R>*, uint32_t ng, uint32_t nt) {
+    return type{C, R_, T, ng, nt};
+  }
+};
+template <class R>
+struct LoopOf<R, true> {
+  using type = RoundLoop2<R>;
+  __device__ static type make(const Ctx& C, cptr<TileRound> R_, cplx<R>* T, cplx<R>* T1, uint32_t ng, uint32_t nt) {
+    return type{C, R_, T, T1, ng, nt};
+  }
+};
+
 // RT_DIAG rounds: register j of the group at index g holds index g | b_j with
 // b_j the subset j of the round's state bits b[0..3].
 template <class R, bool kConj>
@@ -480,8 +533,10 @@ __device__ __forceinline__ void tile_load(const TileKArgs<R>& A, const Ctx& C, c
   }
 }
 
-template <class R, bool kDiag>
-__device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C, cplx<R>* T, uint32_t nthr) {
+// kTwo: the rounds run on T and T1 together (RoundLoop2).
+template <class R, bool kDiag, bool kTwo = false>
+__device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C, cplx<R>* T, uint32_t nthr,
+                                            cplx<R>* T1 = nullptr) {
   // threads [0, nthr) take the register groups; every thread of the workgroup
   // takes part in the barrier after each round
   const uint32_t M = 1u << A.m;
@@ -494,7 +549,7 @@ __device__ __forceinline__ void tile_rounds(const TileKArgs<R>& A, const Ctx& C,
   const cptr<cplx<R>> coef = to_const(A.coef);
   for (uint32_t r = 0; r < A.n_rounds; ++r) {
     const cptr<TileRound> R_ = rounds + r;
-    const RoundLoop<R> L{C, R_, T, ngroups, nthr};
+    const auto L = LoopOf<R, kTwo>::make(C, R_, T, T1, ngroups, nthr);
     switch (R_->type) {
       case RT_DIAG:
         if constexpr (kDiag) {
@@ -953,8 +1008,12 @@ tile_kernel_dual_pipe(TileKArgs<R> A, cplx<R>* lam, RhoTileArgs Q, double* __res
       pipe_issue<R, 0, kDualPipeK>(A, Cn, v0);
       pipe_issue<R, 0, kDualPipeK>(B, Cn, v1);
     }
-    tile_rounds<R, kDiag>(A, C, T0, blockDim.x);
-    tile_rounds<R, kDiag>(A, C, T1, blockDim.x);
+    if constexpr (kDiag) {
+      tile_rounds<R, kDiag>(A, C, T0, blockDim.x);
+      tile_rounds<R, kDiag>(A, C, T1, blockDim.x);
+    } else {
+      tile_rounds<R, false, true>(A, C, T0, blockDim.x, T1);
+    }
     if (Q.nbits) rho::accumulate_tile<R>(T0, T1, M, Q, red, partials, c, n_cosets);
     tile_store<R>(A, C, T0, blockDim.x);
     tile_store<R>(B, C, T1, blockDim.x);
