@@ -945,7 +945,7 @@ __global__ void __launch_bounds__(kWsConsumers + kWsProducers) tile_kernel_ws(Ti
 // resulting tiles, and both tiles are stored back -- 4 S of HBM traffic per
 // layer instead of 6 S for two passes and a separate re-read of both states.
 template <class R, bool kDiag>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
 tile_kernel_dual(TileKArgs<R> A, cplx<R>* lam, RhoTileArgs Q,
                                                                  double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -73,23 +73,67 @@ __device__ __forceinline__ void rho_chunk(const cplx<R>* P, const cplx<R>* Q, ui
       f[j] = Pg[loff[j]];
       l[j] = Qg[loff[j]];
     }
+    if constexpr (kReq == 4 && kN == 16) {
+      // diagonal sums of all four bits from the 16 products conj(l_j) f_j and
+      // one tree of partial sums (p1: over bit 0, p2: bits 0-1, p3: bits 0-2):
+      // the sum over j with bit k clear is p3[0] (k = 3), p2[0] + p2[2],
+      // p1[0] + p1[2] + p1[4] + p1[6], and the even j (k = 0); the sum with
+      // bit k set is the total minus it
+      auto prod = [&](int j) {
+        return cplx<R>{(R)fma(l[j].re, f[j].re, l[j].im * f[j].im), (R)fma(l[j].re, f[j].im, -l[j].im * f[j].re)};
+      };
+      cplx<R> p1[8], p2[4], p3[2], even = {R(0), R(0)};
 #pragma unroll
-    for (int k = 0; k < kReq; ++k)
-#pragma unroll
-      for (int j = 0; j < kN; ++j) {
-        if ((j >> k) & 1) continue;
-        const int j1 = j | (1 << k);
-        const cplx<R> f0 = f[j], f1 = f[j1], l0 = l[j], l1 = l[j1];
-        // two multiply-adds per sum and pair
-        acc[k][0] = fma(l0.re, f0.re, fma(l0.im, f0.im, acc[k][0]));
-        acc[k][1] = fma(l0.re, f0.im, fma(-l0.im, f0.re, acc[k][1]));
-        acc[k][2] = fma(l0.re, f1.re, fma(l0.im, f1.im, acc[k][2]));
-        acc[k][3] = fma(l0.re, f1.im, fma(-l0.im, f1.re, acc[k][3]));
-        acc[k][4] = fma(l1.re, f0.re, fma(l1.im, f0.im, acc[k][4]));
-        acc[k][5] = fma(l1.re, f0.im, fma(-l1.im, f0.re, acc[k][5]));
-        acc[k][6] = fma(l1.re, f1.re, fma(l1.im, f1.im, acc[k][6]));
-        acc[k][7] = fma(l1.re, f1.im, fma(-l1.im, f1.re, acc[k][7]));
+      for (int j = 0; j < 8; ++j) {
+        const cplx<R> c0 = prod(2 * j), c1 = prod(2 * j + 1);
+        even = cadd(even, c0);
+        p1[j] = cadd(c0, c1);
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p2[j] = cadd(p1[2 * j], p1[2 * j + 1]);
+      p3[0] = cadd(p2[0], p2[1]);
+      p3[1] = cadd(p2[2], p2[3]);
+      const cplx<R> tot = cadd(p3[0], p3[1]);
+      const cplx<R> s0[4] = {even, cadd(cadd(p1[0], p1[2]), cadd(p1[4], p1[6])), cadd(p2[0], p2[2]), p3[0]};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        acc[k][0] += s0[k].re;
+        acc[k][1] += s0[k].im;
+        acc[k][6] += tot.re - s0[k].re;
+        acc[k][7] += tot.im - s0[k].im;
+      }
+      // the cross terms pair by pair, two multiply-adds per sum and pair
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if ((j >> k) & 1) continue;
+          const int j1 = j | (1 << k);
+          const cplx<R> f0 = f[j], f1 = f[j1], l0 = l[j], l1 = l[j1];
+          acc[k][2] = fma(l0.re, f1.re, fma(l0.im, f1.im, acc[k][2]));
+          acc[k][3] = fma(l0.re, f1.im, fma(-l0.im, f1.re, acc[k][3]));
+          acc[k][4] = fma(l1.re, f0.re, fma(l1.im, f0.im, acc[k][4]));
+          acc[k][5] = fma(l1.re, f0.im, fma(-l1.im, f0.re, acc[k][5]));
+        }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kReq; ++k)
+#pragma unroll
+        for (int j = 0; j < kN; ++j) {
+          if ((j >> k) & 1) continue;
+          const int j1 = j | (1 << k);
+          const cplx<R> f0 = f[j], f1 = f[j1], l0 = l[j], l1 = l[j1];
+          // two multiply-adds per sum and pair
+          acc[k][0] = fma(l0.re, f0.re, fma(l0.im, f0.im, acc[k][0]));
+          acc[k][1] = fma(l0.re, f0.im, fma(-l0.im, f0.re, acc[k][1]));
+          acc[k][2] = fma(l0.re, f1.re, fma(l0.im, f1.im, acc[k][2]));
+          acc[k][3] = fma(l0.re, f1.im, fma(-l0.im, f1.re, acc[k][3]));
+          acc[k][4] = fma(l1.re, f0.re, fma(l1.im, f0.im, acc[k][4]));
+          acc[k][5] = fma(l1.re, f0.im, fma(-l1.im, f0.re, acc[k][5]));
+          acc[k][6] = fma(l1.re, f1.re, fma(l1.im, f1.im, acc[k][6]));
+          acc[k][7] = fma(l1.re, f1.im, fma(-l1.im, f1.re, acc[k][7]));
+        }
+    }
   }
   // sums over the wavefront by recursive halving (fixed order): each exchange
   // at lane distance d hands half of a lane's values to its partner, so the
