@@ -297,3 +297,44 @@ def test_long_rotation_runs_keep_the_norm(qs):
     before = qs.norm2(st)
     qs.apply(st, qs.Plan(n, stream))
     assert abs(qs.norm2(st) / before - 1.0) < 2e-6
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_single_qubit_round_factorisations(qs, dtype):
+    """Layers of single-qubit gates whose fused 2x2 matrices sit at the edges
+    of the tile rounds' D2 [[1, -t], [t, 1]] D1 form: pure phases (t = 0),
+    X-like matrices (no factorisation: the plain matrix round), |t| just below
+    and above the factored bound 8, Hadamards (scaled unitaries), RY near pi,
+    RY then RZ (D1 all ones), RZ then RY (D2 all ones) and Haar unitaries
+    (both tables), three layers deep, against the oracle."""
+    n = 14
+    rng = np.random.default_rng(21)
+    t8 = 2.0 * math.atan(8.0)
+    per_qubit = [
+        [W.G("RZ", 0, theta=0.7), W.G("S", 0), W.G("T", 0)],
+        [W.G("X", 0), W.G("RZ", 0, theta=0.3)],
+        [W.G("RY", 0, theta=t8 - 1e-3)],
+        [W.G("RY", 0, theta=t8 + 1e-3)],
+        [W.G("H", 0)],
+        [W.G("RY", 0, theta=math.pi - 1e-4), W.G("RZ", 0, theta=-1.1)],
+        [W.G("RY", 0, theta=0.4), W.G("RZ", 0, theta=1.3)],
+        [W.G("RZ", 0, theta=-0.6), W.G("RY", 0, theta=2.2)],
+        [W.G("U", 0, mat=W.random_unitary(2, rng))],
+        [W.G("SX", 0), W.G("P", 0, theta=0.9)],
+        [W.G("Y", 0)],
+        [W.G("RX", 0, theta=1.7), W.G("RZ", 0, theta=0.2)],
+        [W.G("U", 0, mat=W.random_unitary(2, rng)), W.G("H", 0)],
+        [W.G("RY", 0, theta=-2.9)],
+    ]
+    stream = []
+    for layer in range(3):
+        for q in range(n):
+            for g in per_qubit[(q + 5 * layer) % len(per_qubit)]:
+                mat = None if g.mat is None else np.array(g.mat).reshape(2, 2)
+                stream.append(W.G(g.name, q, theta=g.theta, mat=mat))
+        stream.append(W.G("CNOT", layer, layer + 7))
+    st, psi0 = start(qs, n, dtype, 4)
+    plan = qs.Plan(n, stream, window_k=-1)  # structured tile rounds, no dense windows
+    assert all(l["kind"] != "dense" for l in plan.describe()["layers"])
+    qs.apply(st, plan)
+    compare(qs, st, sv.run(psi0, n, stream), dtype, n)
