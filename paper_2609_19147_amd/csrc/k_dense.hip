@@ -316,7 +316,10 @@ __global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per
 // complex128 k = 6: the 64 x 64 matrix (64 KB) does not fit the register
 // file, so it is staged in LDS next to the tile and each wave reads its A
 // fragments from there; otherwise as dense_kernel (f64 MFMA, D[i][j] in lane
-// j + 16 (i % 4), register i / 4).
+// j + 16 (i % 4), register i / 4).  The staged rows are kUsStride = 65
+// entries apart: the 16 rows a fragment read touches then fall in 16
+// different bank groups (at 64 they would all share one).
+constexpr int kUsStride = 65;
 __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<double>* __restrict__ psi,
                                                                       const cplx<double>* U_, DenseGeom G) {
   constexpr int K = 64, RT = K / 16, KS = K / 4;
@@ -325,7 +328,7 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<doubl
   const uint32_t M = 1u << G.m;
   cplx<double>* T = reinterpret_cast<cplx<double>*>(smem_raw);
   cplx<double>* Us = T + dense_lds_off(M);
-  uint32_t* hi_tab = reinterpret_cast<uint32_t*>(Us + K * K);
+  uint32_t* hi_tab = reinterpret_cast<uint32_t*>(Us + K * kUsStride);
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t li = lane & 15u, lk = lane >> 4;
   for (uint32_t h = threadIdx.x; h < (1u << G.n_hi); h += kDenseThreads) {
@@ -334,7 +337,7 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<doubl
       if ((h >> j) & 1u) off |= 1u << G.hi_bit[j];
     hi_tab[h] = off;
   }
-  for (uint32_t e = threadIdx.x; e < (uint32_t)(K * K); e += kDenseThreads) Us[e] = U_[e];
+  for (uint32_t e = threadIdx.x; e < (uint32_t)(K * K); e += kDenseThreads) Us[(e / K) * kUsStride + e % K] = U_[e];
   const uint32_t colmask = (M - 1u) & ~G.rowmask;
   uint32_t brow[KS];
 #pragma unroll
@@ -347,12 +350,36 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<doubl
   const uint32_t ncb = (1u << G.c) >> 4;
   __syncthreads();
 
-  for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
+  // one workgroup per CU (tile and matrix fill the LDS): the next tile's first
+  // kPre accesses are issued before this tile's contraction, the rest at the
+  // top of its turn, so HBM reads overlap the matrix cores
+  constexpr int kAcc = 8, kPre = 8;
+  const bool pipe = M == 2u * kDenseThreads * kAcc;  // full tiles (n - k >= 6)
+  auto tile_base = [&](uint32_t t) {
     uint32_t base = 0;
     for (uint32_t j = 0; j < G.n_free; ++j)
       if ((t >> j) & 1u) base |= 1u << G.free_bit[j];
-    dense_load<double, 4>(psi, T, M, base, G.L, hi_tab);
+    return base;
+  };
+  cplx2<double> pre[kPre];
+  if (pipe && blockIdx.x < G.n_tiles) dense_issue<double, 0, kPre>(psi, tile_base(blockIdx.x), G.L, hi_tab, pre);
+  for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
+    const uint32_t base = tile_base(t);
+    if (pipe) {
+      if constexpr (kPre < kAcc) {
+        cplx2<double> rest[kAcc > kPre ? kAcc - kPre : 1];
+        dense_issue<double, kPre, kAcc>(psi, base, G.L, hi_tab, rest);
+        dense_put<double, 0, kPre>(T, pre);
+        dense_put<double, kPre, kAcc>(T, rest);
+      } else {
+        dense_put<double, 0, kPre>(T, pre);
+      }
+    } else {
+      dense_load<double, 4>(psi, T, M, base, G.L, hi_tab);
+    }
     __syncthreads();
+    if (pipe && t + gridDim.x < G.n_tiles)
+      dense_issue<double, 0, kPre>(psi, tile_base(t + gridDim.x), G.L, hi_tab, pre);
     for (uint32_t cb = wave; cb < ncb; cb += kDenseThreads / 64) {
       const uint32_t colp = deposit(16u * cb + li, colmask);
       acc_t yr[RT], yi[RT];
@@ -367,7 +394,7 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<doubl
         const double nxi = -x.im;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-          const cplx<double> u = Us[(16u * rt + li) * K + 4u * ks + lk];
+          const cplx<double> u = Us[(16u * rt + li) * kUsStride + 4u * ks + lk];
           yr[rt] = mfma16(u.re, x.re, yr[rt]);
           yr[rt] = mfma16(u.im, nxi, yr[rt]);
           yi[rt] = mfma16(u.re, x.im, yi[rt]);
@@ -438,8 +465,8 @@ bool launch_dense(cplx<R>* psi, int n, int k, const int* bits_sorted, const cplx
   } else if constexpr (sizeof(R) == 4) {
     QS_LAUNCH("dense_k6", s, (dense_kernel<R, 64>), dim3(grid), dim3(kDenseThreads), lds, s, psi, U_dev, G);
   } else {
-    // the tile, the 64 x 64 complex128 matrix and the offset table: ~132 KB
-    const size_t lds6 = lds + sizeof(cplx<double>) * 64 * 64;
+    // the tile, the 64 x 64 complex128 matrix (rows padded) and the offset table: ~136 KB
+    const size_t lds6 = lds + sizeof(cplx<double>) * 64 * kUsStride;
     static bool attr_set = false;
     if (!attr_set) {
       allow_dynamic_lds((const void*)dense_kernel_k6_c128, (int)lds6, "dense_k6");
