@@ -67,10 +67,10 @@ __device__ __forceinline__ uint32_t dense_lds_off(uint32_t pos) { return pos + (
 template <class R, int K>
 constexpr int dense_io() { return K == 16 ? 2 : 4; }
 
-template <class R, int kIO>
+template <class R, int kIO, uint32_t NT = kDenseThreads>
 __device__ __forceinline__ void dense_load(const cplx<R>* __restrict__ psi, cplx<R>* T, uint32_t M, uint32_t base,
                                            uint32_t L, const uint32_t* hi_tab) {
-  const uint32_t Lmask = (1u << L) - 1u, step = 2u * kDenseThreads;
+  const uint32_t Lmask = (1u << L) - 1u, step = 2u * NT;
   for (uint32_t p0 = 2u * threadIdx.x; p0 < M; p0 += step * kIO) {
     cplx2<R> v[kIO];
 #pragma unroll
@@ -86,10 +86,10 @@ __device__ __forceinline__ void dense_load(const cplx<R>* __restrict__ psi, cplx
   }
 }
 
-template <class R, int kIO>
+template <class R, int kIO, uint32_t NT = kDenseThreads>
 __device__ __forceinline__ void dense_store(cplx<R>* __restrict__ psi, const cplx<R>* T, uint32_t M, uint32_t base,
                                             uint32_t L, const uint32_t* hi_tab) {
-  const uint32_t Lmask = (1u << L) - 1u, step = 2u * kDenseThreads;
+  const uint32_t Lmask = (1u << L) - 1u, step = 2u * NT;
   for (uint32_t p0 = 2u * threadIdx.x; p0 < M; p0 += step * kIO) {
     cplx2<R> v[kIO];
 #pragma unroll
@@ -105,23 +105,23 @@ __device__ __forceinline__ void dense_store(cplx<R>* __restrict__ psi, const cpl
   }
 }
 
-// Accesses [K0, K1) of a tile's pair accesses (p = 2 threadIdx.x + 2 kDenseThreads k)
-// into registers, and from registers into the LDS tile.
-template <class R, int K0, int K1>
+// Accesses [K0, K1) of a tile's pair accesses (p = 2 threadIdx.x + 2 NT k, NT
+// threads) into registers, and from registers into the LDS tile.
+template <class R, int K0, int K1, uint32_t NT = kDenseThreads>
 __device__ __forceinline__ void dense_issue(const cplx<R>* __restrict__ psi, uint32_t base, uint32_t L,
                                             const uint32_t* hi_tab, cplx2<R>* v) {
   const uint32_t Lmask = (1u << L) - 1u;
 #pragma unroll
   for (int k = K0; k < K1; ++k) {
-    const uint32_t p = 2u * threadIdx.x + 2u * kDenseThreads * k;
+    const uint32_t p = 2u * threadIdx.x + 2u * NT * k;
     v[k - K0] = ld_nt(reinterpret_cast<const cplx2<R>*>(psi + (base | (p & Lmask) | hi_tab[p >> L])));
   }
 }
-template <class R, int K0, int K1>
+template <class R, int K0, int K1, uint32_t NT = kDenseThreads>
 __device__ __forceinline__ void dense_put(cplx<R>* T, const cplx2<R>* v) {
 #pragma unroll
   for (int k = K0; k < K1; ++k) {
-    const uint32_t p = 2u * threadIdx.x + 2u * kDenseThreads * k;
+    const uint32_t p = 2u * threadIdx.x + 2u * NT * k;
     *reinterpret_cast<cplx2<R>*>(T + dense_lds_off(p)) = v[k - K0];
   }
 }
@@ -320,9 +320,15 @@ __global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per
 // entries apart: the 16 rows a fragment read touches then fall in 16
 // different bank groups (at 64 they would all share one).
 constexpr int kUsStride = 65;
-__global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<double>* __restrict__ psi,
-                                                                      const cplx<double>* U_, DenseGeom G) {
-  constexpr int K = 64, RT = K / 16, KS = K / 4;
+constexpr uint32_t kThreads6 = 512;
+__global__ void __launch_bounds__(kThreads6) dense_kernel_k6_c128(cplx<double>* __restrict__ psi,
+                                                                  const cplx<double>* U_, DenseGeom G) {
+  // 512 threads, two waves per SIMD: the waves of a pair take the same
+  // column block, each two of U's four 16-row tiles (as the complex64 k = 6
+  // split), with a barrier between a column block's reads and its in-place
+  // writes
+  constexpr int K = 64, RT = 2, KS = K / 4;
+  constexpr uint32_t NT = kThreads6;
   typedef f64x4 acc_t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const uint32_t M = 1u << G.m;
@@ -331,13 +337,14 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<doubl
   uint32_t* hi_tab = reinterpret_cast<uint32_t*>(Us + K * kUsStride);
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t li = lane & 15u, lk = lane >> 4;
-  for (uint32_t h = threadIdx.x; h < (1u << G.n_hi); h += kDenseThreads) {
+  const uint32_t rt0 = 2u * (wave & 1u), cb0 = wave >> 1, cbs = NT / 128u;
+  for (uint32_t h = threadIdx.x; h < (1u << G.n_hi); h += NT) {
     uint32_t off = 0;
     for (uint32_t j = 0; j < G.n_hi; ++j)
       if ((h >> j) & 1u) off |= 1u << G.hi_bit[j];
     hi_tab[h] = off;
   }
-  for (uint32_t e = threadIdx.x; e < (uint32_t)(K * K); e += kDenseThreads) Us[(e / K) * kUsStride + e % K] = U_[e];
+  for (uint32_t e = threadIdx.x; e < (uint32_t)(K * K); e += NT) Us[(e / K) * kUsStride + e % K] = U_[e];
   const uint32_t colmask = (M - 1u) & ~G.rowmask;
   uint32_t brow[KS];
 #pragma unroll
@@ -346,68 +353,67 @@ __global__ void __launch_bounds__(kDenseThreads) dense_kernel_k6_c128(cplx<doubl
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) drow[rt][v] = deposit(16u * rt + lk + 4u * v, G.rowmask);
+    for (int v = 0; v < 4; ++v) drow[rt][v] = deposit(16u * (rt0 + rt) + lk + 4u * v, G.rowmask);
   const uint32_t ncb = (1u << G.c) >> 4;
+  const uint32_t trips = (ncb + cbs - 1u) / cbs;
   __syncthreads();
 
-  // one workgroup per CU (tile and matrix fill the LDS): the next tile's first
-  // kPre accesses are issued before this tile's contraction, the rest at the
-  // top of its turn, so HBM reads overlap the matrix cores
-  constexpr int kAcc = 8, kPre = 8;
-  const bool pipe = M == 2u * kDenseThreads * kAcc;  // full tiles (n - k >= 6)
+  // the next tile's loads are issued before this tile's contraction (one
+  // workgroup per CU: tile and matrix fill the LDS)
+  constexpr int kAcc = 4;
+  const bool pipe = M == 2u * NT * kAcc;  // full tiles (n - k >= 6)
   auto tile_base = [&](uint32_t t) {
     uint32_t base = 0;
     for (uint32_t j = 0; j < G.n_free; ++j)
       if ((t >> j) & 1u) base |= 1u << G.free_bit[j];
     return base;
   };
-  cplx2<double> pre[kPre];
-  if (pipe && blockIdx.x < G.n_tiles) dense_issue<double, 0, kPre>(psi, tile_base(blockIdx.x), G.L, hi_tab, pre);
+  cplx2<double> pre[kAcc];
+  if (pipe && blockIdx.x < G.n_tiles) dense_issue<double, 0, kAcc, NT>(psi, tile_base(blockIdx.x), G.L, hi_tab, pre);
   for (uint32_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
     const uint32_t base = tile_base(t);
-    if (pipe) {
-      if constexpr (kPre < kAcc) {
-        cplx2<double> rest[kAcc > kPre ? kAcc - kPre : 1];
-        dense_issue<double, kPre, kAcc>(psi, base, G.L, hi_tab, rest);
-        dense_put<double, 0, kPre>(T, pre);
-        dense_put<double, kPre, kAcc>(T, rest);
-      } else {
-        dense_put<double, 0, kPre>(T, pre);
-      }
-    } else {
-      dense_load<double, 4>(psi, T, M, base, G.L, hi_tab);
-    }
+    if (pipe)
+      dense_put<double, 0, kAcc, NT>(T, pre);
+    else
+      dense_load<double, 2, NT>(psi, T, M, base, G.L, hi_tab);
     __syncthreads();
     if (pipe && t + gridDim.x < G.n_tiles)
-      dense_issue<double, 0, kPre>(psi, tile_base(t + gridDim.x), G.L, hi_tab, pre);
-    for (uint32_t cb = wave; cb < ncb; cb += kDenseThreads / 64) {
-      const uint32_t colp = deposit(16u * cb + li, colmask);
+      dense_issue<double, 0, kAcc, NT>(psi, tile_base(t + gridDim.x), G.L, hi_tab, pre);
+    for (uint32_t it = 0; it < trips; ++it) {
+      const uint32_t cb = cb0 + it * cbs;
+      const bool active = cb < ncb;
+      const uint32_t colp = deposit(16u * (active ? cb : 0u) + li, colmask);
       acc_t yr[RT], yi[RT];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         yr[rt] = acc_t{0, 0, 0, 0};
         yi[rt] = acc_t{0, 0, 0, 0};
       }
+      if (active) {
 #pragma unroll 4
-      for (int ks = 0; ks < KS; ++ks) {
-        const cplx<double> x = T[dense_lds_off(brow[ks] | colp)];
-        const double nxi = -x.im;
+        for (int ks = 0; ks < KS; ++ks) {
+          const cplx<double> x = T[dense_lds_off(brow[ks] | colp)];
+          const double nxi = -x.im;
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          const cplx<double> u = Us[(16u * rt + li) * kUsStride + 4u * ks + lk];
-          yr[rt] = mfma16(u.re, x.re, yr[rt]);
-          yr[rt] = mfma16(u.im, nxi, yr[rt]);
-          yi[rt] = mfma16(u.re, x.im, yi[rt]);
-          yi[rt] = mfma16(u.im, x.re, yi[rt]);
+          for (int rt = 0; rt < RT; ++rt) {
+            const cplx<double> u = Us[(16u * (rt0 + rt) + li) * kUsStride + 4u * ks + lk];
+            yr[rt] = mfma16(u.re, x.re, yr[rt]);
+            yr[rt] = mfma16(u.im, nxi, yr[rt]);
+            yi[rt] = mfma16(u.re, x.im, yi[rt]);
+            yi[rt] = mfma16(u.im, x.re, yi[rt]);
+          }
         }
       }
+      __syncthreads();  // both waves of the pair have read the column block
+      if (active) {
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) T[dense_lds_off(drow[rt][v] | colp)] = cplx<double>{yr[rt][v], yi[rt][v]};
+          for (int v = 0; v < 4; ++v) T[dense_lds_off(drow[rt][v] | colp)] = cplx<double>{yr[rt][v], yi[rt][v]};
+      }
     }
     __syncthreads();
-    dense_store<double, 4>(psi, T, M, base, G.L, hi_tab);
+    dense_store<double, 2, NT>(psi, T, M, base, G.L, hi_tab);
     __syncthreads();
   }
 }
@@ -472,7 +478,7 @@ bool launch_dense(cplx<R>* psi, int n, int k, const int* bits_sorted, const cplx
       allow_dynamic_lds((const void*)dense_kernel_k6_c128, (int)lds6, "dense_k6");
       attr_set = true;
     }
-    QS_LAUNCH("dense_k6", s, dense_kernel_k6_c128, dim3(grid), dim3(kDenseThreads), lds6, s, psi, U_dev, G);
+    QS_LAUNCH("dense_k6", s, dense_kernel_k6_c128, dim3(grid), dim3(kThreads6), lds6, s, psi, U_dev, G);
   }
   return true;
 }
