@@ -231,9 +231,11 @@ __global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per
   // complex64 k = 6 (2^12-amplitude tiles, eight pair accesses per thread):
   // the first kPre accesses of the next tile are issued before this tile's
   // contraction (the register file holds no more at three waves per SIMD),
-  // the rest at the top of the tile's turn
-  constexpr bool kPipe = kSplit;
-  constexpr int kAcc = 8, kPre = 4;
+  // the rest at the top of the tile's turn.  (Measured: prefetching k = 4 and
+  // k = 5 tiles, which are HBM-bound, gains nothing or loses.)
+  constexpr int kAcc = K / 8;
+  constexpr int kPre = kSplit ? 4 : 0;
+  constexpr bool kPipe = kPre > 0;
   const bool pipe = kPipe && M == 2u * kDenseThreads * kAcc;  // full tiles (n - k >= 6)
   auto tile_base = [&](uint32_t t) {
     uint32_t base = 0;
@@ -250,10 +252,14 @@ __global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per
     const uint32_t base = tile_base(t);
     // load: tile bit 0 is state bit 0, so pairs (p, p + 1) are adjacent
     if (kPipe && pipe) {
-      cplx2<R> rest[kAcc - kPre];
-      dense_issue<R, kPre, kAcc>(psi, base, G.L, hi_tab, rest);
-      dense_put<R, 0, kPre>(T, pre);
-      dense_put<R, kPre, kAcc>(T, rest);
+      if constexpr (kPre < kAcc) {
+        cplx2<R> rest[kAcc > kPre ? kAcc - kPre : 1];
+        dense_issue<R, kPre, kAcc>(psi, base, G.L, hi_tab, rest);
+        dense_put<R, 0, kPre>(T, pre);
+        dense_put<R, kPre, kAcc>(T, rest);
+      } else {
+        dense_put<R, 0, kPre>(T, pre);
+      }
     } else if constexpr (sizeof(R) == 8 && K == 16) {
       // complex128, k = 4 (K = 16, memory-bound): one 16-byte amplitude per lane and
       // access (for k = 5 the extra address work costs more than it saves)
