@@ -323,6 +323,28 @@ __global__ void __launch_bounds__(kThreads) gf2_kernel(const cplx<R>* __restrict
 }
 
 // out_i = sum over groups g of (c0_g + sum_k w_k count_k(j)) psi_j, j = i ^ x_g.
+// A thread takes the amplitude pair (i, i ^ 1): for every group both sources
+// j and j ^ 1 are one 16-byte load (swapped when x_g flips bit 0).
+template <class R>
+__device__ __forceinline__ void pauli_coef(cptr<PauliGroup> G, cptr<PauliCount> K, int g, uint32_t j, double& cr,
+                                           double& ci) {
+  cr = G[g].c0re;
+  ci = G[g].c0im;
+  const int k1 = G[g].k0 + G[g].nk;
+  for (int k = G[g].k0; k < k1; ++k) {
+    const int form = K[k].form;
+    const uint32_t m = K[k].mask;
+    int c;
+    if (form == DT_SHIFT_XOR)
+      c = popc((j ^ (j >> K[k].shift)) & m);
+    else if (form == DT_PARITY)
+      c = popc(j & m) & 1;
+    else
+      c = popc(j & m);
+    cr = fma(K[k].wre, (double)c, cr);
+    ci = fma(K[k].wim, (double)c, ci);
+  }
+}
 template <class R>
 __global__ void __launch_bounds__(kThreads) pauli_apply_kernel(const cplx<R>* __restrict__ psi,
                                                                cplx<R>* __restrict__ out, uint64_t N,
@@ -330,31 +352,23 @@ __global__ void __launch_bounds__(kThreads) pauli_apply_kernel(const cplx<R>* __
                                                                const PauliCount* counts) {
   const cptr<PauliGroup> G = to_const(groups);
   const cptr<PauliCount> K = to_const(counts);
-  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < N; t += (uint64_t)gridDim.x * kThreads) {
-    const uint32_t i = (uint32_t)t;
-    double ar = 0.0, ai = 0.0;
+  for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; 2 * t < N; t += (uint64_t)gridDim.x * kThreads) {
+    const uint32_t i = 2u * (uint32_t)t;  // and i + 1
+    double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
     for (int g = 0; g < ng; ++g) {
-      const uint32_t j = i ^ G[g].x;
-      double cr = G[g].c0re, ci = G[g].c0im;
-      const int k1 = G[g].k0 + G[g].nk;
-      for (int k = G[g].k0; k < k1; ++k) {
-        const int form = K[k].form;
-        const uint32_t m = K[k].mask;
-        int c;
-        if (form == DT_SHIFT_XOR)
-          c = popc((j ^ (j >> K[k].shift)) & m);
-        else if (form == DT_PARITY)
-          c = popc(j & m) & 1;
-        else
-          c = popc(j & m);
-        cr = fma(K[k].wre, (double)c, cr);
-        ci = fma(K[k].wim, (double)c, ci);
-      }
-      const cplx<R> v = psi[j];
-      ar = fma(cr, (double)v.re, fma(-ci, (double)v.im, ar));
-      ai = fma(cr, (double)v.im, fma(ci, (double)v.re, ai));
+      const uint32_t x = G[g].x;
+      const uint32_t j0 = i ^ x;  // source of i; i + 1 reads j0 ^ 1
+      const cplx2<R> v = *reinterpret_cast<const cplx2<R>*>(psi + (j0 & ~1u));
+      const cplx<R> s0 = (x & 1u) ? v.b : v.a, s1 = (x & 1u) ? v.a : v.b;
+      double cr, ci;
+      pauli_coef<R>(G, K, g, j0, cr, ci);
+      a0r = fma(cr, (double)s0.re, fma(-ci, (double)s0.im, a0r));
+      a0i = fma(cr, (double)s0.im, fma(ci, (double)s0.re, a0i));
+      pauli_coef<R>(G, K, g, j0 ^ 1u, cr, ci);
+      a1r = fma(cr, (double)s1.re, fma(-ci, (double)s1.im, a1r));
+      a1i = fma(cr, (double)s1.im, fma(ci, (double)s1.re, a1i));
     }
-    out[i] = {(R)ar, (R)ai};
+    *reinterpret_cast<cplx2<R>*>(out + i) = cplx2<R>{{(R)a0r, (R)a0i}, {(R)a1r, (R)a1i}};
   }
 }
 
@@ -364,8 +378,8 @@ template <class R>
 void launch_pauli_apply(const cplx<R>* psi, cplx<R>* out, int n, const PauliGroup* groups, int n_groups,
                         const PauliCount* counts, hipStream_t s) {
   const uint64_t N = 1ull << n;
-  QS_LAUNCH("pauli_apply", s, pauli_apply_kernel<R>, dim3(grid_for(N, kThreads)), dim3(kThreads), 0, s, psi, out, N,
-            groups, n_groups, counts);
+  QS_LAUNCH("pauli_apply", s, pauli_apply_kernel<R>, dim3(grid_for(N / 2, kThreads)), dim3(kThreads), 0, s, psi, out,
+            N, groups, n_groups, counts);
 }
 template void launch_pauli_apply<float>(const cplx<float>*, cplx<float>*, int, const PauliGroup*, int,
                                         const PauliCount*, hipStream_t);
