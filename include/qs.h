@@ -59,7 +59,7 @@ typedef enum {
   QS_EINVAL = -1,       /* invalid argument: wires, sizes, counts, mismatch */
   QS_ENOMEM = -2,       /* capacity exceeded or device allocation failed */
   QS_EDEVICE = -3,      /* HIP runtime / kernel error */
-  QS_EUNSUPPORTED = -4  /* valid request this build does not implement */
+  QS_EUNSUPPORTED = -4  /* valid request the library does not implement */
 } qs_status;
 
 typedef enum { QS_C64 = 0, QS_C128 = 1 } qs_dtype;
